@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the DSBI Poisson-Boltzmann hot path on one MI355X.
+
+One step = one whole solve of the star-shaped synthetic protein surface
+(81,920 triangles, 2,000 interior charges): collocation geometry, source
+terms, restarted GMRES(10) with the refined-FP32 matvec (FP64 outer
+residuals, FP64 Arnoldi), solvation energy.  Inputs are device-resident
+before the timed region starts.  The solve tolerance is the loosest of a
+fixed ladder whose energy is within 1e-6 (relative) of an FP64 solve at
+tol 1e-12; the ladder search runs before timing.
+
+Prints one JSON line.  `value` = matvec pair interactions per second over
+the whole step (all FP32 and FP64 matvecs, N(N-1) pairs each) in G/s;
+`ms_per_step` = time to E_solv at 1e-6 relative error.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR = 58.0          # algorithmic FLOP of one matvec pair (FMA = 2)
+PEAK_FP32_VECTOR = 157.3e12   # MI355X published FP32 vector peak
+PEAK_FP64_VECTOR = 78.6e12
+TOL_LADDER = [1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 1e-8]
+E_TARGET = 1e-6
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, seconds=12.0):
+    """The FP64 oracle's matvec on a bounded sample of target rows of the
+    same workload, on the host's cores."""
+    import numpy as np
+    from oracle import dsbi
+    g = dsbi.geometry(w.verts, w.tris)
+    x = np.random.default_rng(0).normal(size=2 * g.n)
+    rng = np.random.default_rng(1)
+    probe = np.sort(rng.choice(g.n, 256, replace=False))
+    t0 = time.perf_counter()
+    dsbi.matvec(g, w.eps_out / w.eps_in, w.kappa, x, rows=probe)
+    dt = time.perf_counter() - t0
+    rows_n = int(min(g.n, max(256, 256 * seconds / max(dt, 1e-3))))
+    rows = np.sort(rng.choice(g.n, rows_n, replace=False))
+    t0 = time.perf_counter()
+    dsbi.matvec(g, w.eps_out / w.eps_in, w.kappa, x, rows=rows)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": rows_n * (g.n - 1) / dt / 1e9,
+        "unit": "G pair-interactions/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"FP64 oracle matvec, {rows_n} of {g.n} target rows of the same "
+                  f"{g.n}-triangle surface ({rows_n * (g.n - 1):.3g} pairs, {dt:.1f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp32-ir", "fp64"], default="fp32-ir")
+    ap.add_argument("--workload", choices=["star81920", "star327680"], default="star81920")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the solver runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2312_10044_amd import Context, Params, PB_FP64, PB_FP32_IR
+    from paper_2312_10044_amd import pbsolve as pbs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(0)
+    if args.workload == "star81920":
+        w = synth.star_protein()
+    else:
+        w = synth.large_star_protein()
+    N = w.n_tri
+    _log(f"bench: workload {w.name}: {N} triangles, {w.n_charges} charges")
+    tv = torch.from_numpy(w.verts).to(dev)
+    tt = torch.from_numpy(w.tris.astype(np.int32)).to(dev)
+    tp = torch.from_numpy(w.pos).to(dev)
+    tq = torch.from_numpy(w.q).to(dev)
+    phi = torch.empty(N, dtype=torch.float64, device=dev)
+    dphi = torch.empty_like(phi)
+    stream = torch.cuda.current_stream()
+    ctx = Context(0, stream)
+
+    def solve(params):
+        return ctx.pb_solve_dev(tv, tt, tp, tq, params, phi, dphi)
+
+    base = dict(eps_in=w.eps_in, eps_out=w.eps_out, kappa=w.kappa, restart=10, max_iter=2000)
+    ref = solve(Params(tol=1e-12, precision=PB_FP64, **base))
+    e_ref = ref.e_solv
+    _log(f"bench: FP64 reference E={e_ref:.10f} (tol 1e-12, {ref.iters} iterations)")
+
+    def pick(precision):
+        for tol in TOL_LADDER:
+            if precision == PB_FP32_IR:
+                p = Params(tol=tol, precision=PB_FP32_IR, inner_tol=0.3 * tol,
+                           max_refine=20, **base)
+            else:
+                p = Params(tol=tol, precision=PB_FP64, **base)
+            info = solve(p)
+            err = abs(info.e_solv - e_ref) / abs(e_ref)
+            _log(f"bench: precision={precision} tol={tol:g} E err={err:.2e} iters={info.iters} "
+                 f"t={info.seconds:.3f}s")
+            if err <= E_TARGET and info.status == 0:
+                return p, err
+        raise RuntimeError("no tolerance on the ladder reached the energy target")
+
+    prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
+    params, err_pick = pick(prec)
+
+    for _ in range(args.warmup):
+        solve(params)
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        infos.append(solve(params))
+        _log(f"bench: step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile_enable(False)
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    pairs_per_mv = float(N) * float(N - 1)
+    n_mv = sum(i.matvecs_fp32 + i.matvecs_fp64 for i in infos)
+    value = n_mv * pairs_per_mv / elapsed / 1e9
+    errs = [abs(i.e_solv - e_ref) / abs(e_ref) for i in infos]
+
+    dom = pbs.PB_KERNEL_PAIRS_FP32 if prec == PB_FP32_IR else pbs.PB_KERNEL_PAIRS_FP64
+    launches, kms, kpairs = ctx.profile_read(dom)
+    avg_ms = kms / max(launches, 1)
+    achieved = FLOP_PER_PAIR * (kpairs / max(launches, 1)) / (avg_ms * 1e-3)
+    peak = PEAK_FP32_VECTOR if prec == PB_FP32_IR else PEAK_FP64_VECTOR
+    kernel_rows = {}
+    for name, kid in (("pairs_fp32", pbs.PB_KERNEL_PAIRS_FP32), ("pairs_fp64", pbs.PB_KERNEL_PAIRS_FP64),
+                      ("source", pbs.PB_KERNEL_SOURCE), ("charge", pbs.PB_KERNEL_CHARGE)):
+        n_l, ms_l, pr_l = ctx.profile_read(kid)
+        if n_l:
+            kernel_rows[name] = {"launches": n_l, "avg_ms": ms_l / n_l,
+                                 "gpairs_per_s": pr_l / (ms_l * 1e-3) / 1e9}
+
+    fp64_path = None
+    if not args.no_fp64_compare and prec == PB_FP32_IR:
+        p64, err64 = pick(PB_FP64)
+        solve(p64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        i64 = solve(p64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        fp64_path = {"time_to_solution_s": t64, "tol": p64.tol, "e_rel_err": err64,
+                     "iters": i64.iters,
+                     "gpairs_per_s": i64.matvecs_fp64 * pairs_per_mv / t64 / 1e9}
+
+    out = {
+        "metric": "BIE matvec G-pair-interactions/s; time to E_solv at 1e-6 rel. error",
+        "value": value,
+        "unit": "G pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == PB_FP32_IR else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"star-shaped surface {N} triangles, {w.n_charges} charges, "
+                        f"eps 1/80, kappa 0.1257; one full solve to E_solv within 1e-6",
+            "n_tri": N,
+            "n_charges": w.n_charges,
+            "precision": "FP32 matvec + FP64 refinement" if prec == PB_FP32_IR else "FP64",
+            "tol": params.tol,
+            "inner_tol": params.inner_tol if prec == PB_FP32_IR else None,
+            "gmres_restart": 10,
+        },
+        "time_to_solution_s": ms_step / 1e3,
+        "e_solv": infos[-1].e_solv,
+        "e_rel_err": max(errs),
+        "iters": infos[-1].iters,
+        "matvecs_fp32": infos[-1].matvecs_fp32,
+        "matvecs_fp64": infos[-1].matvecs_fp64,
+        "refinements": infos[-1].refinements,
+        "kernels": kernel_rows,
+        "fp64_path": fp64_path,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_pairs<float,false>" if prec == PB_FP32_IR else "k_pairs<double,false>",
+            "achieved": achieved / 1e12,
+            "peak": peak / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "flop_per_pair": FLOP_PER_PAIR,
+            "pairs_per_launch": kpairs / max(launches, 1),
+            "avg_launch_ms": avg_ms,
+            "launches": launches,
+        },
+        "cpu_baseline": None,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        _log("bench: timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * pbsolve.h -- C ABI of the MI355X direct-sum boundary-integral (DSBI)
+ * Poisson-Boltzmann library (libpbdsbi.so, HIP for gfx950).
+ *
+ * The library solves the well-conditioned boundary integral form of the
+ * linearized Poisson-Boltzmann equation (Sec. 2.2.1, eqs. eqbim_3/eqbim_4)
+ * discretized by centroid collocation on flat triangles (Sec. 2.2.2, eqs.
+ * eqbim_5/eqbim_6, the singular j = i term omitted) with restarted GMRES,
+ * and evaluates the electrostatic solvation energy (eq. solvation_energy).
+ *
+ * Conventions shared by every entry point
+ *   - Sizes are int64_t, reals are double, arrays are row-major and
+ *     C-contiguous.  Vectors of unknowns use block layout [phi; dphi]
+ *     (length 2 n_tri): phi = surface potential, dphi = its normal
+ *     derivative from inside.
+ *   - Units: Angstrom, elementary charges, kcal/mol.  phi/dphi are the
+ *     solution of eqs. eqbim_5/eqbim_6, i.e. the physical potential in e_c/A
+ *     divided by 4 pi; multiply by 4 pi * 332.0716 for kcal/mol/e_c.
+ *   - Triangles are listed counter-clockwise seen from the solvent side, so
+ *     (v1-v0)x(v2-v0) is the outward normal.
+ *   - Ownership: the caller owns every buffer it passes; the library never
+ *     frees or keeps caller memory.  Device scratch belongs to the context
+ *     and is reused across calls.
+ *   - Host-pointer entry points copy inputs to the device and results back;
+ *     *_dev entry points take device pointers, enqueue on the context's
+ *     stream and return after that stream has drained.
+ *   - Errors: every entry point returns a status (below); no exception
+ *     crosses the ABI.  On a negative status outputs are unspecified and
+ *     pb_last_error(ctx) describes the failure.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef PBSOLVE_H
+#define PBSOLVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PB_ABI_VERSION 1
+
+/* status codes */
+#define PB_OK 0
+#define PB_NOT_CONVERGED 1      /* outputs hold the last iterate; info->rel_residual set */
+#define PB_ERR_ARG (-1)         /* NULL pointer, n <= 0, eps <= 0, kappa < 0, tol <= 0, restart < 1 ... */
+#define PB_ERR_GEOMETRY (-2)    /* non-finite vertex, index out of range, zero-area triangle,
+                                   non-positive enclosed volume (wrong orientation) */
+#define PB_ERR_CHARGE (-3)      /* a charge outside the surface (discrete solid angle < 2 pi) */
+#define PB_ERR_HIP (-4)         /* HIP runtime error */
+#define PB_ERR_OOM (-5)         /* device allocation failed */
+
+/* precision of the matvec inside GMRES */
+#define PB_FP64 0               /* FP64 everywhere */
+#define PB_FP32_IR 1            /* FP32 matvec in an inner GMRES, FP64 iterative refinement */
+
+typedef struct pb_ctx pb_ctx;
+
+/* Closed triangulated surface. vert: [n_vert][3]; tri: [n_tri][3] indices into vert. */
+typedef struct {
+    int64_t n_vert, n_tri;
+    const double *vert;
+    const int32_t *tri;
+} pb_surface;
+
+/* Point charges strictly inside the surface. pos: [n][3] (A); q: [n] (e_c). */
+typedef struct {
+    int64_t n;
+    const double *pos;
+    const double *q;
+} pb_charges;
+
+typedef struct {
+    double eps_in, eps_out;     /* dielectric constants inside / outside (> 0) */
+    double kappa;               /* inverse Debye length outside, 1/A (>= 0) */
+    double tol;                 /* relative residual |b - A x|_2 / |b|_2 at which to stop */
+    int32_t restart;            /* GMRES restart length m (>= 1; the paper's runs use 10) */
+    int32_t max_iter;           /* cap on Arnoldi steps (FP64) / outer refinements x inner cap (IR) */
+    int32_t precision;          /* PB_FP64 or PB_FP32_IR */
+    int32_t max_refine;         /* IR: cap on refinement steps */
+    double inner_tol;           /* IR: relative tolerance of each inner FP32 GMRES solve */
+} pb_params;
+
+typedef struct {
+    double e_solv;              /* solvation energy, kcal/mol */
+    double rel_residual;        /* final true relative residual (FP64) */
+    double seconds;             /* wall time inside the call */
+    int32_t iters;              /* Arnoldi steps (one matvec each), all precisions */
+    int32_t matvecs_fp64;       /* FP64 matvecs, including residual checks */
+    int32_t matvecs_fp32;       /* FP32 matvecs */
+    int32_t refinements;        /* IR outer steps (0 for PB_FP64) */
+    int32_t status;             /* same as the return value */
+    int32_t reserved;
+} pb_info;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on, or NULL for a stream the context creates (default priority). */
+int pb_create(int device, void *hip_stream, pb_ctx **out);
+void pb_destroy(pb_ctx *ctx);
+/* Message for the last non-zero status returned on ctx (never NULL). */
+const char *pb_last_error(const pb_ctx *ctx);
+int pb_abi_version(void);
+
+/* ---- host-pointer entry points ---------------------------------------- */
+
+/* Step 1, collocation geometry (Sec. 2.2.2): centroid x_i = (v0+v1+v2)/3,
+ * unit normal (v1-v0)x(v2-v0)/|.|, area |(v1-v0)x(v2-v0)|/2.
+ * cen, nrm: [n_tri][3]; area: [n_tri].  Validates the surface (PB_ERR_GEOMETRY). */
+int pb_geometry(pb_ctx *ctx, const pb_surface *s, double *cen, double *nrm, double *area);
+
+/* Step 2, source terms (eq. source_terms): b = [S1; S2] at the centroids,
+ * S1 = (1/eps_in) sum_k q_k G0(x_i, y_k), S2 = (1/eps_in) sum_k q_k dG0/dnu_x.
+ * b: [2 n_tri]. */
+int pb_source(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_params *p,
+              double *b);
+
+/* Step 3 (and its transpose, step 6): y = A x for the system of eqs.
+ * eqbim_5/eqbim_6, or y = A^T x when transpose != 0.  precision: PB_FP64 or
+ * PB_FP32_IR (FP32 pair arithmetic, FP64 result).  x, y: [2 n_tri]. */
+int pb_matvec(pb_ctx *ctx, const pb_surface *s, const pb_params *p, const double *x,
+              double *y, int transpose, int precision);
+
+/* Step 5, solvation energy (eq. solvation_energy) of a given surface
+ * solution: E = (1/2) sum_k q_k phi_reac(y_k), in kcal/mol.
+ * phi, dphi: [n_tri]. */
+int pb_energy(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_params *p,
+              const double *phi, const double *dphi, double *e_solv);
+
+/* Whole path: geometry, sources, restarted GMRES (FP64, or FP32 inner solves
+ * with FP64 iterative refinement), energy.  phi/dphi ([n_tri] each) may be
+ * NULL.  Returns PB_OK, PB_NOT_CONVERGED or a negative error. */
+int pb_solve(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_params *p,
+             double *phi, double *dphi, pb_info *info);
+
+/* ---- device-pointer entry points -------------------------------------- */
+/* Same operations; every array argument is device memory laid out as above.
+ * Validation of the surface runs on the device. */
+
+int pb_matvec_dev(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                  const int32_t *d_tri, const pb_params *p, const double *d_x, double *d_y,
+                  int transpose, int precision);
+
+int pb_solve_dev(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                 const int32_t *d_tri, int64_t n_charges, const double *d_pos,
+                 const double *d_q, const pb_params *p, double *d_phi, double *d_dphi,
+                 pb_info *info);
+
+/* ---- kernel timing hook (benchmarks, profiling) ------------------------ */
+/* When enabled, every launch of the kernels below is bracketed by a pair of
+ * HIP events recorded on the context's stream; elapsed times are collected
+ * when the entry point that launched them returns.  `pairs` accumulates the
+ * algorithmic pair count of the launches: N(N-1) for a matvec sweep over N
+ * collocation points, N*Nc for the source and charge sweeps. */
+#define PB_KERNEL_PAIRS_FP64 0      /* matvec pair sweep, FP64 */
+#define PB_KERNEL_PAIRS_FP32 1      /* matvec pair sweep, FP32 */
+#define PB_KERNEL_PAIRS_FP64_T 2    /* transpose sweep, FP64 */
+#define PB_KERNEL_PAIRS_FP32_T 3    /* transpose sweep, FP32 */
+#define PB_KERNEL_SOURCE 4          /* source terms */
+#define PB_KERNEL_CHARGE 5          /* reaction potential / solid angle at the charges */
+#define PB_KERNEL_COUNT 6
+
+int pb_profile_enable(pb_ctx *ctx, int enable);
+int pb_profile_reset(pb_ctx *ctx);
+/* launches, total_ms, pairs may each be NULL. */
+int pb_profile_read(pb_ctx *ctx, int kernel, int64_t *launches, double *total_ms, double *pairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBSOLVE_H */

@@ -1,0 +1,1005 @@
+// Host driver and C ABI (include/pbsolve.h) of the DSBI Poisson-Boltzmann
+// library.  Everything that scales with N runs on the device; the host only
+// holds the (m+1) x m Hessenberg matrix of GMRES and its Givens rotations,
+// fed by one small device-to-host copy per Arnoldi step.
+#include "../../include/pbsolve.h"
+#include "pb_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace pbk;
+
+namespace {
+
+constexpr double C_UNITS = 332.0716;      // e_c^2/A -> kcal/mol (Sec. 2.1)
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+constexpr int TARGET_WAVES = 8192;        // ~8 waves per SIMD on 256 CUs x 4 SIMDs
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct ErrorState {
+    std::string msg = "no error";
+};
+
+}  // namespace
+
+struct pb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    ErrorState err;
+    // device scratch
+    DevBuf geo, geo_part, src64, src32, part, vec, V, small, dpart, chg_part, chg_per;
+    DevBuf in_vert, in_tri, in_pos, in_q, io_x, io_y;
+    double *hsmall = nullptr;   // pinned host staging, HSMALL doubles
+    // kernel timing (pb_profile_*)
+    struct Mark {
+        hipEvent_t a, b;
+        int kind;
+        double pairs;
+    };
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<Mark> marks;
+    int64_t prof_launches[PB_KERNEL_COUNT] = {};
+    double prof_ms[PB_KERNEL_COUNT] = {};
+    double prof_pairs[PB_KERNEL_COUNT] = {};
+    // current geometry
+    Geo g{};
+    double center[3] = {0.0, 0.0, 0.0};
+    double volume = 0.0, area_sum = 0.0;
+};
+
+namespace {
+
+constexpr int HSMALL = 4 * (MAX_RESTART + 2) + 64;
+
+int fail(pb_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err.msg = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(c, e_ == hipErrorOutOfMemory ? PB_ERR_OOM : PB_ERR_HIP,           \
+                        "%s failed: %s", #expr, hipGetErrorString(e_));                   \
+    } while (0)
+
+#define LAUNCHCHK()                                                                       \
+    do {                                                                                  \
+        hipError_t e_ = hipGetLastError();                                                \
+        if (e_ != hipSuccess)                                                             \
+            return fail(c, PB_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+#define TRY(expr)              \
+    do {                       \
+        int rc_ = (expr);      \
+        if (rc_ < 0)           \
+            return rc_;        \
+    } while (0)
+
+int ensure(pb_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (bytes <= b.cap)
+        return PB_OK;
+    if (b.p) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipFree(b.p));
+    }
+    b.p = nullptr;
+    b.cap = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, PB_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    b.cap = bytes;
+    return PB_OK;
+}
+
+template <typename T>
+T *as(DevBuf &b) { return static_cast<T *>(b.p); }
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+hipEvent_t pool_event(pb_ctx *c, size_t idx)
+{
+    while (c->ev_pool.size() <= idx) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[idx];
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+    pb_ctx *c;
+    int kind;
+    double pairs;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(pb_ctx *c_, int kind_, double pairs_) : c(c_), kind(kind_), pairs(pairs_)
+    {
+        if (!c->prof_on)
+            return;
+        const size_t k = 2 * c->marks.size();
+        a = pool_event(c, k);
+        b = pool_event(c, k + 1);
+        if (a && b)
+            (void)hipEventRecord(a, c->stream);
+    }
+    ~ProfScope()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, c->stream);
+            c->marks.push_back({a, b, kind, pairs});
+        }
+    }
+};
+
+// Collect elapsed times of recorded launches (the stream must have drained).
+void prof_collect(pb_ctx *c)
+{
+    for (const auto &m : c->marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+            c->prof_ms[m.kind] += ms;
+            c->prof_launches[m.kind] += 1;
+            c->prof_pairs[m.kind] += m.pairs;
+        }
+    }
+    c->marks.clear();
+}
+
+int check_params(pb_ctx *c, const pb_params *p, bool solving)
+{
+    if (!p)
+        return fail(c, PB_ERR_ARG, "params is NULL");
+    if (!(p->eps_in > 0.0) || !(p->eps_out > 0.0) || !std::isfinite(p->eps_in) ||
+        !std::isfinite(p->eps_out))
+        return fail(c, PB_ERR_ARG, "eps_in and eps_out must be finite and > 0");
+    if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa))
+        return fail(c, PB_ERR_ARG, "kappa must be finite and >= 0");
+    if (solving) {
+        if (!(p->tol > 0.0))
+            return fail(c, PB_ERR_ARG, "tol must be > 0");
+        if (p->restart < 1 || p->restart > MAX_RESTART)
+            return fail(c, PB_ERR_ARG, "restart must be in [1, %d]", MAX_RESTART);
+        if (p->max_iter < 1)
+            return fail(c, PB_ERR_ARG, "max_iter must be >= 1");
+        if (p->precision != PB_FP64 && p->precision != PB_FP32_IR)
+            return fail(c, PB_ERR_ARG, "precision must be PB_FP64 or PB_FP32_IR");
+        if (p->precision == PB_FP32_IR) {
+            if (p->max_refine < 1)
+                return fail(c, PB_ERR_ARG, "max_refine must be >= 1");
+            if (!(p->inner_tol > 0.0) || !(p->inner_tol < 1.0))
+                return fail(c, PB_ERR_ARG, "inner_tol must be in (0, 1)");
+        }
+    }
+    return PB_OK;
+}
+
+// ---- geometry (step 1) with validation --------------------------------------
+
+int setup_geometry(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                   const int32_t *d_tri)
+{
+    if (n_tri <= 0 || n_vert < 3)
+        return fail(c, PB_ERR_ARG, "need n_tri > 0 and n_vert >= 3");
+    if (n_tri > (int64_t)1 << 30)
+        return fail(c, PB_ERR_ARG, "n_tri too large");
+    if (!d_vert || !d_tri)
+        return fail(c, PB_ERR_ARG, "vertex or triangle array is NULL");
+    const int64_t npad = round_up(n_tri, TILE);
+    TRY(ensure(c, c->geo, sizeof(double) * NGEO * npad));
+    const int nblk = geometry_blocks(npad);
+    TRY(ensure(c, c->geo_part, sizeof(double) * GEO_RED * nblk));
+    TRY(ensure(c, c->small, sizeof(double) * HSMALL));
+    launch_geometry(c->stream, n_vert, n_tri, d_vert, d_tri, as<double>(c->geo), npad,
+                    as<double>(c->geo_part), nblk);
+    LAUNCHCHK();
+    launch_reduce_cols(c->stream, as<double>(c->geo_part), nblk, GEO_RED, as<double>(c->small));
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(c->hsmall, c->small.p, sizeof(double) * GEO_RED, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const double *r = c->hsmall;
+    c->g.g = as<double>(c->geo);
+    c->g.n = n_tri;
+    c->g.npad = npad;
+    if (r[0] != 0.0)
+        return fail(c, PB_ERR_GEOMETRY,
+                    "%.0f triangle(s) with an out-of-range index, a non-finite vertex or zero area",
+                    r[0]);
+    c->volume = r[1] / 6.0;
+    c->area_sum = r[5];
+    if (!(c->volume > 0.0))
+        return fail(c, PB_ERR_GEOMETRY,
+                    "enclosed volume %.6g <= 0: triangles must be counter-clockwise seen from "
+                    "outside",
+                    c->volume);
+    c->center[0] = r[2] / (double)n_tri;
+    c->center[1] = r[3] / (double)n_tri;
+    c->center[2] = r[4] / (double)n_tri;
+    return PB_OK;
+}
+
+PairParams pair_params(pb_ctx *c, const pb_params *p)
+{
+    PairParams pp;
+    pp.eps = p->eps_out / p->eps_in;
+    pp.kappa = p->kappa;
+    pp.cx = c->center[0];
+    pp.cy = c->center[1];
+    pp.cz = c->center[2];
+    return pp;
+}
+
+// ---- matvec (steps 3 and 6) -----------------------------------------------------
+
+int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const double *x, double *y)
+{
+    const Geo &g = c->g;
+    const Sweep sw = plan_sweep(g.npad, g.npad, TARGET_WAVES);
+    TRY(ensure(c, c->part, sizeof(double) * 2 * sw.n_chunks * g.npad));
+    const PairParams pp = pair_params(c, p);
+    const double eps = pp.eps;
+    const double npairs = (double)g.n * (double)(g.n - 1);
+    if (precision == PB_FP32_IR) {
+        TRY(ensure(c, c->src32, sizeof(float) * 8 * g.npad));
+        launch_pack_f32(c->stream, g, x, as<float>(c->src32), transpose ? 1 : 0, pp.cx, pp.cy,
+                        pp.cz);
+        LAUNCHCHK();
+        ProfScope ps(c, transpose ? PB_KERNEL_PAIRS_FP32_T : PB_KERNEL_PAIRS_FP32, npairs);
+        launch_pairs_f32(c->stream, g, as<float>(c->src32), sw, pp, transpose,
+                         as<double>(c->part));
+    } else {
+        TRY(ensure(c, c->src64, sizeof(double) * 8 * g.npad));
+        launch_pack_f64(c->stream, g, x, as<double>(c->src64), transpose ? 1 : 0);
+        LAUNCHCHK();
+        ProfScope ps(c, transpose ? PB_KERNEL_PAIRS_FP64_T : PB_KERNEL_PAIRS_FP64, npairs);
+        launch_pairs_f64(c->stream, g, as<double>(c->src64), sw, pp, transpose,
+                         as<double>(c->part));
+    }
+    LAUNCHCHK();
+    launch_matvec_finish(c->stream, g, as<double>(c->part), sw.n_chunks, x, 0.5 * (1.0 + eps),
+                         0.5 * (1.0 + 1.0 / eps), transpose, y);
+    LAUNCHCHK();
+    return PB_OK;
+}
+
+// ---- vectors -------------------------------------------------------------------
+
+struct Vecs {
+    int64_t n2 = 0, ld = 0;
+    double *x = nullptr, *b = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
+    double *V = nullptr;
+};
+
+int setup_vectors(pb_ctx *c, int m, Vecs &v)
+{
+    v.n2 = 2 * c->g.n;
+    v.ld = round_up(v.n2, 64);
+    TRY(ensure(c, c->vec, sizeof(double) * 6 * v.ld));
+    TRY(ensure(c, c->V, sizeof(double) * (m + 1) * v.ld));
+    double *base = as<double>(c->vec);
+    v.x = base;
+    v.b = base + v.ld;
+    v.w = base + 2 * v.ld;
+    v.r = base + 3 * v.ld;
+    v.d = base + 4 * v.ld;
+    v.t = base + 5 * v.ld;
+    v.V = as<double>(c->V);
+    const int nblk = dot_blocks(v.n2);
+    TRY(ensure(c, c->dpart, sizeof(double) * (MAX_RESTART + 2) * nblk));
+    TRY(ensure(c, c->small, sizeof(double) * HSMALL));
+    return PB_OK;
+}
+
+// |v|^2 reduced on the device into small[slot]
+int norm2_dev(pb_ctx *c, const double *v, int64_t n, int slot)
+{
+    const int nblk = dot_blocks(n);
+    launch_dots(c->stream, nullptr, 0, 0, v, n, as<double>(c->dpart), nblk);
+    LAUNCHCHK();
+    launch_reduce_cols(c->stream, as<double>(c->dpart), nblk, 1, as<double>(c->small) + slot);
+    LAUNCHCHK();
+    return PB_OK;
+}
+
+int fetch_small(pb_ctx *c, int first, int count)
+{
+    HIPCHK(hipMemcpyAsync(c->hsmall + first, as<double>(c->small) + first, sizeof(double) * count,
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PB_OK;
+}
+
+int norm_host(pb_ctx *c, const double *v, int64_t n, double *out)
+{
+    const int slot = HSMALL - 1;
+    TRY(norm2_dev(c, v, n, slot));
+    TRY(fetch_small(c, slot, 1));
+    *out = std::sqrt(c->hsmall[slot]);
+    return PB_OK;
+}
+
+struct GmresStats {
+    int iters = 0, mv64 = 0, mv32 = 0;
+    double rel = 0.0;
+    bool converged = false;
+};
+
+// Restarted GMRES(m) (Saad & Schultz) on A x = rhs, A applied in `precision`.
+// Arnoldi uses classical Gram-Schmidt with one reorthogonalisation pass
+// (CGS2) in FP64 on the device; the Hessenberg least-squares problem is
+// solved on the host with Givens rotations.  x holds the start vector unless
+// x_zero.  Stops when the true residual |rhs - A x| / |rhs| <= tol.
+int gmres(pb_ctx *c, const pb_params *p, int precision, int transpose, const double *rhs,
+          double *x, bool x_zero, double tol, int max_iter, Vecs &v, GmresStats &st)
+{
+    const int m = p->restart;
+    const int64_t n2 = v.n2;
+    const int nblk = dot_blocks(n2);
+    double *small = as<double>(c->small);
+    double *h1 = small, *h2 = small + (m + 1), *nb2 = small + 2 * (m + 1);
+    double *yv = small + 2 * (m + 1) + 1;
+    double bnorm;
+    TRY(norm_host(c, rhs, n2, &bnorm));
+    st = GmresStats();
+    if (!std::isfinite(bnorm))
+        return fail(c, PB_ERR_GEOMETRY, "non-finite right-hand side");
+    if (bnorm == 0.0) {
+        launch_fill(c->stream, x, 0.0, n2);
+        LAUNCHCHK();
+        st.converged = true;
+        return PB_OK;
+    }
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), yh(m);
+    bool zero_start = x_zero;
+    if (x_zero) {
+        launch_fill(c->stream, x, 0.0, n2);
+        LAUNCHCHK();
+    }
+    for (;;) {
+        // r0 = rhs - A x  (r0 = rhs when starting from zero)
+        double beta;
+        if (zero_start) {
+            HIPCHK(hipMemcpyAsync(v.r, rhs, sizeof(double) * n2, hipMemcpyDeviceToDevice,
+                                  c->stream));
+            beta = bnorm;
+        } else {
+            TRY(apply(c, p, precision, transpose, x, v.w));
+            if (precision == PB_FP64) st.mv64++; else st.mv32++;
+            launch_sub(c->stream, rhs, v.w, v.r, n2);
+            LAUNCHCHK();
+            TRY(norm_host(c, v.r, n2, &beta));
+        }
+        zero_start = false;
+        if (!std::isfinite(beta))
+            return fail(c, PB_ERR_GEOMETRY,
+                        "non-finite residual (coincident collocation points or a charge on "
+                        "the surface?)");
+        st.rel = beta / bnorm;
+        if (st.rel <= tol) {
+            st.converged = true;
+            return PB_OK;
+        }
+        if (st.iters >= max_iter)
+            return PB_OK;
+        // V_0 = r0 / beta
+        TRY(norm2_dev(c, v.r, n2, 2 * (m + 1)));
+        launch_scale_inv_sqrt(c->stream, v.r, nb2, v.V, n2);
+        LAUNCHCHK();
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double *vj = v.V + (int64_t)j * v.ld;
+            TRY(apply(c, p, precision, transpose, vj, v.w));
+            st.iters++;
+            if (precision == PB_FP64) st.mv64++; else st.mv32++;
+            // CGS pass 1 and 2
+            launch_dots(c->stream, v.V, v.ld, j + 1, v.w, n2, as<double>(c->dpart), nblk);
+            LAUNCHCHK();
+            launch_reduce_cols(c->stream, as<double>(c->dpart), nblk, j + 1, h1);
+            LAUNCHCHK();
+            launch_sub_basis(c->stream, v.V, v.ld, j + 1, h1, v.w, n2);
+            LAUNCHCHK();
+            launch_dots(c->stream, v.V, v.ld, j + 1, v.w, n2, as<double>(c->dpart), nblk);
+            LAUNCHCHK();
+            launch_reduce_cols(c->stream, as<double>(c->dpart), nblk, j + 1, h2);
+            LAUNCHCHK();
+            launch_sub_basis(c->stream, v.V, v.ld, j + 1, h2, v.w, n2);
+            LAUNCHCHK();
+            TRY(norm2_dev(c, v.w, n2, 2 * (m + 1)));
+            launch_scale_inv_sqrt(c->stream, v.w, nb2, v.V + (int64_t)(j + 1) * v.ld, n2);
+            LAUNCHCHK();
+            TRY(fetch_small(c, 0, 2 * (m + 1) + 1));
+            const double *hh = c->hsmall;
+            for (int i = 0; i <= j; ++i)
+                H[i * m + j] = hh[i] + hh[(m + 1) + i];
+            const double hn = std::sqrt(hh[2 * (m + 1)]);
+            if (!std::isfinite(hn))
+                return fail(c, PB_ERR_GEOMETRY,
+                            "non-finite Arnoldi vector (coincident collocation points?)");
+            H[(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+            cs[j] = H[j * m + j] / den;
+            sn[j] = H[(j + 1) * m + j] / den;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            k = j + 1;
+            if (std::fabs(gv[j + 1]) / bnorm <= tol || st.iters >= max_iter || hn == 0.0)
+                break;
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double s = gv[i];
+            for (int l = i + 1; l < k; ++l)
+                s -= H[i * m + l] * yh[l];
+            yh[i] = s / H[i * m + i];
+        }
+        std::memcpy(c->hsmall + (yv - small), yh.data(), sizeof(double) * k);
+        HIPCHK(hipMemcpyAsync(yv, c->hsmall + (yv - small), sizeof(double) * k,
+                              hipMemcpyHostToDevice, c->stream));
+        launch_add_basis(c->stream, v.V, v.ld, k, yv, x, n2);
+        LAUNCHCHK();
+        // the host staging row is reused by the next fetch: drain first
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+}
+
+// ---- charges: inside check, sources (step 2), energy (step 5) -----------------
+
+int check_charges_inside(pb_ctx *c, const pb_params *p, int64_t nc, const double *d_pos,
+                         Vecs &v)
+{
+    const Geo &g = c->g;
+    const Sweep sw = plan_sweep(nc, g.npad, TARGET_WAVES);
+    const int64_t ncpad = (int64_t)sw.n_tblocks * TPB;
+    TRY(ensure(c, c->chg_part, sizeof(double) * sw.n_chunks * ncpad));
+    TRY(ensure(c, c->chg_per, sizeof(double) * ncpad));
+    TRY(ensure(c, c->src64, sizeof(double) * 8 * g.npad));
+    // unit potential, zero flux: the stream carries m_j = a_j n_j
+    launch_fill(c->stream, v.t, 1.0, g.n);
+    LAUNCHCHK();
+    launch_fill(c->stream, v.t + g.n, 0.0, g.n);
+    LAUNCHCHK();
+    launch_pack_f64(c->stream, g, v.t, as<double>(c->src64), 0);
+    LAUNCHCHK();
+    {
+        ProfScope ps(c, PB_KERNEL_CHARGE, (double)g.n * (double)nc);
+        launch_charge_pairs(c->stream, g, as<double>(c->src64), nc, d_pos, sw, pair_params(c, p),
+                            1, as<double>(c->chg_part), ncpad);
+    }
+    LAUNCHCHK();
+    launch_charge_finish(c->stream, as<double>(c->chg_part), sw.n_chunks, nc, ncpad, nullptr,
+                         as<double>(c->chg_per), nullptr);
+    LAUNCHCHK();
+    std::vector<double> omega(nc);
+    HIPCHK(hipMemcpyAsync(omega.data(), c->chg_per.p, sizeof(double) * nc, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int64_t k = 0; k < nc; ++k) {
+        // discrete solid angle: ~4 pi inside, ~0 outside
+        if (!(omega[k] >= TWO_PI))
+            return fail(c, PB_ERR_CHARGE,
+                        "charge %lld is not inside the surface (solid angle %.4g, need >= 2 pi)",
+                        (long long)k, omega[k]);
+    }
+    return PB_OK;
+}
+
+int energy_dev(pb_ctx *c, const pb_params *p, int64_t nc, const double *d_pos, const double *d_q,
+               const double *x, double *e_out)
+{
+    const Geo &g = c->g;
+    const Sweep sw = plan_sweep(nc, g.npad, TARGET_WAVES);
+    const int64_t ncpad = (int64_t)sw.n_tblocks * TPB;
+    TRY(ensure(c, c->chg_part, sizeof(double) * sw.n_chunks * ncpad));
+    TRY(ensure(c, c->src64, sizeof(double) * 8 * g.npad));
+    TRY(ensure(c, c->small, sizeof(double) * HSMALL));
+    launch_pack_f64(c->stream, g, x, as<double>(c->src64), 0);
+    LAUNCHCHK();
+    {
+        ProfScope ps(c, PB_KERNEL_CHARGE, (double)g.n * (double)nc);
+        launch_charge_pairs(c->stream, g, as<double>(c->src64), nc, d_pos, sw, pair_params(c, p),
+                            0, as<double>(c->chg_part), ncpad);
+    }
+    LAUNCHCHK();
+    const int slot = HSMALL - 2;
+    launch_charge_finish(c->stream, as<double>(c->chg_part), sw.n_chunks, nc, ncpad, d_q, nullptr,
+                         as<double>(c->small) + slot);
+    LAUNCHCHK();
+    TRY(fetch_small(c, slot, 1));
+    // E = (1/2) sum_k q_k phi_reac(y_k) in kcal/mol; the pair sums carry 4 pi K
+    *e_out = 0.5 * C_UNITS * c->hsmall[slot];
+    return PB_OK;
+}
+
+int check_charges_args(pb_ctx *c, int64_t nc, const void *pos, const void *q)
+{
+    if (nc <= 0)
+        return fail(c, PB_ERR_ARG, "need at least one charge");
+    if (!pos || !q)
+        return fail(c, PB_ERR_ARG, "charge position or value array is NULL");
+    return PB_OK;
+}
+
+// Whole path on device-resident inputs.
+int solve_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+              const int32_t *d_tri, int64_t nc, const double *d_pos, const double *d_q,
+              const pb_params *p, double *d_phi, double *d_dphi, pb_info *info)
+{
+    TRY(check_params(c, p, true));
+    TRY(check_charges_args(c, nc, d_pos, d_q));
+    TRY(setup_geometry(c, n_vert, n_tri, d_vert, d_tri));
+    Vecs v;
+    TRY(setup_vectors(c, p->restart, v));
+    TRY(check_charges_inside(c, p, nc, d_pos, v));
+    {
+        ProfScope ps(c, PB_KERNEL_SOURCE, (double)c->g.n * (double)nc);
+        launch_source(c->stream, c->g, nc, d_pos, d_q, p->eps_in, v.b);
+    }
+    LAUNCHCHK();
+    GmresStats st;
+    int status = PB_OK;
+    int refinements = 0;
+    int iters = 0, mv64 = 0, mv32 = 0;
+    double rel = 0.0;
+    if (p->precision == PB_FP64) {
+        TRY(gmres(c, p, PB_FP64, 0, v.b, v.x, true, p->tol, p->max_iter, v, st));
+        iters = st.iters;
+        mv64 = st.mv64;
+        rel = st.rel;
+        status = st.converged ? PB_OK : PB_NOT_CONVERGED;
+    } else {
+        // FP64 iterative refinement around FP32 inner GMRES solves.
+        double bnorm;
+        TRY(norm_host(c, v.b, v.n2, &bnorm));
+        launch_fill(c->stream, v.x, 0.0, v.n2);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(v.r, v.b, sizeof(double) * v.n2, hipMemcpyDeviceToDevice,
+                              c->stream));
+        double rnorm = bnorm;
+        status = PB_NOT_CONVERGED;
+        for (;;) {
+            rel = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+            if (rel <= p->tol) {
+                status = PB_OK;
+                break;
+            }
+            if (refinements >= p->max_refine || iters >= p->max_iter)
+                break;
+            // inner solve A d = r in FP32 arithmetic; copy r aside (gmres uses v.r)
+            HIPCHK(hipMemcpyAsync(v.t, v.r, sizeof(double) * v.n2, hipMemcpyDeviceToDevice,
+                                  c->stream));
+            TRY(gmres(c, p, PB_FP32_IR, 0, v.t, v.d, true, p->inner_tol, p->max_iter - iters, v,
+                      st));
+            iters += st.iters;
+            mv32 += st.mv32;
+            launch_add(c->stream, v.x, v.d, v.n2);
+            LAUNCHCHK();
+            refinements++;
+            // outer residual in FP64
+            TRY(apply(c, p, PB_FP64, 0, v.x, v.w));
+            mv64++;
+            launch_sub(c->stream, v.b, v.w, v.r, v.n2);
+            LAUNCHCHK();
+            TRY(norm_host(c, v.r, v.n2, &rnorm));
+            if (!std::isfinite(rnorm))
+                return fail(c, PB_ERR_GEOMETRY, "non-finite residual in refinement");
+        }
+    }
+    double e = 0.0;
+    TRY(energy_dev(c, p, nc, d_pos, d_q, v.x, &e));
+    if (d_phi)
+        HIPCHK(hipMemcpyAsync(d_phi, v.x, sizeof(double) * n_tri, hipMemcpyDeviceToDevice,
+                              c->stream));
+    if (d_dphi)
+        HIPCHK(hipMemcpyAsync(d_dphi, v.x + n_tri, sizeof(double) * n_tri,
+                              hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (info) {
+        info->e_solv = e;
+        info->rel_residual = rel;
+        info->iters = iters;
+        info->matvecs_fp64 = mv64;
+        info->matvecs_fp32 = mv32;
+        info->refinements = refinements;
+        info->status = status;
+    }
+    if (status == PB_NOT_CONVERGED)
+        fail(c, PB_NOT_CONVERGED, "GMRES stopped at relative residual %.3e > tol %.3e", rel,
+             p->tol);
+    return status;
+}
+
+// Host inputs -> context buffers.
+int upload_surface(pb_ctx *c, const pb_surface *s, const double **dv, const int32_t **dt)
+{
+    if (!s || !s->vert || !s->tri)
+        return fail(c, PB_ERR_ARG, "surface or its arrays are NULL");
+    if (s->n_tri <= 0 || s->n_vert < 3)
+        return fail(c, PB_ERR_ARG, "need n_tri > 0 and n_vert >= 3");
+    TRY(ensure(c, c->in_vert, sizeof(double) * 3 * s->n_vert));
+    TRY(ensure(c, c->in_tri, sizeof(int32_t) * 3 * s->n_tri));
+    HIPCHK(hipMemcpyAsync(c->in_vert.p, s->vert, sizeof(double) * 3 * s->n_vert,
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->in_tri.p, s->tri, sizeof(int32_t) * 3 * s->n_tri,
+                          hipMemcpyHostToDevice, c->stream));
+    *dv = as<double>(c->in_vert);
+    *dt = as<int32_t>(c->in_tri);
+    return PB_OK;
+}
+
+int upload_charges(pb_ctx *c, const pb_charges *q, const double **dp, const double **dq)
+{
+    if (!q)
+        return fail(c, PB_ERR_ARG, "charges is NULL");
+    TRY(check_charges_args(c, q->n, q->pos, q->q));
+    TRY(ensure(c, c->in_pos, sizeof(double) * 3 * q->n));
+    TRY(ensure(c, c->in_q, sizeof(double) * q->n));
+    HIPCHK(hipMemcpyAsync(c->in_pos.p, q->pos, sizeof(double) * 3 * q->n, hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(c->in_q.p, q->q, sizeof(double) * q->n, hipMemcpyHostToDevice,
+                          c->stream));
+    *dp = as<double>(c->in_pos);
+    *dq = as<double>(c->in_q);
+    return PB_OK;
+}
+
+int enter(pb_ctx *c)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    HIPCHK(hipSetDevice(c->device));
+    return PB_OK;
+}
+
+// Every entry point returns through here: drain the stream and fold the
+// recorded kernel timings in, whatever the status.
+int leave(pb_ctx *c, int st)
+{
+    if (c && !c->marks.empty()) {
+        if (hipStreamSynchronize(c->stream) == hipSuccess)
+            prof_collect(c);
+        else
+            c->marks.clear();
+    }
+    return st;
+}
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ======================= C ABI ===================================================
+
+extern "C" {
+
+int pb_abi_version(void) { return PB_ABI_VERSION; }
+
+int pb_create(int device, void *hip_stream, pb_ctx **out)
+{
+    if (!out)
+        return PB_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return PB_ERR_HIP;
+    if (hipSetDevice(device) != hipSuccess)
+        return PB_ERR_HIP;
+    pb_ctx *c = new (std::nothrow) pb_ctx();
+    if (!c)
+        return PB_ERR_OOM;
+    c->device = device;
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) {
+            delete c;
+            return PB_ERR_HIP;
+        }
+        c->own_stream = true;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->hsmall), sizeof(double) * HSMALL,
+                      hipHostMallocDefault) != hipSuccess) {
+        if (c->own_stream)
+            (void)hipStreamDestroy(c->stream);
+        delete c;
+        return PB_ERR_OOM;
+    }
+    *out = c;
+    return PB_OK;
+}
+
+void pb_destroy(pb_ctx *c)
+{
+    if (!c)
+        return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    DevBuf *bufs[] = {&c->geo, &c->geo_part, &c->src64, &c->src32, &c->part, &c->vec,
+                      &c->V, &c->small, &c->dpart, &c->chg_part, &c->chg_per, &c->in_vert,
+                      &c->in_tri, &c->in_pos, &c->in_q, &c->io_x, &c->io_y};
+    for (DevBuf *b : bufs)
+        if (b->p)
+            (void)hipFree(b->p);
+    if (c->hsmall)
+        (void)hipHostFree(c->hsmall);
+    for (hipEvent_t e : c->ev_pool)
+        (void)hipEventDestroy(e);
+    if (c->own_stream)
+        (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *pb_last_error(const pb_ctx *c)
+{
+    if (!c)
+        return "NULL context";
+    return c->err.msg.c_str();
+}
+
+static int pb_geometry_impl(pb_ctx *c, const pb_surface *s, double *cen, double *nrm, double *area)
+{
+    TRY(enter(c));
+    if (!cen || !nrm || !area)
+        return fail(c, PB_ERR_ARG, "output arrays are NULL");
+    const double *dv;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(setup_geometry(c, s->n_vert, s->n_tri, dv, dt));
+    const int64_t n = c->g.n, np = c->g.npad;
+    std::vector<double> h(NGEO * np);
+    HIPCHK(hipMemcpyAsync(h.data(), c->g.g, sizeof(double) * NGEO * np, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < 3; ++k) {
+            cen[3 * i + k] = h[k * np + i];
+            nrm[3 * i + k] = h[(3 + k) * np + i];
+        }
+        area[i] = h[6 * np + i];
+    }
+    return PB_OK;
+}
+
+static int pb_source_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p, double *b)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    if (!b)
+        return fail(c, PB_ERR_ARG, "output b is NULL");
+    const double *dv, *dp, *dq;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(upload_charges(c, q, &dp, &dq));
+    TRY(setup_geometry(c, s->n_vert, s->n_tri, dv, dt));
+    TRY(ensure(c, c->io_y, sizeof(double) * 2 * s->n_tri));
+    launch_source(c->stream, c->g, q->n, dp, dq, p->eps_in, as<double>(c->io_y));
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(b, c->io_y.p, sizeof(double) * 2 * s->n_tri, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PB_OK;
+}
+
+static int pb_matvec_impl(pb_ctx *c, const pb_surface *s, const pb_params *p, const double *x, double *y,
+              int transpose, int precision)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    if (!x || !y)
+        return fail(c, PB_ERR_ARG, "x or y is NULL");
+    if (precision != PB_FP64 && precision != PB_FP32_IR)
+        return fail(c, PB_ERR_ARG, "precision must be PB_FP64 or PB_FP32_IR");
+    const double *dv;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(setup_geometry(c, s->n_vert, s->n_tri, dv, dt));
+    const int64_t n2 = 2 * s->n_tri;
+    TRY(ensure(c, c->io_x, sizeof(double) * n2));
+    TRY(ensure(c, c->io_y, sizeof(double) * n2));
+    HIPCHK(hipMemcpyAsync(c->io_x.p, x, sizeof(double) * n2, hipMemcpyHostToDevice, c->stream));
+    TRY(apply(c, p, precision, transpose ? 1 : 0, as<double>(c->io_x), as<double>(c->io_y)));
+    HIPCHK(hipMemcpyAsync(y, c->io_y.p, sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PB_OK;
+}
+
+static int pb_matvec_dev_impl(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                  const int32_t *d_tri, const pb_params *p, const double *d_x, double *d_y,
+                  int transpose, int precision)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    if (!d_x || !d_y)
+        return fail(c, PB_ERR_ARG, "x or y is NULL");
+    if (precision != PB_FP64 && precision != PB_FP32_IR)
+        return fail(c, PB_ERR_ARG, "precision must be PB_FP64 or PB_FP32_IR");
+    TRY(setup_geometry(c, n_vert, n_tri, d_vert, d_tri));
+    TRY(apply(c, p, precision, transpose ? 1 : 0, d_x, d_y));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PB_OK;
+}
+
+static int pb_energy_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
+              const double *phi, const double *dphi, double *e_solv)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    if (!phi || !dphi || !e_solv)
+        return fail(c, PB_ERR_ARG, "phi, dphi or e_solv is NULL");
+    const double *dv, *dp, *dq;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(upload_charges(c, q, &dp, &dq));
+    TRY(setup_geometry(c, s->n_vert, s->n_tri, dv, dt));
+    const int64_t n = s->n_tri;
+    TRY(ensure(c, c->io_x, sizeof(double) * 2 * n));
+    HIPCHK(hipMemcpyAsync(c->io_x.p, phi, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(as<double>(c->io_x) + n, dphi, sizeof(double) * n,
+                          hipMemcpyHostToDevice, c->stream));
+    return energy_dev(c, p, q->n, dp, dq, as<double>(c->io_x), e_solv);
+}
+
+static int pb_solve_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
+             double *phi, double *dphi, pb_info *info)
+{
+    const double t0 = now_s();
+    TRY(enter(c));
+    const double *dv, *dp, *dq;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(upload_charges(c, q, &dp, &dq));
+    const int64_t n = s->n_tri;
+    double *dphi_d = nullptr;
+    if (phi || dphi) {
+        TRY(ensure(c, c->io_y, sizeof(double) * 2 * n));
+        dphi_d = as<double>(c->io_y);
+    }
+    const int st = solve_dev(c, s->n_vert, s->n_tri, dv, dt, q->n, dp, dq, p, dphi_d,
+                             dphi_d ? dphi_d + n : nullptr, info);
+    if (st < 0)
+        return st;
+    if (phi)
+        HIPCHK(hipMemcpyAsync(phi, dphi_d, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    if (dphi)
+        HIPCHK(hipMemcpyAsync(dphi, dphi_d + n, sizeof(double) * n, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (info)
+        info->seconds = now_s() - t0;
+    return st;
+}
+
+static int pb_solve_dev_impl(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                 const int32_t *d_tri, int64_t n_charges, const double *d_pos, const double *d_q,
+                 const pb_params *p, double *d_phi, double *d_dphi, pb_info *info)
+{
+    const double t0 = now_s();
+    TRY(enter(c));
+    const int st = solve_dev(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p, d_phi,
+                             d_dphi, info);
+    if (info && st >= 0)
+        info->seconds = now_s() - t0;
+    return st;
+}
+
+
+int pb_geometry(pb_ctx *c, const pb_surface *s, double *cen, double *nrm, double *area)
+{
+    return leave(c, pb_geometry_impl(c, s, cen, nrm, area));
+}
+
+int pb_source(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p, double *b)
+{
+    return leave(c, pb_source_impl(c, s, q, p, b));
+}
+
+int pb_matvec(pb_ctx *c, const pb_surface *s, const pb_params *p, const double *x, double *y,
+              int transpose, int precision)
+{
+    return leave(c, pb_matvec_impl(c, s, p, x, y, transpose, precision));
+}
+
+int pb_matvec_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                  const int32_t *d_tri, const pb_params *p, const double *d_x, double *d_y,
+                  int transpose, int precision)
+{
+    return leave(c, pb_matvec_dev_impl(c, n_vert, n_tri, d_vert, d_tri, p, d_x, d_y, transpose, precision));
+}
+
+int pb_energy(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
+              const double *phi, const double *dphi, double *e_solv)
+{
+    return leave(c, pb_energy_impl(c, s, q, p, phi, dphi, e_solv));
+}
+
+int pb_solve(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
+             double *phi, double *dphi, pb_info *info)
+{
+    return leave(c, pb_solve_impl(c, s, q, p, phi, dphi, info));
+}
+
+int pb_solve_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                 const int32_t *d_tri, int64_t n_charges, const double *d_pos, const double *d_q,
+                 const pb_params *p, double *d_phi, double *d_dphi, pb_info *info)
+{
+    return leave(c, pb_solve_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p, d_phi, d_dphi, info));
+}
+
+int pb_profile_enable(pb_ctx *c, int enable)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    c->prof_on = enable != 0;
+    return PB_OK;
+}
+
+int pb_profile_reset(pb_ctx *c)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    for (int k = 0; k < PB_KERNEL_COUNT; ++k) {
+        c->prof_launches[k] = 0;
+        c->prof_ms[k] = 0.0;
+        c->prof_pairs[k] = 0.0;
+    }
+    c->marks.clear();
+    return PB_OK;
+}
+
+int pb_profile_read(pb_ctx *c, int kernel, int64_t *launches, double *total_ms, double *pairs)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    if (kernel < 0 || kernel >= PB_KERNEL_COUNT)
+        return fail(c, PB_ERR_ARG, "kernel id %d out of range", kernel);
+    if (launches)
+        *launches = c->prof_launches[kernel];
+    if (total_ms)
+        *total_ms = c->prof_ms[kernel];
+    if (pairs)
+        *pairs = c->prof_pairs[kernel];
+    return PB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal interface between the HIP kernels (pb_kernels.hip) and the host
+// driver (pb_capi.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pbk {
+
+constexpr int TPB = 256;        // threads per block of every pair kernel
+constexpr int TILE = 256;       // sources staged in LDS per step (== TPB)
+constexpr int NGEO = 7;         // cx, cy, cz, nx, ny, nz, area
+constexpr int GEO_RED = 6;      // bad, 6*volume, sum cx, sum cy, sum cz, sum area
+constexpr int MAX_RESTART = 64;
+
+// Device-side collocation geometry, SoA: array k at g + k * npad.
+struct Geo {
+    const double *g;
+    int64_t n;      // triangles
+    int64_t npad;   // n rounded up to a multiple of TILE
+};
+
+struct PairParams {
+    double eps;         // eps_out / eps_in
+    double kappa;
+    double cx, cy, cz;  // origin subtracted from positions before FP32 arithmetic
+};
+
+// Launch shape of one pair sweep: targets in blocks of TPB, sources split
+// into n_chunks contiguous ranges of tiles_per_chunk tiles.
+struct Sweep {
+    int n_tblocks;
+    int n_tiles;
+    int n_chunks;
+    int tiles_per_chunk;
+};
+
+Sweep plan_sweep(int64_t n_targets, int64_t n_sources, int target_waves);
+
+// geometry + per-block partial reductions (GEO_RED columns x nblk)
+int geometry_blocks(int64_t n_tri);
+void launch_geometry(hipStream_t s, int64_t n_vert, int64_t n_tri, const double *vert,
+                     const int32_t *tri, double *g, int64_t npad, double *part, int nblk);
+
+// Packed source stream: 8 values per source (x, y, z, w, mx, my, mz, 0).
+// mode 0 (forward): w = a_j psi_j, m = a_j phi_j n_j.
+// mode 1 (transpose): w = l1_j, m = l2_j n_j.
+void launch_pack_f64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode);
+void launch_pack_f32(hipStream_t s, const Geo &geo, const double *x, float *src, int mode,
+                     double cx, double cy, double cz);
+
+// Pair sweep of the matvec: part[(o * n_chunks + c) * npad + i], o in {0,1}.
+void launch_pairs_f64(hipStream_t s, const Geo &geo, const double *src, const Sweep &sw,
+                      const PairParams &pp, int transpose, double *part);
+void launch_pairs_f32(hipStream_t s, const Geo &geo, const float *src, const Sweep &sw,
+                      const PairParams &pp, int transpose, double *part);
+// y = diag * x - (1/4pi) sum_c part  (times a_i when transposed)
+void launch_matvec_finish(hipStream_t s, const Geo &geo, const double *part, int n_chunks,
+                          const double *x, double alpha, double beta, int transpose, double *y);
+
+// Source terms b = [S1; S2].
+void launch_source(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,
+                   const double *q, double eps_in, double *b);
+
+// Per-charge reaction potential partials (mode 0) or solid angle (mode 1).
+// part[c * ncpad + k]; src is a forward-packed FP64 stream (mode 0).
+void launch_charge_pairs(hipStream_t s, const Geo &geo, const double *src, int64_t nc,
+                         const double *pos, const Sweep &sw, const PairParams &pp, int mode,
+                         double *part, int64_t ncpad);
+// out[0] = sum_k q_k sum_c part[c][k] (q may be NULL: then sum over k of the
+// per-charge values is not formed and per[k] receives sum_c part[c][k]).
+void launch_charge_finish(hipStream_t s, const double *part, int n_chunks, int64_t nc,
+                          int64_t ncpad, const double *q, double *per, double *out);
+
+// ---- deterministic BLAS-1 on device vectors of length n ----------------
+int dot_blocks(int64_t n);
+// part[j * nblk + b] = block b's share of <V_j, w> for j < k, and of <w, w> at j = k.
+void launch_dots(hipStream_t s, const double *V, int64_t ld, int k, const double *w, int64_t n,
+                 double *part, int nblk);
+// out[j] = sum_b part[j * nblk + b] in a fixed order, j < ncol.
+void launch_reduce_cols(hipStream_t s, const double *part, int nblk, int ncol, double *out);
+// w -= sum_{j<k} h[j] V_j
+void launch_sub_basis(hipStream_t s, const double *V, int64_t ld, int k, const double *h,
+                      double *w, int64_t n);
+// v = w / sqrt(*nrm2)   (v = 0 when *nrm2 == 0)
+void launch_scale_inv_sqrt(hipStream_t s, const double *w, const double *nrm2, double *v,
+                           int64_t n);
+// x += sum_{j<k} y[j] V_j
+void launch_add_basis(hipStream_t s, const double *V, int64_t ld, int k, const double *y,
+                      double *x, int64_t n);
+// r = b - ax
+void launch_sub(hipStream_t s, const double *b, const double *ax, double *r, int64_t n);
+// x += d
+void launch_add(hipStream_t s, double *x, const double *d, int64_t n);
+void launch_fill(hipStream_t s, double *x, double v, int64_t n);
+
+}  // namespace pbk

@@ -1,0 +1,681 @@
+// HIP kernels (gfx950) of the DSBI Poisson-Boltzmann path.
+//
+// Pair sweeps (matvec, its transpose, sources, reaction potential) are
+// O(N^2) / O(N Nc) n-body sums: each thread keeps one target in registers,
+// the block stages a tile of TILE packed sources in LDS with coalesced
+// loads, and every lane reads the same LDS entry (broadcast, conflict free)
+// while walking the tile.  The source range is split into chunks so that a
+// launch holds ~10 waves per SIMD; chunk = blockIdx % n_chunks keeps each
+// XCD's blocks on the same sources (blocks are dealt to the 8 XCDs round
+// robin), so each XCD's L2 holds only its own share of the stream.  Chunk
+// partials are summed in a fixed order by a second kernel: results are
+// bitwise reproducible.  No atomics anywhere.
+//
+// Kernel algebra (collocation pair i <- j, d = x_i - x_j, r = |d|,
+// e = exp(-kappa r), tm1 = (1 + kappa r) e - 1, eps = eps_out/eps_in,
+// c_x = n_i.d, u = 1/r^3; the 1/(4 pi) is applied once per row):
+//   4pi K1 = (1 - e)/r
+//   4pi K2 = (eps (1 + kappa r) e - 1) (n_j.d) u
+//   4pi K3 = ((1 + kappa r) e / eps - 1) c_x u
+//   4pi K4 = u [tm1 (n_i.n_j) - c_x (n_j.d) (3 tm1 / r^2 + kappa^2 e)]
+// These are the kernels of eqs. Eq_K1/Eq_K2 with d/dnu_x = +nu_x.grad_x
+// (Sec. 2.2.1).  The source stream carries w_j = a_j psi_j and
+// m_j = a_j phi_j n_j, so the per-pair work needs no separate phi_j, n_j:
+//   row 1: sum_j [-(e-1)/r w_j + g2 (m_j.d) u]          g2 = eps tm1 + eps - 1
+//   row 2: sum_j u [tm1 (n_i.m_j) - c_x ((m_j.d) h - g3 w_j)]
+//          h = 3 tm1/r^2 + kappa^2 e,  g3 = tm1/eps + 1/eps - 1
+// The transpose swaps the roles: w_j = l1_j, m_j = l2_j n_j and
+//   row 1: sum_j u [tm1 (n_i.m_j) - c_x ((m_j.d) h + g2 w_j)]
+//   row 2: sum_j [-(e-1)/r w_j - g3 (m_j.d) u]
+// with the target area a_i applied once per row.
+#include "pb_kernels.h"
+
+#include <cmath>
+
+namespace pbk {
+
+namespace {
+
+constexpr double INV_4PI = 0.079577471545947667884441881686257181;
+constexpr double FAR_SRC = 2.0e6;   // padded sources, weight 0
+constexpr double FAR_TGT = -2.0e6;  // padded targets, never written back
+
+template <typename T>
+struct alignas(8 * sizeof(T)) Src8 {
+    T x, y, z, w, mx, my, mz, pad;
+};
+
+// ---- precision-specific primitives ---------------------------------------
+
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
+
+// exp(-t) for t >= 0
+__device__ __forceinline__ float exp_neg(float t)
+{
+    return __builtin_amdgcn_exp2f(t * -1.44269504088896340736f);
+}
+__device__ __forceinline__ double exp_neg(double t) { return exp(-t); }
+
+template <typename T>
+struct Coef {
+    T eps, epsm1, ieps, iepsm1, kappa, k2;
+    __device__ explicit Coef(const PairParams &p)
+        : eps(T(p.eps)), epsm1(T(p.eps - 1.0)), ieps(T(1.0 / p.eps)),
+          iepsm1(T(1.0 / p.eps - 1.0)), kappa(T(p.kappa)), k2(T(p.kappa * p.kappa)) {}
+};
+
+// Sum of per-tile partials.  FP64: plain.  FP32: compensated (Knuth's
+// TwoSum), so the error of the long sum stays at the size of one tile.
+template <typename T>
+struct Acc;
+template <>
+struct Acc<double> {
+    double s = 0.0;
+    __device__ void add(double v) { s += v; }
+    __device__ double value() const { return s; }
+};
+template <>
+struct Acc<float> {
+    float hi = 0.f, lo = 0.f;
+    __device__ void add(float v)
+    {
+        float s = hi + v;
+        float bb = s - hi;
+        float err = (hi - (s - bb)) + (v - bb);
+        hi = s;
+        lo += err;
+    }
+    __device__ double value() const { return double(hi) + double(lo); }
+};
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over the block; valid in thread 0.  sh holds blockDim.x/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k)
+            r += sh[k];
+    }
+    return r;
+}
+
+// ---- geometry -------------------------------------------------------------
+
+__global__ __launch_bounds__(TPB) void k_geometry(int64_t n_vert, int64_t n_tri,
+                                                  const double *__restrict__ vert,
+                                                  const int32_t *__restrict__ tri,
+                                                  double *__restrict__ g, int64_t npad,
+                                                  double *__restrict__ part, int nblk)
+{
+#pragma clang fp contract(off)
+    __shared__ double sh[TPB / 64];
+    double acc[GEO_RED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < npad;
+         i += (int64_t)gridDim.x * TPB) {
+        double c[3] = {FAR_TGT, 0.0, 0.0}, nn[3] = {0.0, 0.0, 1.0}, a = 0.0;
+        if (i < n_tri) {
+            const int32_t ia = tri[3 * i], ib = tri[3 * i + 1], ic = tri[3 * i + 2];
+            bool bad = ia < 0 || ib < 0 || ic < 0 || ia >= n_vert || ib >= n_vert || ic >= n_vert;
+            if (!bad) {
+                const double *v0 = vert + 3 * (int64_t)ia;
+                const double *v1 = vert + 3 * (int64_t)ib;
+                const double *v2 = vert + 3 * (int64_t)ic;
+                double e1[3], e2[3], m[3];
+                for (int k = 0; k < 3; ++k) {
+                    c[k] = (v0[k] + v1[k] + v2[k]) / 3.0;
+                    e1[k] = v1[k] - v0[k];
+                    e2[k] = v2[k] - v0[k];
+                }
+                m[0] = e1[1] * e2[2] - e1[2] * e2[1];
+                m[1] = e1[2] * e2[0] - e1[0] * e2[2];
+                m[2] = e1[0] * e2[1] - e1[1] * e2[0];
+                const double mn = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+                a = 0.5 * mn;
+                for (int k = 0; k < 3; ++k)
+                    nn[k] = m[k] / mn;
+                const double chk = c[0] + c[1] + c[2] + nn[0] + nn[1] + nn[2] + a;
+                bad = !(mn > 0.0) || !isfinite(chk);
+                if (!bad) {
+                    acc[1] += m[0] * c[0] + m[1] * c[1] + m[2] * c[2];
+                    acc[2] += c[0];
+                    acc[3] += c[1];
+                    acc[4] += c[2];
+                    acc[5] += a;
+                }
+            }
+            if (bad) {
+                acc[0] += 1.0;
+                c[0] = FAR_TGT; c[1] = 0.0; c[2] = 0.0;
+                nn[0] = 0.0; nn[1] = 0.0; nn[2] = 1.0;
+                a = 0.0;
+            }
+        }
+        g[i] = c[0];
+        g[npad + i] = c[1];
+        g[2 * npad + i] = c[2];
+        g[3 * npad + i] = nn[0];
+        g[4 * npad + i] = nn[1];
+        g[5 * npad + i] = nn[2];
+        g[6 * npad + i] = a;
+    }
+    for (int k = 0; k < GEO_RED; ++k) {
+        const double s = block_sum(acc[k], sh);
+        if (threadIdx.x == 0)
+            part[(int64_t)k * nblk + blockIdx.x] = s;
+    }
+}
+
+// ---- packing of the source stream ---------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_pack(const double *__restrict__ g, int64_t n,
+                                              int64_t npad, const double *__restrict__ x,
+                                              Src8<T> *__restrict__ src, int mode, double cx,
+                                              double cy, double cz)
+{
+    const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (j >= npad)
+        return;
+    Src8<T> s;
+    if (j < n) {
+        const double a = g[6 * npad + j];
+        double w, f;
+        if (mode == 0) {
+            w = a * x[n + j];   // a_j psi_j
+            f = a * x[j];       // a_j phi_j
+        } else {
+            w = x[j];           // l1_j
+            f = x[n + j];       // l2_j
+        }
+        s.x = T(g[j] - cx);
+        s.y = T(g[npad + j] - cy);
+        s.z = T(g[2 * npad + j] - cz);
+        s.w = T(w);
+        s.mx = T(f * g[3 * npad + j]);
+        s.my = T(f * g[4 * npad + j]);
+        s.mz = T(f * g[5 * npad + j]);
+    } else {
+        s.x = T(FAR_SRC - cx);
+        s.y = T(0.0);
+        s.z = T(0.0);
+        s.w = s.mx = s.my = s.mz = T(0.0);
+    }
+    s.pad = T(0.0);
+    src[j] = s;
+}
+
+// ---- matvec pair sweep ----------------------------------------------------
+
+template <typename T, bool TRANS, bool DIAG>
+__device__ __forceinline__ void sweep_tile(const Src8<T> *sh, int self, T xi, T yi, T zi,
+                                           T nxi, T nyi, T nzi, const Coef<T> &cf, T &accP,
+                                           T &accQ)
+{
+#pragma unroll 2
+    for (int jj = 0; jj < TILE; ++jj) {
+        const Src8<T> s = sh[jj];
+        const T dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        T ir = rsqrt_t(r2);
+        if (DIAG)
+            ir = (jj == self) ? T(0) : ir;   // j = i omitted (eqs. eqbim_5/6)
+        const T ir2 = ir * ir;
+        const T u = ir2 * ir;
+        const T kr = cf.kappa * (r2 * ir);
+        const T e = exp_neg(kr);
+        const T em1 = e - T(1);
+        const T tm1 = fma(kr, e, em1);
+        const T cxd = nxi * dx + nyi * dy + nzi * dz;
+        const T md = s.mx * dx + s.my * dy + s.mz * dz;
+        const T nm = nxi * s.mx + nyi * s.my + nzi * s.mz;
+        const T g2 = fma(cf.eps, tm1, cf.epsm1);
+        const T g3 = fma(cf.ieps, tm1, cf.iepsm1);
+        const T h = fma(tm1, T(3) * ir2, cf.k2 * e);
+        const T cP = TRANS ? -g3 : g2;
+        const T cQ = TRANS ? g2 : -g3;
+        accP = fma(-em1, ir * s.w, accP);
+        accP = fma(cP * md, u, accP);
+        const T inner = fma(md, h, cQ * s.w);
+        accQ = fma(u, fma(-cxd, inner, tm1 * nm), accQ);
+    }
+}
+
+template <typename T, bool TRANS>
+__global__ __launch_bounds__(TPB) void k_pairs(const Src8<T> *__restrict__ src,
+                                               const double *__restrict__ g, int64_t npad,
+                                               Sweep sw, PairParams pp,
+                                               double *__restrict__ part)
+{
+    __shared__ Src8<T> sh[TILE];
+    const int b = blockIdx.x;
+    const int chunk = b % sw.n_chunks;
+    const int tb = b / sw.n_chunks;
+    const int64_t i = (int64_t)tb * TPB + threadIdx.x;
+    const T xi = T(g[i] - pp.cx), yi = T(g[npad + i] - pp.cy), zi = T(g[2 * npad + i] - pp.cz);
+    const T nxi = T(g[3 * npad + i]), nyi = T(g[4 * npad + i]), nzi = T(g[5 * npad + i]);
+    const Coef<T> cf(pp);
+    Acc<T> aP, aQ;
+    const int t0 = chunk * sw.tiles_per_chunk;
+    const int t1 = min(sw.n_tiles, t0 + sw.tiles_per_chunk);
+    for (int t = t0; t < t1; ++t) {
+        __syncthreads();
+        sh[threadIdx.x] = src[(int64_t)t * TILE + threadIdx.x];
+        __syncthreads();
+        T p = T(0), q = T(0);
+        if (t == tb)
+            sweep_tile<T, TRANS, true>(sh, threadIdx.x, xi, yi, zi, nxi, nyi, nzi, cf, p, q);
+        else
+            sweep_tile<T, TRANS, false>(sh, -1, xi, yi, zi, nxi, nyi, nzi, cf, p, q);
+        aP.add(p);
+        aQ.add(q);
+    }
+    const double P = aP.value(), Q = aQ.value();
+    part[(int64_t)chunk * npad + i] = TRANS ? Q : P;
+    part[(int64_t)(sw.n_chunks + chunk) * npad + i] = TRANS ? P : Q;
+}
+
+__global__ __launch_bounds__(TPB) void k_matvec_finish(const double *__restrict__ part,
+                                                       int n_chunks, int64_t npad, int64_t n,
+                                                       const double *__restrict__ area,
+                                                       const double *__restrict__ x,
+                                                       double alpha, double beta, int trans,
+                                                       double *__restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n)
+        return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int c = 0; c < n_chunks; ++c) {
+        s1 += part[(int64_t)c * npad + i];
+        s2 += part[(int64_t)(n_chunks + c) * npad + i];
+    }
+    const double sc = trans ? area[i] * INV_4PI : INV_4PI;
+    y[i] = alpha * x[i] - sc * s1;
+    y[n + i] = beta * x[n + i] - sc * s2;
+}
+
+// ---- source terms ----------------------------------------------------------
+
+__global__ __launch_bounds__(TPB) void k_source(const double *__restrict__ g, int64_t n,
+                                                int64_t npad, int64_t nc,
+                                                const double *__restrict__ pos,
+                                                const double *__restrict__ q, double scale,
+                                                double *__restrict__ b)
+{
+    __shared__ double4 sh[TILE];
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const double xi = g[i], yi = g[npad + i], zi = g[2 * npad + i];
+    const double nxi = g[3 * npad + i], nyi = g[4 * npad + i], nzi = g[5 * npad + i];
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t t0 = 0; t0 < nc; t0 += TILE) {
+        __syncthreads();
+        const int64_t k = t0 + threadIdx.x;
+        sh[threadIdx.x] = (k < nc) ? make_double4(pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], q[k])
+                                   : make_double4(FAR_SRC, 0.0, 0.0, 0.0);
+        __syncthreads();
+        const int cnt = (int)min((int64_t)TILE, nc - t0);
+        for (int kk = 0; kk < cnt; ++kk) {
+            const double4 c = sh[kk];
+            const double dx = xi - c.x, dy = yi - c.y, dz = zi - c.z;
+            const double ir = rsqrt(dx * dx + dy * dy + dz * dz);
+            s1 += c.w * ir;
+            s2 += c.w * (nxi * dx + nyi * dy + nzi * dz) * (ir * ir * ir);
+        }
+    }
+    if (i < n) {
+        b[i] = s1 * scale;      // S1 = (1/eps_in) sum q G0
+        b[n + i] = -s2 * scale; // S2 = (1/eps_in) sum q nu_x.grad_x G0
+    }
+}
+
+// ---- charge-target sweeps: reaction potential / solid angle -----------------
+
+template <int MODE>
+__global__ __launch_bounds__(TPB) void k_charge_pairs(const Src8<double> *__restrict__ src,
+                                                      int64_t nc, const double *__restrict__ pos,
+                                                      Sweep sw, PairParams pp,
+                                                      double *__restrict__ part, int64_t ncpad)
+{
+    __shared__ Src8<double> sh[TILE];
+    const int b = blockIdx.x;
+    const int chunk = b % sw.n_chunks;
+    const int tb = b / sw.n_chunks;
+    const int64_t k = (int64_t)tb * TPB + threadIdx.x;
+    const int64_t kk = k < nc ? k : nc - 1;
+    const double yx = pos[3 * kk], yy = pos[3 * kk + 1], yz = pos[3 * kk + 2];
+    const double eps = pp.eps, epsm1 = pp.eps - 1.0, kap = pp.kappa;
+    Acc<double> acc;
+    const int t0 = chunk * sw.tiles_per_chunk;
+    const int t1 = min(sw.n_tiles, t0 + sw.tiles_per_chunk);
+    for (int t = t0; t < t1; ++t) {
+        __syncthreads();
+        sh[threadIdx.x] = src[(int64_t)t * TILE + threadIdx.x];
+        __syncthreads();
+        double p = 0.0;
+        for (int jj = 0; jj < TILE; ++jj) {
+            const Src8<double> s = sh[jj];
+            const double dx = yx - s.x, dy = yy - s.y, dz = yz - s.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double ir = rsqrt(r2);
+            const double u = ir * ir * ir;
+            const double md = s.mx * dx + s.my * dy + s.mz * dz;
+            if (MODE == 0) {
+                const double kr = kap * (r2 * ir);
+                const double e = exp(-kr);
+                const double em1 = e - 1.0;
+                const double tm1 = fma(kr, e, em1);
+                const double g2 = fma(eps, tm1, epsm1);
+                p = fma(-em1, ir * s.w, p);
+                p = fma(g2 * md, u, p);
+            } else {
+                p = fma(-md, u, p);   // sum_j a_j n_j.(x_j - y) / r^3
+            }
+        }
+        acc.add(p);
+    }
+    part[(int64_t)chunk * ncpad + k] = acc.value();
+}
+
+__global__ __launch_bounds__(TPB) void k_charge_finish(const double *__restrict__ part,
+                                                       int n_chunks, int64_t nc, int64_t ncpad,
+                                                       const double *__restrict__ q,
+                                                       double *__restrict__ per,
+                                                       double *__restrict__ out)
+{
+    __shared__ double sh[TPB / 64];
+    double tot = 0.0;
+    for (int64_t k = threadIdx.x; k < nc; k += TPB) {
+        double s = 0.0;
+        for (int c = 0; c < n_chunks; ++c)
+            s += part[(int64_t)c * ncpad + k];
+        if (per)
+            per[k] = s;
+        if (q)
+            tot += q[k] * s;
+    }
+    const double r = block_sum(tot, sh);
+    if (threadIdx.x == 0 && out)
+        out[0] = r;
+}
+
+// ---- BLAS-1 ----------------------------------------------------------------
+
+__global__ __launch_bounds__(TPB) void k_dots(const double *__restrict__ V, int64_t ld, int k,
+                                              const double *__restrict__ w, int64_t n,
+                                              double *__restrict__ part, int nblk)
+{
+    __shared__ double sh[TPB / 64];
+    const int j = blockIdx.y;
+    const double *a = (j < k) ? V + (int64_t)j * ld : w;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)nblk * TPB)
+        s = fma(a[i], w[i], s);
+    const double r = block_sum(s, sh);
+    if (threadIdx.x == 0)
+        part[(int64_t)j * nblk + blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(TPB) void k_reduce_cols(const double *__restrict__ part, int nblk,
+                                                     double *__restrict__ out)
+{
+    __shared__ double sh[TPB / 64];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += TPB)
+        s += part[(int64_t)j * nblk + b];
+    const double r = block_sum(s, sh);
+    if (threadIdx.x == 0)
+        out[j] = r;
+}
+
+__global__ __launch_bounds__(TPB) void k_sub_basis(const double *__restrict__ V, int64_t ld,
+                                                   int k, const double *__restrict__ h,
+                                                   double *__restrict__ w, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n)
+        return;
+    double s = w[i];
+    for (int j = 0; j < k; ++j)
+        s -= h[j] * V[(int64_t)j * ld + i];
+    w[i] = s;
+}
+
+__global__ __launch_bounds__(TPB) void k_scale_inv_sqrt(const double *__restrict__ w,
+                                                        const double *__restrict__ nrm2,
+                                                        double *__restrict__ v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n)
+        return;
+    const double s2 = nrm2[0];
+    v[i] = (s2 > 0.0) ? w[i] / sqrt(s2) : 0.0;
+}
+
+__global__ __launch_bounds__(TPB) void k_add_basis(const double *__restrict__ V, int64_t ld,
+                                                   int k, const double *__restrict__ y,
+                                                   double *__restrict__ x, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n)
+        return;
+    double s = 0.0;
+    for (int j = 0; j < k; ++j)
+        s += y[j] * V[(int64_t)j * ld + i];
+    x[i] += s;
+}
+
+__global__ __launch_bounds__(TPB) void k_sub(const double *__restrict__ b,
+                                             const double *__restrict__ ax,
+                                             double *__restrict__ r, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i < n)
+        r[i] = b[i] - ax[i];
+}
+
+__global__ __launch_bounds__(TPB) void k_add(double *__restrict__ x, const double *__restrict__ d,
+                                             int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i < n)
+        x[i] += d[i];
+}
+
+__global__ __launch_bounds__(TPB) void k_fill(double *__restrict__ x, double v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i < n)
+        x[i] = v;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
+
+}  // namespace
+
+// ---- host-side launchers ------------------------------------------------------
+
+Sweep plan_sweep(int64_t n_targets, int64_t n_sources, int target_waves)
+{
+    Sweep s;
+    s.n_tblocks = (int)((n_targets + TPB - 1) / TPB);
+    s.n_tiles = (int)((n_sources + TILE - 1) / TILE);
+    if (s.n_tiles < 1)
+        s.n_tiles = 1;
+    const int waves_per_chunk = s.n_tblocks * (TPB / 64);
+    int want = (target_waves + waves_per_chunk - 1) / waves_per_chunk;
+    if (want >= 8)
+        want = (want + 7) / 8 * 8;   // whole XCD rounds
+    if (want > s.n_tiles)
+        want = s.n_tiles;
+    if (want < 1)
+        want = 1;
+    s.tiles_per_chunk = (s.n_tiles + want - 1) / want;
+    s.n_chunks = (s.n_tiles + s.tiles_per_chunk - 1) / s.tiles_per_chunk;
+    return s;
+}
+
+int geometry_blocks(int64_t n_tri)
+{
+    int64_t b = (n_tri + TPB - 1) / TPB;
+    if (b > 1024)
+        b = 1024;
+    if (b < 1)
+        b = 1;
+    return (int)b;
+}
+
+void launch_geometry(hipStream_t s, int64_t n_vert, int64_t n_tri, const double *vert,
+                     const int32_t *tri, double *g, int64_t npad, double *part, int nblk)
+{
+    hipLaunchKernelGGL(k_geometry, dim3(nblk), dim3(TPB), 0, s, n_vert, n_tri, vert, tri, g, npad,
+                       part, nblk);
+}
+
+void launch_pack_f64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode)
+{
+    hipLaunchKernelGGL(k_pack<double>, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
+                       geo.npad, x, reinterpret_cast<Src8<double> *>(src), mode, 0.0, 0.0, 0.0);
+}
+
+void launch_pack_f32(hipStream_t s, const Geo &geo, const double *x, float *src, int mode,
+                     double cx, double cy, double cz)
+{
+    hipLaunchKernelGGL(k_pack<float>, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
+                       geo.npad, x, reinterpret_cast<Src8<float> *>(src), mode, cx, cy, cz);
+}
+
+void launch_pairs_f64(hipStream_t s, const Geo &geo, const double *src, const Sweep &sw,
+                      const PairParams &pp, int transpose, double *part)
+{
+    const dim3 grid(sw.n_tblocks * sw.n_chunks);
+    const auto *p = reinterpret_cast<const Src8<double> *>(src);
+    PairParams q = pp;
+    q.cx = q.cy = q.cz = 0.0;   // FP64 works in the caller's frame
+    if (transpose)
+        hipLaunchKernelGGL((k_pairs<double, true>), grid, dim3(TPB), 0, s, p, geo.g, geo.npad, sw,
+                           q, part);
+    else
+        hipLaunchKernelGGL((k_pairs<double, false>), grid, dim3(TPB), 0, s, p, geo.g, geo.npad, sw,
+                           q, part);
+}
+
+void launch_pairs_f32(hipStream_t s, const Geo &geo, const float *src, const Sweep &sw,
+                      const PairParams &pp, int transpose, double *part)
+{
+    const dim3 grid(sw.n_tblocks * sw.n_chunks);
+    const auto *p = reinterpret_cast<const Src8<float> *>(src);
+    if (transpose)
+        hipLaunchKernelGGL((k_pairs<float, true>), grid, dim3(TPB), 0, s, p, geo.g, geo.npad, sw,
+                           pp, part);
+    else
+        hipLaunchKernelGGL((k_pairs<float, false>), grid, dim3(TPB), 0, s, p, geo.g, geo.npad, sw,
+                           pp, part);
+}
+
+void launch_matvec_finish(hipStream_t s, const Geo &geo, const double *part, int n_chunks,
+                          const double *x, double alpha, double beta, int transpose, double *y)
+{
+    hipLaunchKernelGGL(k_matvec_finish, dim3(blocks_for(geo.n)), dim3(TPB), 0, s, part, n_chunks,
+                       geo.npad, geo.n, geo.g + 6 * geo.npad, x, alpha, beta, transpose, y);
+}
+
+void launch_source(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,
+                   const double *q, double eps_in, double *b)
+{
+    hipLaunchKernelGGL(k_source, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
+                       geo.npad, nc, pos, q, INV_4PI / eps_in, b);
+}
+
+void launch_charge_pairs(hipStream_t s, const Geo &geo, const double *src, int64_t nc,
+                         const double *pos, const Sweep &sw, const PairParams &pp, int mode,
+                         double *part, int64_t ncpad)
+{
+    (void)geo;
+    const dim3 grid(sw.n_tblocks * sw.n_chunks);
+    const auto *p = reinterpret_cast<const Src8<double> *>(src);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_charge_pairs<0>, grid, dim3(TPB), 0, s, p, nc, pos, sw, pp, part,
+                           ncpad);
+    else
+        hipLaunchKernelGGL(k_charge_pairs<1>, grid, dim3(TPB), 0, s, p, nc, pos, sw, pp, part,
+                           ncpad);
+}
+
+void launch_charge_finish(hipStream_t s, const double *part, int n_chunks, int64_t nc,
+                          int64_t ncpad, const double *q, double *per, double *out)
+{
+    hipLaunchKernelGGL(k_charge_finish, dim3(1), dim3(TPB), 0, s, part, n_chunks, nc, ncpad, q,
+                       per, out);
+}
+
+int dot_blocks(int64_t n)
+{
+    int64_t b = (n + TPB - 1) / TPB;
+    if (b > 512)
+        b = 512;
+    if (b < 1)
+        b = 1;
+    return (int)b;
+}
+
+void launch_dots(hipStream_t s, const double *V, int64_t ld, int k, const double *w, int64_t n,
+                 double *part, int nblk)
+{
+    hipLaunchKernelGGL(k_dots, dim3(nblk, k + 1), dim3(TPB), 0, s, V, ld, k, w, n, part, nblk);
+}
+
+void launch_reduce_cols(hipStream_t s, const double *part, int nblk, int ncol, double *out)
+{
+    hipLaunchKernelGGL(k_reduce_cols, dim3(ncol), dim3(TPB), 0, s, part, nblk, out);
+}
+
+void launch_sub_basis(hipStream_t s, const double *V, int64_t ld, int k, const double *h,
+                      double *w, int64_t n)
+{
+    hipLaunchKernelGGL(k_sub_basis, dim3(blocks_for(n)), dim3(TPB), 0, s, V, ld, k, h, w, n);
+}
+
+void launch_scale_inv_sqrt(hipStream_t s, const double *w, const double *nrm2, double *v,
+                           int64_t n)
+{
+    hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(blocks_for(n)), dim3(TPB), 0, s, w, nrm2, v, n);
+}
+
+void launch_add_basis(hipStream_t s, const double *V, int64_t ld, int k, const double *y,
+                      double *x, int64_t n)
+{
+    hipLaunchKernelGGL(k_add_basis, dim3(blocks_for(n)), dim3(TPB), 0, s, V, ld, k, y, x, n);
+}
+
+void launch_sub(hipStream_t s, const double *b, const double *ax, double *r, int64_t n)
+{
+    hipLaunchKernelGGL(k_sub, dim3(blocks_for(n)), dim3(TPB), 0, s, b, ax, r, n);
+}
+
+void launch_add(hipStream_t s, double *x, const double *d, int64_t n)
+{
+    hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(TPB), 0, s, x, d, n);
+}
+
+void launch_fill(hipStream_t s, double *x, double v, int64_t n)
+{
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(TPB), 0, s, x, v, n);
+}
+
+}  // namespace pbk

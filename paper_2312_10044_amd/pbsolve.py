@@ -1,0 +1,302 @@
+"""ctypes binding of libpbdsbi.so (include/pbsolve.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; this module converts numpy
+arrays / torch device tensors to the C structs and pointers of the ABI and
+turns negative status codes into :class:`PbError`.  There is no fallback:
+when the library is not built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpbdsbi.so")
+
+PB_OK = 0
+PB_NOT_CONVERGED = 1
+PB_ERR_ARG = -1
+PB_ERR_GEOMETRY = -2
+PB_ERR_CHARGE = -3
+PB_ERR_HIP = -4
+PB_ERR_OOM = -5
+PB_FP64 = 0
+PB_FP32_IR = 1
+PB_KERNEL_PAIRS_FP64 = 0
+PB_KERNEL_PAIRS_FP32 = 1
+PB_KERNEL_PAIRS_FP64_T = 2
+PB_KERNEL_PAIRS_FP32_T = 3
+PB_KERNEL_SOURCE = 4
+PB_KERNEL_CHARGE = 5
+
+# Every function the header declares, with its C prototype in ctypes terms.
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_dbl = ctypes.c_double
+
+
+class _Surface(ctypes.Structure):
+    _fields_ = [("n_vert", _i64), ("n_tri", _i64), ("vert", _vp), ("tri", _vp)]
+
+
+class _Charges(ctypes.Structure):
+    _fields_ = [("n", _i64), ("pos", _vp), ("q", _vp)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eps_in", _dbl), ("eps_out", _dbl), ("kappa", _dbl), ("tol", _dbl),
+                ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("inner_tol", _dbl)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("e_solv", _dbl), ("rel_residual", _dbl), ("seconds", _dbl),
+                ("iters", ctypes.c_int32), ("matvecs_fp64", ctypes.c_int32),
+                ("matvecs_fp32", ctypes.c_int32), ("refinements", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_PROTOS = {
+    "pb_abi_version": (_int, []),
+    "pb_create": (_int, [_int, _vp, ctypes.POINTER(_vp)]),
+    "pb_destroy": (None, [_vp]),
+    "pb_last_error": (ctypes.c_char_p, [_vp]),
+    "pb_geometry": (_int, [_vp, ctypes.POINTER(_Surface), _vp, _vp, _vp]),
+    "pb_source": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
+                         ctypes.POINTER(_Params), _vp]),
+    "pb_matvec": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params), _vp, _vp,
+                         _int, _int]),
+    "pb_energy": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
+                         ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_dbl)]),
+    "pb_solve": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
+                        ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
+    "pb_matvec_dev": (_int, [_vp, _i64, _i64, _vp, _vp, ctypes.POINTER(_Params), _vp, _vp,
+                             _int, _int]),
+    "pb_solve_dev": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp,
+                            ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
+    "pb_profile_enable": (_int, [_vp, _int]),
+    "pb_profile_reset": (_int, [_vp]),
+    "pb_profile_read": (_int, [_vp, _int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
+                               ctypes.POINTER(_dbl)]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpbdsbi.so and attach prototypes.  Raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"HIP library {path} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(path)
+        for name, (res, args) in _PROTOS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_PROTOS)
+
+
+class PbError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+@dataclass
+class Params:
+    eps_in: float = 1.0
+    eps_out: float = 80.0
+    kappa: float = 0.1257
+    tol: float = 1e-6
+    restart: int = 10
+    max_iter: int = 1000
+    precision: int = PB_FP64
+    max_refine: int = 20
+    inner_tol: float = 1e-4
+
+    def c(self) -> _Params:
+        return _Params(float(self.eps_in), float(self.eps_out), float(self.kappa), float(self.tol),
+                       int(self.restart), int(self.max_iter), int(self.precision),
+                       int(self.max_refine), float(self.inner_tol))
+
+
+@dataclass
+class Info:
+    e_solv: float
+    rel_residual: float
+    seconds: float
+    iters: int
+    matvecs_fp64: int
+    matvecs_fp32: int
+    refinements: int
+    status: int
+
+    @staticmethod
+    def of(ci: _Info) -> "Info":
+        return Info(ci.e_solv, ci.rel_residual, ci.seconds, ci.iters, ci.matvecs_fp64,
+                    ci.matvecs_fp32, ci.refinements, ci.status)
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, _vp(a.ctypes.data)
+
+
+def _dev(t, dtype_name: str):
+    """Pointer of a contiguous torch device tensor of the given dtype."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch." + dtype_name:
+        raise PbError(PB_ERR_ARG, f"expected a contiguous {dtype_name} device tensor")
+    return _vp(t.data_ptr())
+
+
+class Context:
+    """One pb_ctx: a device, a stream and the device scratch reused across calls."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = load_library()
+        h = _vp()
+        s = None
+        if stream is not None:
+            s = _vp(stream if isinstance(stream, int) else int(stream.cuda_stream))
+        st = L.pb_create(int(device), s, ctypes.byref(h))
+        if st != PB_OK or not h.value:
+            raise PbError(st, f"pb_create(device={device}) failed")
+        self._h = h
+        self._L = L
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.pb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st: int) -> int:
+        if st < 0:
+            raise PbError(st, self._L.pb_last_error(self._h).decode())
+        return st
+
+    @staticmethod
+    def _surface(verts, tris):
+        v, pv = _host(verts, np.float64)
+        t, pt = _host(tris, np.int32)
+        return _Surface(v.shape[0], t.shape[0], pv, pt), (v, t)
+
+    @staticmethod
+    def _charges(pos, q):
+        p, pp = _host(pos, np.float64)
+        qq, pq = _host(q, np.float64)
+        return _Charges(qq.shape[0], pp, pq), (p, qq)
+
+    # -- host-pointer entry points ------------------------------------------
+    def pb_geometry(self, verts, tris):
+        s, keep = self._surface(verts, tris)
+        n = s.n_tri
+        cen = np.empty((n, 3))
+        nrm = np.empty((n, 3))
+        area = np.empty(n)
+        self._check(self._L.pb_geometry(self._h, ctypes.byref(s), _vp(cen.ctypes.data),
+                                        _vp(nrm.ctypes.data), _vp(area.ctypes.data)))
+        return cen, nrm, area
+
+    def pb_source(self, verts, tris, pos, q, params: Params):
+        s, k1 = self._surface(verts, tris)
+        c, k2 = self._charges(pos, q)
+        b = np.empty(2 * s.n_tri)
+        p = params.c()
+        self._check(self._L.pb_source(self._h, ctypes.byref(s), ctypes.byref(c), ctypes.byref(p),
+                                      _vp(b.ctypes.data)))
+        return b
+
+    def pb_matvec(self, verts, tris, x, params: Params, transpose=False, precision=PB_FP64):
+        s, k1 = self._surface(verts, tris)
+        xx, px = _host(x, np.float64)
+        y = np.empty_like(xx)
+        p = params.c()
+        self._check(self._L.pb_matvec(self._h, ctypes.byref(s), ctypes.byref(p), px,
+                                      _vp(y.ctypes.data), int(bool(transpose)), int(precision)))
+        return y
+
+    def pb_energy(self, verts, tris, pos, q, phi, dphi, params: Params) -> float:
+        s, k1 = self._surface(verts, tris)
+        c, k2 = self._charges(pos, q)
+        a, pa = _host(phi, np.float64)
+        b, pb = _host(dphi, np.float64)
+        e = _dbl()
+        p = params.c()
+        self._check(self._L.pb_energy(self._h, ctypes.byref(s), ctypes.byref(c), ctypes.byref(p),
+                                      pa, pb, ctypes.byref(e)))
+        return float(e.value)
+
+    def pb_solve(self, verts, tris, pos, q, params: Params):
+        """Returns (info, phi, dphi); info.status is PB_OK or PB_NOT_CONVERGED."""
+        s, k1 = self._surface(verts, tris)
+        c, k2 = self._charges(pos, q)
+        phi = np.empty(s.n_tri)
+        dphi = np.empty(s.n_tri)
+        info = _Info()
+        p = params.c()
+        self._check(self._L.pb_solve(self._h, ctypes.byref(s), ctypes.byref(c), ctypes.byref(p),
+                                     _vp(phi.ctypes.data), _vp(dphi.ctypes.data),
+                                     ctypes.byref(info)))
+        return Info.of(info), phi, dphi
+
+    # -- device-pointer entry points (torch tensors) --------------------------
+    def pb_matvec_dev(self, verts, tris, x, y, params: Params, transpose=False,
+                      precision=PB_FP64):
+        p = params.c()
+        self._check(self._L.pb_matvec_dev(self._h, verts.shape[0], tris.shape[0],
+                                          _dev(verts, "float64"), _dev(tris, "int32"), ctypes.byref(p),
+                                          _dev(x, "float64"), _dev(y, "float64"),
+                                          int(bool(transpose)), int(precision)))
+        return y
+
+    def pb_solve_dev(self, verts, tris, pos, q, params: Params, phi=None, dphi=None) -> Info:
+        p = params.c()
+        info = _Info()
+        self._check(self._L.pb_solve_dev(self._h, verts.shape[0], tris.shape[0],
+                                         _dev(verts, "float64"), _dev(tris, "int32"), q.shape[0],
+                                         _dev(pos, "float64"), _dev(q, "float64"), ctypes.byref(p),
+                                         _dev(phi, "float64"), _dev(dphi, "float64"),
+                                         ctypes.byref(info)))
+        return Info.of(info)
+
+    # -- kernel timing hook ------------------------------------------------------
+    def profile_enable(self, on: bool = True):
+        self._check(self._L.pb_profile_enable(self._h, int(bool(on))))
+
+    def profile_reset(self):
+        self._check(self._L.pb_profile_reset(self._h))
+
+    def profile_read(self, kernel: int):
+        """(launches, total_ms, algorithmic pairs) accumulated for one kernel id."""
+        n = _i64()
+        ms = _dbl()
+        pr = _dbl()
+        self._check(self._L.pb_profile_read(self._h, int(kernel), ctypes.byref(n),
+                                            ctypes.byref(ms), ctypes.byref(pr)))
+        return int(n.value), float(ms.value), float(pr.value)
