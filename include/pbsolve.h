@@ -90,7 +90,7 @@ typedef struct {
     int32_t matvecs_fp32;       /* FP32 matvecs */
     int32_t refinements;        /* IR outer steps (0 for PB_FP64) */
     int32_t status;             /* same as the return value */
-    int32_t reserved;
+    int32_t adjoint_iters;      /* Arnoldi steps of the adjoint solve (pb_forces*) */
 } pb_info;
 
 /* ---- context ---------------------------------------------------------- */
@@ -134,6 +134,17 @@ int pb_energy(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_pa
 int pb_solve(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_params *p,
              double *phi, double *dphi, pb_info *info);
 
+/* Step 6 and the adjoint method: forward solve (as pb_solve), adjoint solve
+ * A^T lam = B^T q with the transpose matvec (same precision and tolerance),
+ * then the derivatives of E_sol for a fixed surface:
+ *   dE_dpos [n_charges][3]  dE_sol/dy_k in kcal/mol/A (the force is minus it),
+ *   dE_dq   [n_charges]     dE_sol/dq_k in kcal/mol/e_c.
+ * E = (1/2) q^T B xi with A xi = b(y) q-linear, so
+ *   dE/dq = (1/2)(B xi + C^T lam) scaled, dE/dy_k = q_k grad_y(...) (see the
+ * kernel comments).  info->e_solv, iters (forward) and adjoint_iters are set. */
+int pb_forces(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_params *p,
+              double *dE_dpos, double *dE_dq, pb_info *info);
+
 /* ---- device-pointer entry points -------------------------------------- */
 /* Same operations; every array argument is device memory laid out as above.
  * Validation of the surface runs on the device. */
@@ -146,6 +157,11 @@ int pb_solve_dev(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_ver
                  const int32_t *d_tri, int64_t n_charges, const double *d_pos,
                  const double *d_q, const pb_params *p, double *d_phi, double *d_dphi,
                  pb_info *info);
+
+int pb_forces_dev(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                  const int32_t *d_tri, int64_t n_charges, const double *d_pos,
+                  const double *d_q, const pb_params *p, double *d_dE_dpos, double *d_dE_dq,
+                  pb_info *info);
 
 /* ---- kernel timing hook (benchmarks, profiling) ------------------------ */
 /* When enabled, every launch of the kernels below is bracketed by a pair of

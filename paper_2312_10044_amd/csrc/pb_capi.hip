@@ -296,6 +296,7 @@ int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
 struct Vecs {
     int64_t n2 = 0, ld = 0;
     double *x = nullptr, *b = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
+    double *lam = nullptr, *aux = nullptr;
     double *V = nullptr;
 };
 
@@ -303,7 +304,7 @@ int setup_vectors(pb_ctx *c, int m, Vecs &v)
 {
     v.n2 = 2 * c->g.n;
     v.ld = round_up(v.n2, 64);
-    TRY(ensure(c, c->vec, sizeof(double) * 6 * v.ld));
+    TRY(ensure(c, c->vec, sizeof(double) * 8 * v.ld));
     TRY(ensure(c, c->V, sizeof(double) * (m + 1) * v.ld));
     double *base = as<double>(c->vec);
     v.x = base;
@@ -312,6 +313,8 @@ int setup_vectors(pb_ctx *c, int m, Vecs &v)
     v.r = base + 3 * v.ld;
     v.d = base + 4 * v.ld;
     v.t = base + 5 * v.ld;
+    v.lam = base + 6 * v.ld;
+    v.aux = base + 7 * v.ld;
     v.V = as<double>(c->V);
     const int nblk = dot_blocks(v.n2);
     TRY(ensure(c, c->dpart, sizeof(double) * (MAX_RESTART + 2) * nblk));
@@ -557,15 +560,72 @@ int check_charges_args(pb_ctx *c, int64_t nc, const void *pos, const void *q)
     return PB_OK;
 }
 
-// Whole path on device-resident inputs.
-int solve_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
-              const int32_t *d_tri, int64_t nc, const double *d_pos, const double *d_q,
-              const pb_params *p, double *d_phi, double *d_dphi, pb_info *info)
+struct SolveStats {
+    int iters = 0, mv64 = 0, mv32 = 0, refinements = 0, status = PB_OK;
+    double rel = 0.0;
+};
+
+// A x = rhs (A^T x = rhs when transposed) to p->tol: FP64 GMRES, or FP32
+// inner GMRES solves inside FP64 iterative refinement (r = rhs - A x in
+// FP64; inner solve A d = r in FP32 pair arithmetic to inner_tol; x += d).
+// Uses v.w, v.r, v.t, v.d and the Krylov basis; rhs and x must be other slots.
+int solve_system(pb_ctx *c, const pb_params *p, int transpose, const double *rhs, double *x,
+                 Vecs &v, SolveStats &out)
+{
+    out = SolveStats();
+    GmresStats st;
+    if (p->precision == PB_FP64) {
+        TRY(gmres(c, p, PB_FP64, transpose, rhs, x, true, p->tol, p->max_iter, v, st));
+        out.iters = st.iters;
+        out.mv64 = st.mv64;
+        out.rel = st.rel;
+        out.status = st.converged ? PB_OK : PB_NOT_CONVERGED;
+        return PB_OK;
+    }
+    double bnorm;
+    TRY(norm_host(c, rhs, v.n2, &bnorm));
+    launch_fill(c->stream, x, 0.0, v.n2);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(v.r, rhs, sizeof(double) * v.n2, hipMemcpyDeviceToDevice, c->stream));
+    double rnorm = bnorm;
+    out.status = PB_NOT_CONVERGED;
+    for (;;) {
+        out.rel = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+        if (out.rel <= p->tol) {
+            out.status = PB_OK;
+            break;
+        }
+        if (out.refinements >= p->max_refine || out.iters >= p->max_iter)
+            break;
+        HIPCHK(hipMemcpyAsync(v.t, v.r, sizeof(double) * v.n2, hipMemcpyDeviceToDevice,
+                              c->stream));
+        TRY(gmres(c, p, PB_FP32_IR, transpose, v.t, v.d, true, p->inner_tol,
+                  p->max_iter - out.iters, v, st));
+        out.iters += st.iters;
+        out.mv32 += st.mv32;
+        launch_add(c->stream, x, v.d, v.n2);
+        LAUNCHCHK();
+        out.refinements++;
+        TRY(apply(c, p, PB_FP64, transpose, x, v.w));
+        out.mv64++;
+        launch_sub(c->stream, rhs, v.w, v.r, v.n2);
+        LAUNCHCHK();
+        TRY(norm_host(c, v.r, v.n2, &rnorm));
+        if (!std::isfinite(rnorm))
+            return fail(c, PB_ERR_GEOMETRY, "non-finite residual in refinement");
+    }
+    return PB_OK;
+}
+
+// Steps 1, 2 and the forward solve on device-resident inputs; leaves the
+// solution in v.x.
+int forward_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                const int32_t *d_tri, int64_t nc, const double *d_pos, const double *d_q,
+                const pb_params *p, Vecs &v, SolveStats &ss)
 {
     TRY(check_params(c, p, true));
     TRY(check_charges_args(c, nc, d_pos, d_q));
     TRY(setup_geometry(c, n_vert, n_tri, d_vert, d_tri));
-    Vecs v;
     TRY(setup_vectors(c, p->restart, v));
     TRY(check_charges_inside(c, p, nc, d_pos, v));
     {
@@ -573,55 +633,35 @@ int solve_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
         launch_source(c->stream, c->g, nc, d_pos, d_q, p->eps_in, v.b);
     }
     LAUNCHCHK();
-    GmresStats st;
-    int status = PB_OK;
-    int refinements = 0;
-    int iters = 0, mv64 = 0, mv32 = 0;
-    double rel = 0.0;
-    if (p->precision == PB_FP64) {
-        TRY(gmres(c, p, PB_FP64, 0, v.b, v.x, true, p->tol, p->max_iter, v, st));
-        iters = st.iters;
-        mv64 = st.mv64;
-        rel = st.rel;
-        status = st.converged ? PB_OK : PB_NOT_CONVERGED;
-    } else {
-        // FP64 iterative refinement around FP32 inner GMRES solves.
-        double bnorm;
-        TRY(norm_host(c, v.b, v.n2, &bnorm));
-        launch_fill(c->stream, v.x, 0.0, v.n2);
-        LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(v.r, v.b, sizeof(double) * v.n2, hipMemcpyDeviceToDevice,
-                              c->stream));
-        double rnorm = bnorm;
-        status = PB_NOT_CONVERGED;
-        for (;;) {
-            rel = bnorm > 0.0 ? rnorm / bnorm : 0.0;
-            if (rel <= p->tol) {
-                status = PB_OK;
-                break;
-            }
-            if (refinements >= p->max_refine || iters >= p->max_iter)
-                break;
-            // inner solve A d = r in FP32 arithmetic; copy r aside (gmres uses v.r)
-            HIPCHK(hipMemcpyAsync(v.t, v.r, sizeof(double) * v.n2, hipMemcpyDeviceToDevice,
-                                  c->stream));
-            TRY(gmres(c, p, PB_FP32_IR, 0, v.t, v.d, true, p->inner_tol, p->max_iter - iters, v,
-                      st));
-            iters += st.iters;
-            mv32 += st.mv32;
-            launch_add(c->stream, v.x, v.d, v.n2);
-            LAUNCHCHK();
-            refinements++;
-            // outer residual in FP64
-            TRY(apply(c, p, PB_FP64, 0, v.x, v.w));
-            mv64++;
-            launch_sub(c->stream, v.b, v.w, v.r, v.n2);
-            LAUNCHCHK();
-            TRY(norm_host(c, v.r, v.n2, &rnorm));
-            if (!std::isfinite(rnorm))
-                return fail(c, PB_ERR_GEOMETRY, "non-finite residual in refinement");
-        }
-    }
+    TRY(solve_system(c, p, 0, v.b, v.x, v, ss));
+    return PB_OK;
+}
+
+void fill_info(pb_info *info, double e, const SolveStats &f, const SolveStats *a)
+{
+    if (!info)
+        return;
+    info->e_solv = e;
+    info->rel_residual = f.rel;
+    info->iters = f.iters;
+    info->matvecs_fp64 = f.mv64 + (a ? a->mv64 : 0);
+    info->matvecs_fp32 = f.mv32 + (a ? a->mv32 : 0);
+    info->refinements = f.refinements;
+    info->adjoint_iters = a ? a->iters : 0;
+    int st = f.status;
+    if (a && a->status != PB_OK)
+        st = a->status;
+    info->status = st;
+}
+
+// Whole path on device-resident inputs.
+int solve_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+              const int32_t *d_tri, int64_t nc, const double *d_pos, const double *d_q,
+              const pb_params *p, double *d_phi, double *d_dphi, pb_info *info)
+{
+    Vecs v;
+    SolveStats ss;
+    TRY(forward_dev(c, n_vert, n_tri, d_vert, d_tri, nc, d_pos, d_q, p, v, ss));
     double e = 0.0;
     TRY(energy_dev(c, p, nc, d_pos, d_q, v.x, &e));
     if (d_phi)
@@ -631,19 +671,55 @@ int solve_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
         HIPCHK(hipMemcpyAsync(d_dphi, v.x + n_tri, sizeof(double) * n_tri,
                               hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (info) {
-        info->e_solv = e;
-        info->rel_residual = rel;
-        info->iters = iters;
-        info->matvecs_fp64 = mv64;
-        info->matvecs_fp32 = mv32;
-        info->refinements = refinements;
-        info->status = status;
-    }
-    if (status == PB_NOT_CONVERGED)
-        fail(c, PB_NOT_CONVERGED, "GMRES stopped at relative residual %.3e > tol %.3e", rel,
+    fill_info(info, e, ss, nullptr);
+    if (ss.status == PB_NOT_CONVERGED)
+        fail(c, PB_NOT_CONVERGED, "GMRES stopped at relative residual %.3e > tol %.3e", ss.rel,
              p->tol);
-    return status;
+    return ss.status;
+}
+
+// Forward solve, adjoint solve A^T lam' = B'^T q and the gradient sweep.
+int forces_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+               const int32_t *d_tri, int64_t nc, const double *d_pos, const double *d_q,
+               const pb_params *p, double *d_dpos, double *d_dq, pb_info *info)
+{
+    if (!d_dpos || !d_dq)
+        return fail(c, PB_ERR_ARG, "gradient outputs are NULL");
+    Vecs v;
+    SolveStats fs, as_;
+    TRY(forward_dev(c, n_vert, n_tri, d_vert, d_tri, nc, d_pos, d_q, p, v, fs));
+    const Geo &g = c->g;
+    const PairParams pp = pair_params(c, p);
+    {
+        ProfScope ps(c, PB_KERNEL_CHARGE, (double)g.n * (double)nc);
+        launch_adjoint_rhs(c->stream, g, nc, d_pos, d_q, pp.eps, pp.kappa, v.aux);
+    }
+    LAUNCHCHK();
+    TRY(solve_system(c, p, 1, v.aux, v.lam, v, as_));
+    const Sweep sw = plan_sweep(nc, g.npad, TARGET_WAVES);
+    const int64_t ncpad = (int64_t)sw.n_tblocks * TPB;
+    TRY(ensure(c, c->chg_part, sizeof(double) * 8 * sw.n_chunks * ncpad));
+    TRY(ensure(c, c->src64, sizeof(double) * 16 * g.npad));
+    double *fwd = as<double>(c->src64), *adj = fwd + 8 * g.npad;
+    launch_pack_f64(c->stream, g, v.x, fwd, 0);
+    LAUNCHCHK();
+    launch_pack_f64(c->stream, g, v.lam, adj, 1);
+    LAUNCHCHK();
+    {
+        ProfScope ps(c, PB_KERNEL_CHARGE, (double)g.n * (double)nc);
+        launch_force_pairs(c->stream, fwd, adj, nc, d_pos, sw, pp, as<double>(c->chg_part), ncpad);
+    }
+    LAUNCHCHK();
+    const int slot = HSMALL - 3;
+    launch_force_finish(c->stream, as<double>(c->chg_part), sw.n_chunks, nc, ncpad, d_q,
+                        0.5 * C_UNITS, 1.0 / (4.0 * M_PI * p->eps_in), d_dpos, d_dq,
+                        as<double>(c->small) + slot);
+    LAUNCHCHK();
+    TRY(fetch_small(c, slot, 1));
+    fill_info(info, c->hsmall[slot], fs, &as_);
+    if (info && info->status == PB_NOT_CONVERGED)
+        fail(c, PB_NOT_CONVERGED, "forward or adjoint GMRES did not reach tol %.3e", p->tol);
+    return info ? info->status : (fs.status != PB_OK ? fs.status : as_.status);
 }
 
 // Host inputs -> context buffers.
@@ -910,6 +986,45 @@ static int pb_solve_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q, co
     return st;
 }
 
+static int pb_forces_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q,
+                          const pb_params *p, double *dE_dpos, double *dE_dq, pb_info *info)
+{
+    const double t0 = now_s();
+    TRY(enter(c));
+    if (!dE_dpos || !dE_dq)
+        return fail(c, PB_ERR_ARG, "gradient outputs are NULL");
+    const double *dv, *dp, *dq;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(upload_charges(c, q, &dp, &dq));
+    TRY(ensure(c, c->io_y, sizeof(double) * 4 * q->n));
+    double *gpos = as<double>(c->io_y), *gq = gpos + 3 * q->n;
+    const int st = forces_dev(c, s->n_vert, s->n_tri, dv, dt, q->n, dp, dq, p, gpos, gq, info);
+    if (st < 0)
+        return st;
+    HIPCHK(hipMemcpyAsync(dE_dpos, gpos, sizeof(double) * 3 * q->n, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(dE_dq, gq, sizeof(double) * q->n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (info)
+        info->seconds = now_s() - t0;
+    return st;
+}
+
+static int pb_forces_dev_impl(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                              const int32_t *d_tri, int64_t n_charges, const double *d_pos,
+                              const double *d_q, const pb_params *p, double *d_dE_dpos,
+                              double *d_dE_dq, pb_info *info)
+{
+    const double t0 = now_s();
+    TRY(enter(c));
+    const int st = forces_dev(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p,
+                              d_dE_dpos, d_dE_dq, info);
+    if (info && st >= 0)
+        info->seconds = now_s() - t0;
+    return st;
+}
+
 static int pb_solve_dev_impl(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
                  const int32_t *d_tri, int64_t n_charges, const double *d_pos, const double *d_q,
                  const pb_params *p, double *d_phi, double *d_dphi, pb_info *info)
@@ -964,6 +1079,21 @@ int pb_solve_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
                  const pb_params *p, double *d_phi, double *d_dphi, pb_info *info)
 {
     return leave(c, pb_solve_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p, d_phi, d_dphi, info));
+}
+
+int pb_forces(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
+              double *dE_dpos, double *dE_dq, pb_info *info)
+{
+    return leave(c, pb_forces_impl(c, s, q, p, dE_dpos, dE_dq, info));
+}
+
+int pb_forces_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                  const int32_t *d_tri, int64_t n_charges, const double *d_pos,
+                  const double *d_q, const pb_params *p, double *d_dE_dpos, double *d_dE_dq,
+                  pb_info *info)
+{
+    return leave(c, pb_forces_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p,
+                                       d_dE_dpos, d_dE_dq, info));
 }
 
 int pb_profile_enable(pb_ctx *c, int enable)

@@ -72,6 +72,18 @@ void launch_charge_pairs(hipStream_t s, const Geo &geo, const double *src, int64
 void launch_charge_finish(hipStream_t s, const double *part, int n_chunks, int64_t nc,
                           int64_t ncpad, const double *q, double *per, double *out);
 
+// Adjoint right-hand side w' = B'^T q (2n).
+void launch_adjoint_rhs(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,
+                        const double *q, double eps, double kappa, double *w);
+// Gradient sweep: fwd = forward-packed xi, adj = transpose-packed lambda';
+// part[(o * n_chunks + c) * ncpad + k], o < 8.
+void launch_force_pairs(hipStream_t s, const double *fwd, const double *adj, int64_t nc,
+                        const double *pos, const Sweep &sw, const PairParams &pp, double *part,
+                        int64_t ncpad);
+void launch_force_finish(hipStream_t s, const double *part, int n_chunks, int64_t nc,
+                         int64_t ncpad, const double *q, double half_cu, double inv4pi_eps_in,
+                         double *dpos, double *dq, double *out);
+
 // ---- deterministic BLAS-1 on device vectors of length n ----------------
 int dot_blocks(int64_t n);
 // part[j * nblk + b] = block b's share of <V_j, w> for j < k, and of <w, w> at j = k.

@@ -413,6 +413,147 @@ __global__ __launch_bounds__(TPB) void k_charge_finish(const double *__restrict_
         out[0] = r;
 }
 
+// ---- adjoint (forces) --------------------------------------------------------
+//
+// E = (c_u/2) q^T B' xi with A xi = b(y) and B'_{k,.} = [a_j K2'(y_k,x_j) | a_j K1'(y_k,x_j)]
+// (K' = 4 pi K).  The adjoint right-hand side w' = B'^T q, per triangle j
+// (d = x_j - y_k, c_x = n_j.d):
+//   w'1_j = -a_j sum_k q_k g2 c_x / r^3      (phi block, K2')
+//   w'2_j = -a_j sum_k q_k (e - 1) / r       (psi block, K1')
+__global__ __launch_bounds__(TPB) void k_adjoint_rhs(const double *__restrict__ g, int64_t n,
+                                                     int64_t npad, int64_t nc,
+                                                     const double *__restrict__ pos,
+                                                     const double *__restrict__ q, double eps,
+                                                     double kappa, double *__restrict__ w)
+{
+    __shared__ double4 sh[TILE];
+    const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const double xj = g[j], yj = g[npad + j], zj = g[2 * npad + j];
+    const double nxj = g[3 * npad + j], nyj = g[4 * npad + j], nzj = g[5 * npad + j];
+    const double epsm1 = eps - 1.0;
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t t0 = 0; t0 < nc; t0 += TILE) {
+        __syncthreads();
+        const int64_t k = t0 + threadIdx.x;
+        sh[threadIdx.x] = (k < nc) ? make_double4(pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], q[k])
+                                   : make_double4(FAR_SRC, 0.0, 0.0, 0.0);
+        __syncthreads();
+        const int cnt = (int)min((int64_t)TILE, nc - t0);
+        for (int kk = 0; kk < cnt; ++kk) {
+            const double4 c = sh[kk];
+            const double dx = xj - c.x, dy = yj - c.y, dz = zj - c.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double ir = rsqrt(r2);
+            const double kr = kappa * (r2 * ir);
+            const double e = exp(-kr);
+            const double em1 = e - 1.0;
+            const double g2 = fma(eps, fma(kr, e, em1), epsm1);
+            const double cxd = nxj * dx + nyj * dy + nzj * dz;
+            s1 = fma(c.w * g2 * cxd, ir * ir * ir, s1);
+            s2 = fma(c.w * em1, ir, s2);
+        }
+    }
+    if (j < n) {
+        const double a = g[6 * npad + j];
+        w[j] = -a * s1;
+        w[n + j] = -a * s2;
+    }
+}
+
+// Per-charge sweep over triangles for the gradients (d = y_k - x_j):
+//  out0: P'_k = sum_j [-(e-1)/r w_j + g2 (m_j.d) u]                (reaction potential)
+//  out1-3: grad_y P'_k = sum_j u {d [w_j (kappa r e + e - 1) - eps kappa^2 e (m_j.d)
+//                                    - 3 g2 (m_j.d)/r^2] + g2 m_j}
+//  out4: c_k = sum_j [l_j / r + (p_j.d) u]                        (sum_i lam_i C'_ik eps_in)
+//  out5-7: grad_y c_k = sum_j u [p_j - d (l_j + 3 (p_j.d)/r^2)]
+// with (w, m) = (a psi, a phi n) from the forward stream and (l, p) =
+// (lam1, lam2 n) from the transposed stream.
+__global__ __launch_bounds__(TPB) void k_force_pairs(const Src8<double> *__restrict__ fwd,
+                                                     const Src8<double> *__restrict__ adj,
+                                                     int64_t nc, const double *__restrict__ pos,
+                                                     Sweep sw, PairParams pp,
+                                                     double *__restrict__ part, int64_t ncpad)
+{
+    __shared__ Src8<double> shf[TILE];
+    __shared__ Src8<double> sha[TILE];
+    const int b = blockIdx.x;
+    const int chunk = b % sw.n_chunks;
+    const int tb = b / sw.n_chunks;
+    const int64_t k = (int64_t)tb * TPB + threadIdx.x;
+    const int64_t kk = k < nc ? k : nc - 1;
+    const double yx = pos[3 * kk], yy = pos[3 * kk + 1], yz = pos[3 * kk + 2];
+    const double eps = pp.eps, epsm1 = pp.eps - 1.0, kap = pp.kappa, ek2 = pp.eps * kap * kap;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int t0 = chunk * sw.tiles_per_chunk;
+    const int t1 = min(sw.n_tiles, t0 + sw.tiles_per_chunk);
+    for (int t = t0; t < t1; ++t) {
+        __syncthreads();
+        shf[threadIdx.x] = fwd[(int64_t)t * TILE + threadIdx.x];
+        sha[threadIdx.x] = adj[(int64_t)t * TILE + threadIdx.x];
+        __syncthreads();
+        for (int jj = 0; jj < TILE; ++jj) {
+            const Src8<double> f = shf[jj];
+            const Src8<double> a = sha[jj];
+            const double dx = yx - f.x, dy = yy - f.y, dz = yz - f.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double ir = rsqrt(r2);
+            const double ir2 = ir * ir;
+            const double u = ir2 * ir;
+            const double kr = kap * (r2 * ir);
+            const double e = exp(-kr);
+            const double em1 = e - 1.0;
+            const double g2 = fma(eps, fma(kr, e, em1), epsm1);
+            const double md = f.mx * dx + f.my * dy + f.mz * dz;
+            acc[0] = fma(-em1, ir * f.w, acc[0]);
+            acc[0] = fma(g2 * md, u, acc[0]);
+            const double cd = f.w * fma(kr, e, em1) - ek2 * e * md - 3.0 * g2 * md * ir2;
+            acc[1] = fma(u, fma(dx, cd, g2 * f.mx), acc[1]);
+            acc[2] = fma(u, fma(dy, cd, g2 * f.my), acc[2]);
+            acc[3] = fma(u, fma(dz, cd, g2 * f.mz), acc[3]);
+            const double pd = a.mx * dx + a.my * dy + a.mz * dz;
+            acc[4] = fma(a.w, ir, acc[4]);
+            acc[4] = fma(pd, u, acc[4]);
+            const double ca = a.w + 3.0 * pd * ir2;
+            acc[5] = fma(u, fma(-dx, ca, a.mx), acc[5]);
+            acc[6] = fma(u, fma(-dy, ca, a.my), acc[6]);
+            acc[7] = fma(u, fma(-dz, ca, a.mz), acc[7]);
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+        part[((int64_t)o * sw.n_chunks + chunk) * ncpad + k] = acc[o];
+}
+
+// dE/dq_k = (c_u/2) [P'_k + c_k/(4 pi eps_in)],
+// dE/dy_k = (c_u/2) q_k [grad P'_k + grad c_k/(4 pi eps_in)], out[0] = E.
+__global__ __launch_bounds__(TPB) void k_force_finish(const double *__restrict__ part,
+                                                      int n_chunks, int64_t nc, int64_t ncpad,
+                                                      const double *__restrict__ q,
+                                                      double half_cu, double inv4pi_eps_in,
+                                                      double *__restrict__ dpos,
+                                                      double *__restrict__ dq,
+                                                      double *__restrict__ out)
+{
+    __shared__ double sh[TPB / 64];
+    double tot = 0.0;
+    for (int64_t k = threadIdx.x; k < nc; k += TPB) {
+        double v[8];
+        for (int o = 0; o < 8; ++o) {
+            double s = 0.0;
+            for (int c = 0; c < n_chunks; ++c)
+                s += part[((int64_t)o * n_chunks + c) * ncpad + k];
+            v[o] = s;
+        }
+        tot += q[k] * v[0];
+        dq[k] = half_cu * (v[0] + inv4pi_eps_in * v[4]);
+        for (int d = 0; d < 3; ++d)
+            dpos[3 * k + d] = half_cu * q[k] * (v[1 + d] + inv4pi_eps_in * v[5 + d]);
+    }
+    const double r = block_sum(tot, sh);
+    if (threadIdx.x == 0)
+        out[0] = half_cu * r;
+}
+
 // ---- BLAS-1 ----------------------------------------------------------------
 
 __global__ __launch_bounds__(TPB) void k_dots(const double *__restrict__ V, int64_t ld, int k,
@@ -622,6 +763,30 @@ void launch_charge_finish(hipStream_t s, const double *part, int n_chunks, int64
 {
     hipLaunchKernelGGL(k_charge_finish, dim3(1), dim3(TPB), 0, s, part, n_chunks, nc, ncpad, q,
                        per, out);
+}
+
+void launch_adjoint_rhs(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,
+                        const double *q, double eps, double kappa, double *w)
+{
+    hipLaunchKernelGGL(k_adjoint_rhs, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
+                       geo.npad, nc, pos, q, eps, kappa, w);
+}
+
+void launch_force_pairs(hipStream_t s, const double *fwd, const double *adj, int64_t nc,
+                        const double *pos, const Sweep &sw, const PairParams &pp, double *part,
+                        int64_t ncpad)
+{
+    hipLaunchKernelGGL(k_force_pairs, dim3(sw.n_tblocks * sw.n_chunks), dim3(TPB), 0, s,
+                       reinterpret_cast<const Src8<double> *>(fwd),
+                       reinterpret_cast<const Src8<double> *>(adj), nc, pos, sw, pp, part, ncpad);
+}
+
+void launch_force_finish(hipStream_t s, const double *part, int n_chunks, int64_t nc,
+                         int64_t ncpad, const double *q, double half_cu, double inv4pi_eps_in,
+                         double *dpos, double *dq, double *out)
+{
+    hipLaunchKernelGGL(k_force_finish, dim3(1), dim3(TPB), 0, s, part, n_chunks, nc, ncpad, q,
+                       half_cu, inv4pi_eps_in, dpos, dq, out);
 }
 
 int dot_blocks(int64_t n)

@@ -58,7 +58,7 @@ class _Info(ctypes.Structure):
     _fields_ = [("e_solv", _dbl), ("rel_residual", _dbl), ("seconds", _dbl),
                 ("iters", ctypes.c_int32), ("matvecs_fp64", ctypes.c_int32),
                 ("matvecs_fp32", ctypes.c_int32), ("refinements", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("adjoint_iters", ctypes.c_int32)]
 
 
 _PROTOS = {
@@ -79,6 +79,10 @@ _PROTOS = {
                              _int, _int]),
     "pb_solve_dev": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp,
                             ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
+    "pb_forces": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
+                         ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
+    "pb_forces_dev": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp,
+                             ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
     "pb_profile_enable": (_int, [_vp, _int]),
     "pb_profile_reset": (_int, [_vp]),
     "pb_profile_read": (_int, [_vp, _int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
@@ -142,11 +146,12 @@ class Info:
     matvecs_fp32: int
     refinements: int
     status: int
+    adjoint_iters: int = 0
 
     @staticmethod
     def of(ci: _Info) -> "Info":
         return Info(ci.e_solv, ci.rel_residual, ci.seconds, ci.iters, ci.matvecs_fp64,
-                    ci.matvecs_fp32, ci.refinements, ci.status)
+                    ci.matvecs_fp32, ci.refinements, ci.status, ci.adjoint_iters)
 
 
 def _host(a, dtype):
@@ -265,6 +270,19 @@ class Context:
                                      ctypes.byref(info)))
         return Info.of(info), phi, dphi
 
+    def pb_forces(self, verts, tris, pos, q, params: Params):
+        """Returns (info, dE_dpos [Nc,3], dE_dq [Nc]) for a fixed surface."""
+        s, k1 = self._surface(verts, tris)
+        c, k2 = self._charges(pos, q)
+        gpos = np.empty((c.n, 3))
+        gq = np.empty(c.n)
+        info = _Info()
+        p = params.c()
+        self._check(self._L.pb_forces(self._h, ctypes.byref(s), ctypes.byref(c), ctypes.byref(p),
+                                      _vp(gpos.ctypes.data), _vp(gq.ctypes.data),
+                                      ctypes.byref(info)))
+        return Info.of(info), gpos, gq
+
     # -- device-pointer entry points (torch tensors) --------------------------
     def pb_matvec_dev(self, verts, tris, x, y, params: Params, transpose=False,
                       precision=PB_FP64):
@@ -283,6 +301,16 @@ class Context:
                                          _dev(pos, "float64"), _dev(q, "float64"), ctypes.byref(p),
                                          _dev(phi, "float64"), _dev(dphi, "float64"),
                                          ctypes.byref(info)))
+        return Info.of(info)
+
+    def pb_forces_dev(self, verts, tris, pos, q, params: Params, dE_dpos, dE_dq) -> Info:
+        p = params.c()
+        info = _Info()
+        self._check(self._L.pb_forces_dev(self._h, verts.shape[0], tris.shape[0],
+                                          _dev(verts, "float64"), _dev(tris, "int32"), q.shape[0],
+                                          _dev(pos, "float64"), _dev(q, "float64"), ctypes.byref(p),
+                                          _dev(dE_dpos, "float64"), _dev(dE_dq, "float64"),
+                                          ctypes.byref(info)))
         return Info.of(info)
 
     # -- kernel timing hook ------------------------------------------------------
