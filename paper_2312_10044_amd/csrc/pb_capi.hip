@@ -55,6 +55,9 @@ struct pb_ctx {
     int64_t prof_launches[PB_KERNEL_COUNT] = {};
     double prof_ms[PB_KERNEL_COUNT] = {};
     double prof_pairs[PB_KERNEL_COUNT] = {};
+    // launch configuration of the FP32 forward sweep (pb_set_sweep_config / pb_autotune)
+    int f32_tpt = 1;
+    int f32_waves = TARGET_WAVES;
     // current geometry
     Geo g{};
     double center[3] = {0.0, 0.0, 0.0};
@@ -213,7 +216,7 @@ int setup_geometry(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_ver
         return fail(c, PB_ERR_ARG, "n_tri too large");
     if (!d_vert || !d_tri)
         return fail(c, PB_ERR_ARG, "vertex or triangle array is NULL");
-    const int64_t npad = round_up(n_tri, TILE);
+    const int64_t npad = round_up(n_tri, PADN);
     TRY(ensure(c, c->geo, sizeof(double) * NGEO * npad));
     const int nblk = geometry_blocks(npad);
     TRY(ensure(c, c->geo_part, sizeof(double) * GEO_RED * nblk));
@@ -263,17 +266,27 @@ PairParams pair_params(pb_ctx *c, const pb_params *p)
 int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const double *x, double *y)
 {
     const Geo &g = c->g;
-    const Sweep sw = plan_sweep(g.npad, g.npad, TARGET_WAVES);
+    const bool fast32 = precision == PB_FP32_IR && !transpose;
+    const Sweep sw = fast32 ? plan_sweep(g.npad, g.npad, c->f32_waves, c->f32_tpt)
+                            : plan_sweep(g.npad, g.npad, TARGET_WAVES);
     TRY(ensure(c, c->part, sizeof(double) * 2 * sw.n_chunks * g.npad));
     const PairParams pp = pair_params(c, p);
     const double eps = pp.eps;
     const double npairs = (double)g.n * (double)(g.n - 1);
-    if (precision == PB_FP32_IR) {
+    double scale1 = 1.0;
+    if (fast32) {
         TRY(ensure(c, c->src32, sizeof(float) * 8 * g.npad));
-        launch_pack_f32(c->stream, g, x, as<float>(c->src32), transpose ? 1 : 0, pp.cx, pp.cy,
-                        pp.cz);
+        launch_pack_f32(c->stream, g, x, as<float>(c->src32), 2, pp.cx, pp.cy, pp.cz, eps);
         LAUNCHCHK();
-        ProfScope ps(c, transpose ? PB_KERNEL_PAIRS_FP32_T : PB_KERNEL_PAIRS_FP32, npairs);
+        ProfScope ps(c, PB_KERNEL_PAIRS_FP32, npairs);
+        launch_pairs_f32_fwd(c->stream, g, as<float>(c->src32), sw, pp, c->f32_tpt,
+                             as<double>(c->part));
+        scale1 = eps;   // the reduced form sums row 1 divided by eps
+    } else if (precision == PB_FP32_IR) {
+        TRY(ensure(c, c->src32, sizeof(float) * 8 * g.npad));
+        launch_pack_f32(c->stream, g, x, as<float>(c->src32), 1, pp.cx, pp.cy, pp.cz, eps);
+        LAUNCHCHK();
+        ProfScope ps(c, PB_KERNEL_PAIRS_FP32_T, npairs);
         launch_pairs_f32(c->stream, g, as<float>(c->src32), sw, pp, transpose,
                          as<double>(c->part));
     } else {
@@ -286,7 +299,7 @@ int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
     }
     LAUNCHCHK();
     launch_matvec_finish(c->stream, g, as<double>(c->part), sw.n_chunks, x, 0.5 * (1.0 + eps),
-                         0.5 * (1.0 + 1.0 / eps), transpose, y);
+                         0.5 * (1.0 + 1.0 / eps), transpose, scale1, y);
     LAUNCHCHK();
     return PB_OK;
 }
@@ -1094,6 +1107,94 @@ int pb_forces_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert
 {
     return leave(c, pb_forces_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p,
                                        d_dE_dpos, d_dE_dq, info));
+}
+
+int pb_set_sweep_config(pb_ctx *c, int targets_per_thread, int target_waves)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    if (targets_per_thread != 0 && targets_per_thread != 1 && targets_per_thread != 2)
+        return fail(c, PB_ERR_ARG, "targets_per_thread must be 1 or 2");
+    if (target_waves < 0 || target_waves > (1 << 22))
+        return fail(c, PB_ERR_ARG, "target_waves out of range");
+    if (targets_per_thread)
+        c->f32_tpt = targets_per_thread;
+    if (target_waves)
+        c->f32_waves = target_waves;
+    return PB_OK;
+}
+
+int pb_get_sweep_config(pb_ctx *c, int *targets_per_thread, int *target_waves)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    if (targets_per_thread)
+        *targets_per_thread = c->f32_tpt;
+    if (target_waves)
+        *target_waves = c->f32_waves;
+    return PB_OK;
+}
+
+static int pb_autotune_impl(pb_ctx *c, const pb_surface *s, const pb_params *p, int *best_tpt,
+                            int *best_waves)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    const double *dv;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(setup_geometry(c, s->n_vert, s->n_tri, dv, dt));
+    const int64_t n2 = 2 * c->g.n;
+    TRY(ensure(c, c->io_x, sizeof(double) * n2));
+    TRY(ensure(c, c->io_y, sizeof(double) * n2));
+    launch_fill(c->stream, as<double>(c->io_x), 1.0, n2);
+    LAUNCHCHK();
+    static const int tpts[] = {1, 2};
+    static const int waves[] = {4096, 8192, 16384, 32768};
+    hipEvent_t e0 = pool_event(c, 0), e1 = pool_event(c, 1);
+    if (!e0 || !e1)
+        return fail(c, PB_ERR_HIP, "hipEventCreate failed");
+    const bool prof = c->prof_on;
+    c->prof_on = false;
+    float best = 0.f;
+    int bt = c->f32_tpt, bw = c->f32_waves;
+    for (int tp : tpts) {
+        for (int wv : waves) {
+            c->f32_tpt = tp;
+            c->f32_waves = wv;
+            int rc = apply(c, p, PB_FP32_IR, 0, as<double>(c->io_x), as<double>(c->io_y));
+            if (rc < 0) {
+                c->prof_on = prof;
+                return rc;
+            }
+            HIPCHK(hipEventRecord(e0, c->stream));
+            for (int rep = 0; rep < 2; ++rep)
+                TRY(apply(c, p, PB_FP32_IR, 0, as<double>(c->io_x), as<double>(c->io_y)));
+            HIPCHK(hipEventRecord(e1, c->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (best == 0.f || ms < best) {
+                best = ms;
+                bt = tp;
+                bw = wv;
+            }
+        }
+    }
+    c->prof_on = prof;
+    c->f32_tpt = bt;
+    c->f32_waves = bw;
+    if (best_tpt)
+        *best_tpt = bt;
+    if (best_waves)
+        *best_waves = bw;
+    return PB_OK;
+}
+
+int pb_autotune(pb_ctx *c, const pb_surface *s, const pb_params *p, int *best_tpt,
+                int *best_waves)
+{
+    return leave(c, pb_autotune_impl(c, s, p, best_tpt, best_waves));
 }
 
 int pb_profile_enable(pb_ctx *c, int enable)

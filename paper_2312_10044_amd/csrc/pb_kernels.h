@@ -12,12 +12,13 @@ constexpr int TILE = 256;       // sources staged in LDS per step (== TPB)
 constexpr int NGEO = 7;         // cx, cy, cz, nx, ny, nz, area
 constexpr int GEO_RED = 6;      // bad, 6*volume, sum cx, sum cy, sum cz, sum area
 constexpr int MAX_RESTART = 64;
+constexpr int PADN = 512;       // collocation arrays are padded to a multiple of this
 
 // Device-side collocation geometry, SoA: array k at g + k * npad.
 struct Geo {
     const double *g;
     int64_t n;      // triangles
-    int64_t npad;   // n rounded up to a multiple of TILE
+    int64_t npad;   // n rounded up to a multiple of PADN
 };
 
 struct PairParams {
@@ -35,28 +36,35 @@ struct Sweep {
     int tiles_per_chunk;
 };
 
-Sweep plan_sweep(int64_t n_targets, int64_t n_sources, int target_waves);
+// tpt = targets per thread (blocks cover TPB * tpt targets).
+Sweep plan_sweep(int64_t n_targets, int64_t n_sources, int target_waves, int tpt = 1);
 
 // geometry + per-block partial reductions (GEO_RED columns x nblk)
 int geometry_blocks(int64_t n_tri);
 void launch_geometry(hipStream_t s, int64_t n_vert, int64_t n_tri, const double *vert,
                      const int32_t *tri, double *g, int64_t npad, double *part, int nblk);
 
-// Packed source stream: 8 values per source (x, y, z, w, mx, my, mz, 0).
+// Packed source stream: 8 values per source (x, y, z, w, mx, my, mz, pad).
 // mode 0 (forward): w = a_j psi_j, m = a_j phi_j n_j.
 // mode 1 (transpose): w = l1_j, m = l2_j n_j.
+// mode 2 (FP32 forward, reduced form): w = (1-1/eps) a psi, m = 3 a phi n,
+//        pad = a psi / eps.
 void launch_pack_f64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode);
 void launch_pack_f32(hipStream_t s, const Geo &geo, const double *x, float *src, int mode,
-                     double cx, double cy, double cz);
+                     double cx, double cy, double cz, double eps);
 
 // Pair sweep of the matvec: part[(o * n_chunks + c) * npad + i], o in {0,1}.
 void launch_pairs_f64(hipStream_t s, const Geo &geo, const double *src, const Sweep &sw,
                       const PairParams &pp, int transpose, double *part);
 void launch_pairs_f32(hipStream_t s, const Geo &geo, const float *src, const Sweep &sw,
                       const PairParams &pp, int transpose, double *part);
-// y = diag * x - (1/4pi) sum_c part  (times a_i when transposed)
+// FP32 forward sweep (mode-2 stream), tpt in {1, 2} targets per thread.
+void launch_pairs_f32_fwd(hipStream_t s, const Geo &geo, const float *src, const Sweep &sw,
+                          const PairParams &pp, int tpt, double *part);
+// y = diag * x - (1/4pi) [scale1 * sum_c part0; sum_c part1]  (times a_i when transposed)
 void launch_matvec_finish(hipStream_t s, const Geo &geo, const double *part, int n_chunks,
-                          const double *x, double alpha, double beta, int transpose, double *y);
+                          const double *x, double alpha, double beta, int transpose,
+                          double scale1, double *y);
 
 // Source terms b = [S1; S2].
 void launch_source(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,

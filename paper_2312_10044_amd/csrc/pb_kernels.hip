@@ -186,7 +186,7 @@ template <typename T>
 __global__ __launch_bounds__(TPB) void k_pack(const double *__restrict__ g, int64_t n,
                                               int64_t npad, const double *__restrict__ x,
                                               Src8<T> *__restrict__ src, int mode, double cx,
-                                              double cy, double cz)
+                                              double cy, double cz, double eps)
 {
     const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (j >= npad)
@@ -195,12 +195,18 @@ __global__ __launch_bounds__(TPB) void k_pack(const double *__restrict__ g, int6
     if (j < n) {
         const double a = g[6 * npad + j];
         double w, f;
+        double pad = 0.0;
         if (mode == 0) {
             w = a * x[n + j];   // a_j psi_j
             f = a * x[j];       // a_j phi_j
-        } else {
+        } else if (mode == 1) {
             w = x[j];           // l1_j
             f = x[n + j];       // l2_j
+        } else {
+            const double ap = a * x[n + j];
+            w = (1.0 - 1.0 / eps) * ap;   // w1
+            pad = ap / eps;               // w2
+            f = 3.0 * a * x[j];
         }
         s.x = T(g[j] - cx);
         s.y = T(g[npad + j] - cy);
@@ -209,13 +215,14 @@ __global__ __launch_bounds__(TPB) void k_pack(const double *__restrict__ g, int6
         s.mx = T(f * g[3 * npad + j]);
         s.my = T(f * g[4 * npad + j]);
         s.mz = T(f * g[5 * npad + j]);
+        s.pad = T(pad);
     } else {
         s.x = T(FAR_SRC - cx);
         s.y = T(0.0);
         s.z = T(0.0);
         s.w = s.mx = s.my = s.mz = T(0.0);
+        s.pad = T(0.0);
     }
-    s.pad = T(0.0);
     src[j] = s;
 }
 
@@ -289,12 +296,122 @@ __global__ __launch_bounds__(TPB) void k_pairs(const Src8<T> *__restrict__ src,
     part[(int64_t)(sw.n_chunks + chunk) * npad + i] = TRANS ? P : Q;
 }
 
+// FP32 forward sweep in reduced form.  Stream entries (mode 2):
+//   (x, y, z, w1 = (1 - 1/eps) a psi, 3 a phi n, w2 = a psi / eps),
+// targets keep n_i and n_i/3 in registers.  With md3 = 3 (a phi n_j).d,
+// b = (tm1 + 1 - 1/eps)/3 and h3 = tm1/r^2 + kappa^2 e/3:
+//   row 1 / eps: sum_j [-(e-1)/r w2 + b md3 u]
+//   row 2:       sum_j u [tm1 (n_i/3).(3 a phi n_j) - c_x (md3 h3 + w1 - tm1 w2)]
+// which is the same algebra as the generic kernel with two multiplies
+// folded into the stream (36 VALU operations per pair).  TPT targets per
+// thread share every LDS read.
+struct CoefF32 {
+    float kappa, kexp, c13, k23;
+};
+
+template <int TPT, int DSLOT>
+__device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&tg)[TPT][9],
+                                          const CoefF32 &cf, float (&P)[TPT], float (&Q)[TPT])
+{
+#pragma unroll 2
+    for (int jj = 0; jj < TILE; ++jj) {
+        const Src8<float> s = sh[jj];
+#pragma unroll
+        for (int t = 0; t < TPT; ++t) {
+            const float dx = tg[t][0] - s.x, dy = tg[t][1] - s.y, dz = tg[t][2] - s.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            float ir = __builtin_amdgcn_rsqf(r2);
+            if (DSLOT == t)
+                ir = (jj == (int)threadIdx.x) ? 0.f : ir;   // j = i omitted
+            const float ir2 = ir * ir;
+            const float u = ir2 * ir;
+            const float r = r2 * ir;
+            const float kr = cf.kappa * r;
+            const float e = __builtin_amdgcn_exp2f(cf.kexp * r);
+            const float em1 = e - 1.f;
+            const float tm1 = fmaf(kr, e, em1);
+            const float cxd = tg[t][3] * dx + tg[t][4] * dy + tg[t][5] * dz;
+            const float md3 = s.mx * dx + s.my * dy + s.mz * dz;
+            const float nm = tg[t][6] * s.mx + tg[t][7] * s.my + tg[t][8] * s.mz;
+            const float b = fmaf(tm1, 0.333333343f, cf.c13);
+            P[t] = fmaf(-em1, ir * s.pad, P[t]);
+            P[t] = fmaf(b * md3, u, P[t]);
+            const float h3 = fmaf(tm1, ir2, cf.k23 * e);
+            const float cqw = fmaf(-tm1, s.pad, s.w);
+            const float inner = fmaf(md3, h3, cqw);
+            Q[t] = fmaf(u, fmaf(-cxd, inner, tm1 * nm), Q[t]);
+        }
+    }
+}
+
+template <int TPT>
+__global__ __launch_bounds__(TPB) void k_pairs_f32_fwd(const Src8<float> *__restrict__ src,
+                                                       const double *__restrict__ g, int64_t npad,
+                                                       Sweep sw, PairParams pp,
+                                                       double *__restrict__ part)
+{
+    __shared__ Src8<float> sh[TILE];
+    const int b = blockIdx.x;
+    const int chunk = b % sw.n_chunks;
+    const int tb = b / sw.n_chunks;
+    float tg[TPT][9];
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+        const int64_t i = ((int64_t)tb * TPT + t) * TPB + threadIdx.x;
+        tg[t][0] = float(g[i] - pp.cx);
+        tg[t][1] = float(g[npad + i] - pp.cy);
+        tg[t][2] = float(g[2 * npad + i] - pp.cz);
+        const double nx = g[3 * npad + i], ny = g[4 * npad + i], nz = g[5 * npad + i];
+        tg[t][3] = float(nx);
+        tg[t][4] = float(ny);
+        tg[t][5] = float(nz);
+        tg[t][6] = float(nx / 3.0);
+        tg[t][7] = float(ny / 3.0);
+        tg[t][8] = float(nz / 3.0);
+    }
+    CoefF32 cf;
+    cf.kappa = float(pp.kappa);
+    cf.kexp = float(-pp.kappa * 1.4426950408889634074);
+    cf.c13 = float((1.0 - 1.0 / pp.eps) / 3.0);
+    cf.k23 = float(pp.kappa * pp.kappa / 3.0);
+    Acc<float> aP[TPT], aQ[TPT];
+    const int t0 = chunk * sw.tiles_per_chunk;
+    const int t1 = min(sw.n_tiles, t0 + sw.tiles_per_chunk);
+    for (int t = t0; t < t1; ++t) {
+        __syncthreads();
+        sh[threadIdx.x] = src[(int64_t)t * TILE + threadIdx.x];
+        __syncthreads();
+        float P[TPT], Q[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k)
+            P[k] = Q[k] = 0.f;
+        const int ds = t - tb * TPT;   // slot whose target lies in this tile
+        if (ds == 0)
+            sweep_f32<TPT, 0>(sh, tg, cf, P, Q);
+        else if (TPT > 1 && ds == 1)
+            sweep_f32<TPT, 1>(sh, tg, cf, P, Q);
+        else
+            sweep_f32<TPT, -1>(sh, tg, cf, P, Q);
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            aP[k].add(P[k]);
+            aQ[k].add(Q[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        const int64_t i = ((int64_t)tb * TPT + k) * TPB + threadIdx.x;
+        part[(int64_t)chunk * npad + i] = aP[k].value();
+        part[(int64_t)(sw.n_chunks + chunk) * npad + i] = aQ[k].value();
+    }
+}
+
 __global__ __launch_bounds__(TPB) void k_matvec_finish(const double *__restrict__ part,
                                                        int n_chunks, int64_t npad, int64_t n,
                                                        const double *__restrict__ area,
                                                        const double *__restrict__ x,
                                                        double alpha, double beta, int trans,
-                                                       double *__restrict__ y)
+                                                       double scale1, double *__restrict__ y)
 {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (i >= n)
@@ -305,7 +422,7 @@ __global__ __launch_bounds__(TPB) void k_matvec_finish(const double *__restrict_
         s2 += part[(int64_t)(n_chunks + c) * npad + i];
     }
     const double sc = trans ? area[i] * INV_4PI : INV_4PI;
-    y[i] = alpha * x[i] - sc * s1;
+    y[i] = alpha * x[i] - sc * scale1 * s1;
     y[n + i] = beta * x[n + i] - sc * s2;
 }
 
@@ -651,10 +768,11 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); 
 
 // ---- host-side launchers ------------------------------------------------------
 
-Sweep plan_sweep(int64_t n_targets, int64_t n_sources, int target_waves)
+Sweep plan_sweep(int64_t n_targets, int64_t n_sources, int target_waves, int tpt)
 {
     Sweep s;
-    s.n_tblocks = (int)((n_targets + TPB - 1) / TPB);
+    const int64_t per_block = (int64_t)TPB * tpt;
+    s.n_tblocks = (int)((n_targets + per_block - 1) / per_block);
     s.n_tiles = (int)((n_sources + TILE - 1) / TILE);
     if (s.n_tiles < 1)
         s.n_tiles = 1;
@@ -691,14 +809,28 @@ void launch_geometry(hipStream_t s, int64_t n_vert, int64_t n_tri, const double 
 void launch_pack_f64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode)
 {
     hipLaunchKernelGGL(k_pack<double>, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
-                       geo.npad, x, reinterpret_cast<Src8<double> *>(src), mode, 0.0, 0.0, 0.0);
+                       geo.npad, x, reinterpret_cast<Src8<double> *>(src), mode, 0.0, 0.0, 0.0,
+                       1.0);
 }
 
 void launch_pack_f32(hipStream_t s, const Geo &geo, const double *x, float *src, int mode,
-                     double cx, double cy, double cz)
+                     double cx, double cy, double cz, double eps)
 {
     hipLaunchKernelGGL(k_pack<float>, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
-                       geo.npad, x, reinterpret_cast<Src8<float> *>(src), mode, cx, cy, cz);
+                       geo.npad, x, reinterpret_cast<Src8<float> *>(src), mode, cx, cy, cz, eps);
+}
+
+void launch_pairs_f32_fwd(hipStream_t s, const Geo &geo, const float *src, const Sweep &sw,
+                          const PairParams &pp, int tpt, double *part)
+{
+    const dim3 grid(sw.n_tblocks * sw.n_chunks);
+    const auto *p = reinterpret_cast<const Src8<float> *>(src);
+    if (tpt == 2)
+        hipLaunchKernelGGL(k_pairs_f32_fwd<2>, grid, dim3(TPB), 0, s, p, geo.g, geo.npad, sw, pp,
+                           part);
+    else
+        hipLaunchKernelGGL(k_pairs_f32_fwd<1>, grid, dim3(TPB), 0, s, p, geo.g, geo.npad, sw, pp,
+                           part);
 }
 
 void launch_pairs_f64(hipStream_t s, const Geo &geo, const double *src, const Sweep &sw,
@@ -730,10 +862,11 @@ void launch_pairs_f32(hipStream_t s, const Geo &geo, const float *src, const Swe
 }
 
 void launch_matvec_finish(hipStream_t s, const Geo &geo, const double *part, int n_chunks,
-                          const double *x, double alpha, double beta, int transpose, double *y)
+                          const double *x, double alpha, double beta, int transpose,
+                          double scale1, double *y)
 {
     hipLaunchKernelGGL(k_matvec_finish, dim3(blocks_for(geo.n)), dim3(TPB), 0, s, part, n_chunks,
-                       geo.npad, geo.n, geo.g + 6 * geo.npad, x, alpha, beta, transpose, y);
+                       geo.npad, geo.n, geo.g + 6 * geo.npad, x, alpha, beta, transpose, scale1, y);
 }
 
 void launch_source(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,

@@ -83,6 +83,10 @@ _PROTOS = {
                          ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
     "pb_forces_dev": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp,
                              ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
+    "pb_set_sweep_config": (_int, [_vp, _int, _int]),
+    "pb_get_sweep_config": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
+    "pb_autotune": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params),
+                           ctypes.POINTER(_int), ctypes.POINTER(_int)]),
     "pb_profile_enable": (_int, [_vp, _int]),
     "pb_profile_reset": (_int, [_vp]),
     "pb_profile_read": (_int, [_vp, _int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
@@ -312,6 +316,24 @@ class Context:
                                           _dev(dE_dpos, "float64"), _dev(dE_dq, "float64"),
                                           ctypes.byref(info)))
         return Info.of(info)
+
+    # -- launch configuration --------------------------------------------------
+    def set_sweep_config(self, targets_per_thread: int = 0, target_waves: int = 0):
+        self._check(self._L.pb_set_sweep_config(self._h, int(targets_per_thread),
+                                                int(target_waves)))
+
+    def get_sweep_config(self):
+        a, b = _int(), _int()
+        self._check(self._L.pb_get_sweep_config(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
+    def pb_autotune(self, verts, tris, params: Params):
+        s, keep = self._surface(verts, tris)
+        a, b = _int(), _int()
+        p = params.c()
+        self._check(self._L.pb_autotune(self._h, ctypes.byref(s), ctypes.byref(p),
+                                        ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
 
     # -- kernel timing hook ------------------------------------------------------
     def profile_enable(self, on: bool = True):
