@@ -107,6 +107,8 @@ def main():
         return ctx.pb_solve_dev(tv, tt, tp, tq, params, phi, dphi)
 
     base = dict(eps_in=w.eps_in, eps_out=w.eps_out, kappa=w.kappa, restart=10, max_iter=2000)
+    tuned = ctx.pb_autotune(w.verts, w.tris, Params(**base))
+    _log(f"bench: autotuned FP32 sweep: targets/thread={tuned[0]} target_waves={tuned[1]}")
     ref = solve(Params(tol=1e-12, precision=PB_FP64, **base))
     e_ref = ref.e_solv
     _log(f"bench: FP64 reference E={e_ref:.10f} (tol 1e-12, {ref.iters} iterations)")
@@ -197,6 +199,7 @@ def main():
             "tol": params.tol,
             "inner_tol": params.inner_tol if prec == PB_FP32_IR else None,
             "gmres_restart": 10,
+            "fp32_sweep": {"targets_per_thread": tuned[0], "target_waves": tuned[1]},
         },
         "time_to_solution_s": ms_step / 1e3,
         "e_solv": infos[-1].e_solv,

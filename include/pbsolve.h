@@ -78,7 +78,9 @@ typedef struct {
     int32_t max_iter;           /* cap on Arnoldi steps (FP64) / outer refinements x inner cap (IR) */
     int32_t precision;          /* PB_FP64 or PB_FP32_IR */
     int32_t max_refine;         /* IR: cap on refinement steps */
-    double inner_tol;           /* IR: relative tolerance of each inner FP32 GMRES solve */
+    double inner_tol;           /* IR: relative tolerance of each inner FP32 GMRES solve;
+                                   values below 1e-6 (beyond what FP32 pair arithmetic
+                                   resolves) are raised to 1e-6 */
 } pb_params;
 
 typedef struct {

@@ -42,8 +42,8 @@ def test_forces_fp32_ir_close_to_fp64(pb):
     w = synth.star_protein(freq=12, r0=10.0, n_charges=300, seed=41)
     i64, p64, q64 = ctx.pb_forces(w.verts, w.tris, w.pos, w.q, m.Params(tol=1e-12))
     i32, p32, q32 = ctx.pb_forces(w.verts, w.tris, w.pos, w.q,
-                                  m.Params(tol=1e-8, precision=m.PB_FP32_IR, inner_tol=3e-9))
-    assert i32.status == m.PB_OK
+                                  m.Params(tol=1e-8, precision=m.PB_FP32_IR, inner_tol=1e-4))
+    assert i32.status == m.PB_OK and i32.refinements >= 2
     assert np.abs(p32 - p64).max() <= 1e-5 * np.abs(p64).max()
     assert np.abs(q32 - q64).max() <= 1e-5 * np.abs(q64).max()
 
