@@ -72,6 +72,11 @@ def main():
     ap.add_argument("--workload", choices=["star81920", "star327680"], default="star81920")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--mode", choices=["solve", "matvec", "copy"], default="solve",
+                    help="solve: the benchmark; matvec: only --steps matvecs of --precision "
+                         "(for counter runs); copy: a device copy of --copy-mib MiB (the "
+                         "reference kernel that calibrates FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -88,6 +93,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read": n * 8, "bytes_written": n * 8,
+                          "launches": max(1, args.steps)}), flush=True)
+        return
     if args.workload == "star81920":
         w = synth.star_protein()
     else:
@@ -109,6 +124,24 @@ def main():
     base = dict(eps_in=w.eps_in, eps_out=w.eps_out, kappa=w.kappa, restart=10, max_iter=2000)
     tuned = ctx.pb_autotune(w.verts, w.tris, Params(**base))
     _log(f"bench: autotuned FP32 sweep: targets/thread={tuned[0]} target_waves={tuned[1]}")
+    if args.mode == "matvec":
+        prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
+        x = torch.from_numpy(np.random.default_rng(0).normal(size=2 * N)).to(dev)
+        y = torch.empty_like(x)
+        ctx.profile_reset()
+        ctx.profile_enable(True)
+        for _ in range(args.steps):
+            ctx.pb_matvec_dev(tv, tt, x, y, Params(**base), precision=prec)
+        torch.cuda.synchronize()
+        kid = pbs.PB_KERNEL_PAIRS_FP32 if prec == PB_FP32_IR else pbs.PB_KERNEL_PAIRS_FP64
+        n_l, ms_l, pr_l = ctx.profile_read(kid)
+        print(json.dumps({"mode": "matvec", "precision": args.precision, "n_tri": N,
+                          "launches": n_l, "avg_ms": ms_l / n_l,
+                          "pairs_per_launch": pr_l / n_l,
+                          "tflops_algorithmic": FLOP_PER_PAIR * pr_l / (ms_l * 1e-3) / 1e12,
+                          "fp32_sweep": list(tuned)}), flush=True)
+        ctx.close()
+        return
     ref = solve(Params(tol=1e-12, precision=PB_FP64, **base))
     e_ref = ref.e_solv
     _log(f"bench: FP64 reference E={e_ref:.10f} (tol 1e-12, {ref.iters} iterations)")

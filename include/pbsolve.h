@@ -169,11 +169,11 @@ int pb_forces_dev(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_ve
 /* The FP32 forward pair sweep (the hot loop of PB_FP32_IR solves) keeps
  * `targets_per_thread` collocation points (1 or 2) in registers per thread
  * and splits the source range into chunks so that one launch holds about
- * `target_waves` wavefronts.  0 leaves a value unchanged.  Defaults: 1, 8192. */
+ * `target_waves` wavefronts.  0 leaves a value unchanged.  Defaults: 1, 32768. */
 int pb_set_sweep_config(pb_ctx *ctx, int targets_per_thread, int target_waves);
 int pb_get_sweep_config(pb_ctx *ctx, int *targets_per_thread, int *target_waves);
 /* Time every candidate configuration (targets_per_thread in {1, 2} x
- * target_waves in {4096, 8192, 16384, 32768}) on this surface with HIP events
+ * target_waves in {8192, 16384, 32768, 65536, 131072}) on this surface with HIP events
  * and keep the fastest in the context.  best_* may be NULL. */
 int pb_autotune(pb_ctx *ctx, const pb_surface *s, const pb_params *p, int *best_tpt,
                 int *best_waves);

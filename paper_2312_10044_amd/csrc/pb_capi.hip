@@ -22,7 +22,7 @@ namespace {
 
 constexpr double C_UNITS = 332.0716;      // e_c^2/A -> kcal/mol (Sec. 2.1)
 constexpr double TWO_PI = 6.283185307179586476925286766559;
-constexpr int TARGET_WAVES = 8192;        // ~8 waves per SIMD on 256 CUs x 4 SIMDs
+constexpr int TARGET_WAVES = 32768;       // ~32 waves per SIMD over a launch (256 CUs x 4 SIMDs)
 
 struct DevBuf {
     void *p = nullptr;
@@ -58,7 +58,7 @@ struct pb_ctx {
     double prof_pairs[PB_KERNEL_COUNT] = {};
     // launch configuration of the FP32 forward sweep (pb_set_sweep_config / pb_autotune)
     int f32_tpt = 1;
-    int f32_waves = TARGET_WAVES;
+    int f32_waves = 32768;
     // current geometry
     Geo g{};
     double center[3] = {0.0, 0.0, 0.0};
@@ -529,7 +529,7 @@ int check_charges_inside(pb_ctx *c, const pb_params *p, int64_t nc, const double
     }
     LAUNCHCHK();
     launch_charge_finish(c->stream, as<double>(c->chg_part), sw.n_chunks, nc, ncpad, nullptr,
-                         as<double>(c->chg_per), nullptr);
+                         1.0, as<double>(c->chg_per), nullptr);
     LAUNCHCHK();
     std::vector<double> omega(nc);
     HIPCHK(hipMemcpyAsync(omega.data(), c->chg_per.p, sizeof(double) * nc, hipMemcpyDeviceToHost,
@@ -563,12 +563,13 @@ int energy_dev(pb_ctx *c, const pb_params *p, int64_t nc, const double *d_pos, c
     }
     LAUNCHCHK();
     const int slot = HSMALL - 2;
-    launch_charge_finish(c->stream, as<double>(c->chg_part), sw.n_chunks, nc, ncpad, d_q, nullptr,
-                         as<double>(c->small) + slot);
+    TRY(ensure(c, c->chg_per, sizeof(double) * ncpad));
+    // E = (1/2) sum_k q_k phi_reac(y_k) in kcal/mol; the pair sums carry 4 pi K
+    launch_charge_finish(c->stream, as<double>(c->chg_part), sw.n_chunks, nc, ncpad, d_q,
+                         0.5 * C_UNITS, as<double>(c->chg_per), as<double>(c->small) + slot);
     LAUNCHCHK();
     TRY(fetch_small(c, slot, 1));
-    // E = (1/2) sum_k q_k phi_reac(y_k) in kcal/mol; the pair sums carry 4 pi K
-    *e_out = 0.5 * C_UNITS * c->hsmall[slot];
+    *e_out = c->hsmall[slot];
     return PB_OK;
 }
 
@@ -732,9 +733,10 @@ int forces_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
     }
     LAUNCHCHK();
     const int slot = HSMALL - 3;
+    TRY(ensure(c, c->chg_per, sizeof(double) * ncpad));
     launch_force_finish(c->stream, as<double>(c->chg_part), sw.n_chunks, nc, ncpad, d_q,
                         0.5 * C_UNITS, 1.0 / (4.0 * M_PI * p->eps_in), d_dpos, d_dq,
-                        as<double>(c->small) + slot);
+                        as<double>(c->chg_per), as<double>(c->small) + slot);
     LAUNCHCHK();
     TRY(fetch_small(c, slot, 1));
     fill_info(info, c->hsmall[slot], fs, &as_);
@@ -1158,7 +1160,7 @@ static int pb_autotune_impl(pb_ctx *c, const pb_surface *s, const pb_params *p, 
     launch_fill(c->stream, as<double>(c->io_x), 1.0, n2);
     LAUNCHCHK();
     static const int tpts[] = {1, 2};
-    static const int waves[] = {4096, 8192, 16384, 32768};
+    static const int waves[] = {8192, 16384, 32768, 65536, 131072};
     hipEvent_t e0 = pool_event(c, 0), e1 = pool_event(c, 1);
     if (!e0 || !e1)
         return fail(c, PB_ERR_HIP, "hipEventCreate failed");

@@ -75,10 +75,10 @@ void launch_source(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,
 void launch_charge_pairs(hipStream_t s, const Geo &geo, const double *src, int64_t nc,
                          const double *pos, const Sweep &sw, const PairParams &pp, int mode,
                          double *part, int64_t ncpad);
-// out[0] = sum_k q_k sum_c part[c][k] (q may be NULL: then sum over k of the
-// per-charge values is not formed and per[k] receives sum_c part[c][k]).
+// per[k] = sum_c part[c][k]; when q and out are given, also
+// out[0] = scale * sum_k q_k per[k] (fixed order).
 void launch_charge_finish(hipStream_t s, const double *part, int n_chunks, int64_t nc,
-                          int64_t ncpad, const double *q, double *per, double *out);
+                          int64_t ncpad, const double *q, double scale, double *per, double *out);
 
 // Adjoint right-hand side w' = B'^T q (2n).
 void launch_adjoint_rhs(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,
@@ -88,9 +88,10 @@ void launch_adjoint_rhs(hipStream_t s, const Geo &geo, int64_t nc, const double 
 void launch_force_pairs(hipStream_t s, const double *fwd, const double *adj, int64_t nc,
                         const double *pos, const Sweep &sw, const PairParams &pp, double *part,
                         int64_t ncpad);
+// per [nc] is scratch (receives P'_k); out[0] = E.
 void launch_force_finish(hipStream_t s, const double *part, int n_chunks, int64_t nc,
                          int64_t ncpad, const double *q, double half_cu, double inv4pi_eps_in,
-                         double *dpos, double *dq, double *out);
+                         double *dpos, double *dq, double *per, double *out);
 
 // ---- deterministic BLAS-1 on device vectors of length n ----------------
 int dot_blocks(int64_t n);

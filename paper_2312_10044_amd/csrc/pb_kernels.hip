@@ -29,6 +29,7 @@
 //   row 2: sum_j [-(e-1)/r w_j - g3 (m_j.d) u]
 // with the target area a_i applied once per row.
 #include "pb_kernels.h"
+#include "pb_device.h"
 
 #include <cmath>
 
@@ -36,83 +37,7 @@ namespace pbk {
 
 namespace {
 
-constexpr double INV_4PI = 0.079577471545947667884441881686257181;
-constexpr double FAR_SRC = 2.0e6;   // padded sources, weight 0
-constexpr double FAR_TGT = -2.0e6;  // padded targets, never written back
-
-template <typename T>
-struct alignas(8 * sizeof(T)) Src8 {
-    T x, y, z, w, mx, my, mz, pad;
-};
-
-// ---- precision-specific primitives ---------------------------------------
-
-__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
-
-// exp(-t) for t >= 0
-__device__ __forceinline__ float exp_neg(float t)
-{
-    return __builtin_amdgcn_exp2f(t * -1.44269504088896340736f);
-}
-__device__ __forceinline__ double exp_neg(double t) { return exp(-t); }
-
-template <typename T>
-struct Coef {
-    T eps, epsm1, ieps, iepsm1, kappa, k2;
-    __device__ explicit Coef(const PairParams &p)
-        : eps(T(p.eps)), epsm1(T(p.eps - 1.0)), ieps(T(1.0 / p.eps)),
-          iepsm1(T(1.0 / p.eps - 1.0)), kappa(T(p.kappa)), k2(T(p.kappa * p.kappa)) {}
-};
-
-// Sum of per-tile partials.  FP64: plain.  FP32: compensated (Knuth's
-// TwoSum), so the error of the long sum stays at the size of one tile.
-template <typename T>
-struct Acc;
-template <>
-struct Acc<double> {
-    double s = 0.0;
-    __device__ void add(double v) { s += v; }
-    __device__ double value() const { return s; }
-};
-template <>
-struct Acc<float> {
-    float hi = 0.f, lo = 0.f;
-    __device__ void add(float v)
-    {
-        float s = hi + v;
-        float bb = s - hi;
-        float err = (hi - (s - bb)) + (v - bb);
-        hi = s;
-        lo += err;
-    }
-    __device__ double value() const { return double(hi) + double(lo); }
-};
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// Sum over the block; valid in thread 0.  sh holds blockDim.x/64 doubles.
-__device__ __forceinline__ double block_sum(double v, double *sh)
-{
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0)
-        sh[wid] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k)
-            r += sh[k];
-    }
-    return r;
-}
+using namespace dev;
 
 // ---- geometry -------------------------------------------------------------
 
@@ -228,40 +153,6 @@ __global__ __launch_bounds__(TPB) void k_pack(const double *__restrict__ g, int6
 
 // ---- matvec pair sweep ----------------------------------------------------
 
-template <typename T, bool TRANS, bool DIAG>
-__device__ __forceinline__ void sweep_tile(const Src8<T> *sh, int self, T xi, T yi, T zi,
-                                           T nxi, T nyi, T nzi, const Coef<T> &cf, T &accP,
-                                           T &accQ)
-{
-#pragma unroll 2
-    for (int jj = 0; jj < TILE; ++jj) {
-        const Src8<T> s = sh[jj];
-        const T dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        T ir = rsqrt_t(r2);
-        if (DIAG)
-            ir = (jj == self) ? T(0) : ir;   // j = i omitted (eqs. eqbim_5/6)
-        const T ir2 = ir * ir;
-        const T u = ir2 * ir;
-        const T kr = cf.kappa * (r2 * ir);
-        const T e = exp_neg(kr);
-        const T em1 = e - T(1);
-        const T tm1 = fma(kr, e, em1);
-        const T cxd = nxi * dx + nyi * dy + nzi * dz;
-        const T md = s.mx * dx + s.my * dy + s.mz * dz;
-        const T nm = nxi * s.mx + nyi * s.my + nzi * s.mz;
-        const T g2 = fma(cf.eps, tm1, cf.epsm1);
-        const T g3 = fma(cf.ieps, tm1, cf.iepsm1);
-        const T h = fma(tm1, T(3) * ir2, cf.k2 * e);
-        const T cP = TRANS ? -g3 : g2;
-        const T cQ = TRANS ? g2 : -g3;
-        accP = fma(-em1, ir * s.w, accP);
-        accP = fma(cP * md, u, accP);
-        const T inner = fma(md, h, cQ * s.w);
-        accQ = fma(u, fma(-cxd, inner, tm1 * nm), accQ);
-    }
-}
-
 template <typename T, bool TRANS>
 __global__ __launch_bounds__(TPB) void k_pairs(const Src8<T> *__restrict__ src,
                                                const double *__restrict__ g, int64_t npad,
@@ -294,54 +185,6 @@ __global__ __launch_bounds__(TPB) void k_pairs(const Src8<T> *__restrict__ src,
     const double P = aP.value(), Q = aQ.value();
     part[(int64_t)chunk * npad + i] = TRANS ? Q : P;
     part[(int64_t)(sw.n_chunks + chunk) * npad + i] = TRANS ? P : Q;
-}
-
-// FP32 forward sweep in reduced form.  Stream entries (mode 2):
-//   (x, y, z, w1 = (1 - 1/eps) a psi, 3 a phi n, w2 = a psi / eps),
-// targets keep n_i and n_i/3 in registers.  With md3 = 3 (a phi n_j).d,
-// b = (tm1 + 1 - 1/eps)/3 and h3 = tm1/r^2 + kappa^2 e/3:
-//   row 1 / eps: sum_j [-(e-1)/r w2 + b md3 u]
-//   row 2:       sum_j u [tm1 (n_i/3).(3 a phi n_j) - c_x (md3 h3 + w1 - tm1 w2)]
-// which is the same algebra as the generic kernel with two multiplies
-// folded into the stream (36 VALU operations per pair).  TPT targets per
-// thread share every LDS read.
-struct CoefF32 {
-    float kappa, kexp, c13, k23;
-};
-
-template <int TPT, int DSLOT>
-__device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&tg)[TPT][9],
-                                          const CoefF32 &cf, float (&P)[TPT], float (&Q)[TPT])
-{
-#pragma unroll 2
-    for (int jj = 0; jj < TILE; ++jj) {
-        const Src8<float> s = sh[jj];
-#pragma unroll
-        for (int t = 0; t < TPT; ++t) {
-            const float dx = tg[t][0] - s.x, dy = tg[t][1] - s.y, dz = tg[t][2] - s.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            float ir = __builtin_amdgcn_rsqf(r2);
-            if (DSLOT == t)
-                ir = (jj == (int)threadIdx.x) ? 0.f : ir;   // j = i omitted
-            const float ir2 = ir * ir;
-            const float u = ir2 * ir;
-            const float r = r2 * ir;
-            const float kr = cf.kappa * r;
-            const float e = __builtin_amdgcn_exp2f(cf.kexp * r);
-            const float em1 = e - 1.f;
-            const float tm1 = fmaf(kr, e, em1);
-            const float cxd = tg[t][3] * dx + tg[t][4] * dy + tg[t][5] * dz;
-            const float md3 = s.mx * dx + s.my * dy + s.mz * dz;
-            const float nm = tg[t][6] * s.mx + tg[t][7] * s.my + tg[t][8] * s.mz;
-            const float b = fmaf(tm1, 0.333333343f, cf.c13);
-            P[t] = fmaf(-em1, ir * s.pad, P[t]);
-            P[t] = fmaf(b * md3, u, P[t]);
-            const float h3 = fmaf(tm1, ir2, cf.k23 * e);
-            const float cqw = fmaf(-tm1, s.pad, s.w);
-            const float inner = fmaf(md3, h3, cqw);
-            Q[t] = fmaf(u, fmaf(-cxd, inner, tm1 * nm), Q[t]);
-        }
-    }
 }
 
 template <int TPT>
@@ -508,26 +351,32 @@ __global__ __launch_bounds__(TPB) void k_charge_pairs(const Src8<double> *__rest
     part[(int64_t)chunk * ncpad + k] = acc.value();
 }
 
-__global__ __launch_bounds__(TPB) void k_charge_finish(const double *__restrict__ part,
-                                                       int n_chunks, int64_t nc, int64_t ncpad,
-                                                       const double *__restrict__ q,
-                                                       double *__restrict__ per,
-                                                       double *__restrict__ out)
+// Per-charge sums over the source chunks (one thread per charge), then
+// out[0] = sum_k q_k per[k] in a fixed order by a single block.
+__global__ __launch_bounds__(TPB) void k_charge_sum(const double *__restrict__ part,
+                                                    int n_chunks, int64_t nc, int64_t ncpad,
+                                                    double *__restrict__ per)
+{
+    const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (k >= nc)
+        return;
+    double s = 0.0;
+    for (int c = 0; c < n_chunks; ++c)
+        s += part[(int64_t)c * ncpad + k];
+    per[k] = s;
+}
+
+__global__ __launch_bounds__(TPB) void k_weighted_total(const double *__restrict__ per,
+                                                        const double *__restrict__ q, int64_t nc,
+                                                        double scale, double *__restrict__ out)
 {
     __shared__ double sh[TPB / 64];
     double tot = 0.0;
-    for (int64_t k = threadIdx.x; k < nc; k += TPB) {
-        double s = 0.0;
-        for (int c = 0; c < n_chunks; ++c)
-            s += part[(int64_t)c * ncpad + k];
-        if (per)
-            per[k] = s;
-        if (q)
-            tot += q[k] * s;
-    }
+    for (int64_t k = threadIdx.x; k < nc; k += TPB)
+        tot += q[k] * per[k];
     const double r = block_sum(tot, sh);
-    if (threadIdx.x == 0 && out)
-        out[0] = r;
+    if (threadIdx.x == 0)
+        out[0] = scale * r;
 }
 
 // ---- adjoint (forces) --------------------------------------------------------
@@ -642,33 +491,29 @@ __global__ __launch_bounds__(TPB) void k_force_pairs(const Src8<double> *__restr
 }
 
 // dE/dq_k = (c_u/2) [P'_k + c_k/(4 pi eps_in)],
-// dE/dy_k = (c_u/2) q_k [grad P'_k + grad c_k/(4 pi eps_in)], out[0] = E.
+// dE/dy_k = (c_u/2) q_k [grad P'_k + grad c_k/(4 pi eps_in)]; per[k] = P'_k.
 __global__ __launch_bounds__(TPB) void k_force_finish(const double *__restrict__ part,
                                                       int n_chunks, int64_t nc, int64_t ncpad,
                                                       const double *__restrict__ q,
                                                       double half_cu, double inv4pi_eps_in,
                                                       double *__restrict__ dpos,
                                                       double *__restrict__ dq,
-                                                      double *__restrict__ out)
+                                                      double *__restrict__ per)
 {
-    __shared__ double sh[TPB / 64];
-    double tot = 0.0;
-    for (int64_t k = threadIdx.x; k < nc; k += TPB) {
-        double v[8];
-        for (int o = 0; o < 8; ++o) {
-            double s = 0.0;
-            for (int c = 0; c < n_chunks; ++c)
-                s += part[((int64_t)o * n_chunks + c) * ncpad + k];
-            v[o] = s;
-        }
-        tot += q[k] * v[0];
-        dq[k] = half_cu * (v[0] + inv4pi_eps_in * v[4]);
-        for (int d = 0; d < 3; ++d)
-            dpos[3 * k + d] = half_cu * q[k] * (v[1 + d] + inv4pi_eps_in * v[5 + d]);
+    const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (k >= nc)
+        return;
+    double v[8];
+    for (int o = 0; o < 8; ++o) {
+        double s = 0.0;
+        for (int c = 0; c < n_chunks; ++c)
+            s += part[((int64_t)o * n_chunks + c) * ncpad + k];
+        v[o] = s;
     }
-    const double r = block_sum(tot, sh);
-    if (threadIdx.x == 0)
-        out[0] = half_cu * r;
+    per[k] = v[0];
+    dq[k] = half_cu * (v[0] + inv4pi_eps_in * v[4]);
+    for (int d = 0; d < 3; ++d)
+        dpos[3 * k + d] = half_cu * q[k] * (v[1 + d] + inv4pi_eps_in * v[5 + d]);
 }
 
 // ---- BLAS-1 ----------------------------------------------------------------
@@ -892,10 +737,12 @@ void launch_charge_pairs(hipStream_t s, const Geo &geo, const double *src, int64
 }
 
 void launch_charge_finish(hipStream_t s, const double *part, int n_chunks, int64_t nc,
-                          int64_t ncpad, const double *q, double *per, double *out)
+                          int64_t ncpad, const double *q, double scale, double *per, double *out)
 {
-    hipLaunchKernelGGL(k_charge_finish, dim3(1), dim3(TPB), 0, s, part, n_chunks, nc, ncpad, q,
-                       per, out);
+    hipLaunchKernelGGL(k_charge_sum, dim3(blocks_for(nc)), dim3(TPB), 0, s, part, n_chunks, nc,
+                       ncpad, per);
+    if (q && out)
+        hipLaunchKernelGGL(k_weighted_total, dim3(1), dim3(TPB), 0, s, per, q, nc, scale, out);
 }
 
 void launch_adjoint_rhs(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,
@@ -916,10 +763,11 @@ void launch_force_pairs(hipStream_t s, const double *fwd, const double *adj, int
 
 void launch_force_finish(hipStream_t s, const double *part, int n_chunks, int64_t nc,
                          int64_t ncpad, const double *q, double half_cu, double inv4pi_eps_in,
-                         double *dpos, double *dq, double *out)
+                         double *dpos, double *dq, double *per, double *out)
 {
-    hipLaunchKernelGGL(k_force_finish, dim3(1), dim3(TPB), 0, s, part, n_chunks, nc, ncpad, q,
-                       half_cu, inv4pi_eps_in, dpos, dq, out);
+    hipLaunchKernelGGL(k_force_finish, dim3(blocks_for(nc)), dim3(TPB), 0, s, part, n_chunks, nc,
+                       ncpad, q, half_cu, inv4pi_eps_in, dpos, dq, per);
+    hipLaunchKernelGGL(k_weighted_total, dim3(1), dim3(TPB), 0, s, per, q, nc, half_cu, out);
 }
 
 int dot_blocks(int64_t n)
