@@ -77,6 +77,8 @@ def main():
                          "(for counter runs); copy: a device copy of --copy-mib MiB (the "
                          "reference kernel that calibrates FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the FP32 sweep configurations first and use the fastest")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -122,8 +124,12 @@ def main():
         return ctx.pb_solve_dev(tv, tt, tp, tq, params, phi, dphi)
 
     base = dict(eps_in=w.eps_in, eps_out=w.eps_out, kappa=w.kappa, restart=10, max_iter=2000)
-    tuned = ctx.pb_autotune(w.verts, w.tris, Params(**base))
-    _log(f"bench: autotuned FP32 sweep: targets/thread={tuned[0]} target_waves={tuned[1]}")
+    if args.autotune:
+        tuned = ctx.pb_autotune(w.verts, w.tris, Params(**base))
+    else:
+        tuned = ctx.get_sweep_config()
+    _log(f"bench: FP32 sweep: targets/thread={tuned[0]} target_waves={tuned[1]} "
+         f"({'autotuned' if args.autotune else 'library default'})")
     if args.mode == "matvec":
         prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
         x = torch.from_numpy(np.random.default_rng(0).normal(size=2 * N)).to(dev)

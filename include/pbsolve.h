@@ -147,6 +147,24 @@ int pb_solve(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_par
 int pb_forces(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_params *p,
               double *dE_dpos, double *dE_dq, pb_info *info);
 
+/* Batched solves of n_sys independent systems (surfaces[b], charges[b]) with
+ * shared parameters, in shared launches: one persistent pair sweep over a
+ * work list of (system, target block, source range) items per matvec, GMRES
+ * in lockstep with per-system state, masks and convergence tests on the
+ * device, one restart cycle captured in a hipGraph and replayed until all
+ * systems converge.  Restart residuals are FP64; with PB_FP32_IR the Arnoldi
+ * matvecs are FP32 (each cycle is a refinement step).  restart <= 32.
+ *   e_solv  [n_sys]                     kcal/mol
+ *   dE_dpos [sum_b n_b][3], dE_dq [sum_b n_b] (charges concatenated in
+ *           system order) or both NULL: when given, the adjoint solves and
+ *           gradient sweeps run as well (same meaning as pb_forces).
+ *   info    [n_sys] or NULL; seconds is the wall time of the whole call.
+ * Returns PB_OK, PB_NOT_CONVERGED (some system hit max_iter) or an error;
+ * error messages name the offending system. */
+int pb_solve_batch(pb_ctx *ctx, int32_t n_sys, const pb_surface *surfaces,
+                   const pb_charges *charges, const pb_params *p, double *e_solv,
+                   double *dE_dpos, double *dE_dq, pb_info *info);
+
 /* ---- device-pointer entry points -------------------------------------- */
 /* Same operations; every array argument is device memory laid out as above.
  * Validation of the surface runs on the device. */

@@ -40,11 +40,13 @@ def lib():
         L.orc_matvec.argtypes = [i64, p, p, p, d, d, p, p, i64, p, p, p, p, p]
         L.orc_matvec_t.argtypes = [i64, p, p, p, d, d, p, p, i64, p, p, p, p, p]
         L.orc_assemble.argtypes = [i64, p, p, p, d, d, p]
+        L.orc_assemble_subset.argtypes = [i64, p, p, p, d, d, i64, p, p]
         L.orc_source.argtypes = [i64, p, p, i64, p, p, d, i64, p, p, p]
         L.orc_reaction.argtypes = [i64, p, p, p, d, d, p, p, i64, p, p, p]
         L.orc_adjoint_rhs.argtypes = [i64, p, p, p, d, d, i64, p, p, p, p]
         L.orc_source_adjoint.argtypes = [i64, p, p, d, p, p, i64, p, p, p]
         for f in (L.orc_green, L.orc_kernels, L.orc_matvec, L.orc_matvec_t, L.orc_assemble,
+                  L.orc_assemble_subset,
                   L.orc_source, L.orc_reaction, L.orc_adjoint_rhs, L.orc_source_adjoint):
             f.restype = None
         _lib = L

@@ -201,6 +201,31 @@ void orc_assemble(int64_t n, const double *cen, const double *nrm, const double 
     }
 }
 
+/* Rows and columns idx[0..m) of the dense matrix, as a 2m x 2m block in
+ * the same [phi; psi] block layout (the leaf blocks of the preconditioner of
+ * Sec. 2.2.4). */
+void orc_assemble_subset(int64_t n, const double *cen, const double *nrm, const double *area,
+                         double eps, double kappa, int64_t m, const int64_t *idx, double *B)
+{
+    (void)n;
+    int64_t m2 = 2 * m;
+    for (int64_t r = 0; r < m; ++r) {
+        int64_t i = idx[r];
+        for (int64_t q = 0; q < m; ++q) {
+            int64_t j = idx[q];
+            double K[4] = {0.0, 0.0, 0.0, 0.0};
+            if (j != i)
+                kernels(cen + 3 * i, nrm + 3 * i, cen + 3 * j, nrm + 3 * j, eps, kappa, K);
+            B[r * m2 + q] = -K[1] * area[j];
+            B[r * m2 + m + q] = -K[0] * area[j];
+            B[(m + r) * m2 + q] = -K[3] * area[j];
+            B[(m + r) * m2 + m + q] = -K[2] * area[j];
+        }
+        B[r * m2 + r] += 0.5 * (1.0 + eps);
+        B[(m + r) * m2 + m + r] += 0.5 * (1.0 + 1.0 / eps);
+    }
+}
+
 /* Source terms, eq. source_terms:
  *   S1_i = (1/eps_in) sum_k q_k G0(x_i, y_k)
  *   S2_i = (1/eps_in) sum_k q_k dG0(x_i, y_k)/dnu_x */

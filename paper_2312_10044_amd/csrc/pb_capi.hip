@@ -3,6 +3,7 @@
 // holds the (m+1) x m Hessenberg matrix of GMRES and its Givens rotations,
 // fed by one small device-to-host copy per Arnoldi step.
 #include "../../include/pbsolve.h"
+#include "pb_ctx.h"
 #include "pb_kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -19,164 +20,6 @@
 using namespace pbk;
 
 namespace {
-
-constexpr double C_UNITS = 332.0716;      // e_c^2/A -> kcal/mol (Sec. 2.1)
-constexpr double TWO_PI = 6.283185307179586476925286766559;
-constexpr int TARGET_WAVES = 32768;       // ~32 waves per SIMD over a launch (256 CUs x 4 SIMDs)
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t cap = 0;
-};
-
-struct ErrorState {
-    std::string msg = "no error";
-};
-
-}  // namespace
-
-struct pb_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    ErrorState err;
-    // device scratch
-    DevBuf geo, geo_part, src64, src32, part, vec, V, small, dpart, chg_part, chg_per;
-    DevBuf in_vert, in_tri, in_pos, in_q, io_x, io_y;
-    double *hsmall = nullptr;   // pinned host staging, HSMALL doubles
-    // kernel timing (pb_profile_*)
-    struct Mark {
-        hipEvent_t a, b;
-        int kind;
-        double pairs;
-    };
-    bool prof_on = false;
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<Mark> marks;
-    int64_t prof_launches[PB_KERNEL_COUNT] = {};
-    double prof_ms[PB_KERNEL_COUNT] = {};
-    double prof_pairs[PB_KERNEL_COUNT] = {};
-    // launch configuration of the FP32 forward sweep (pb_set_sweep_config / pb_autotune)
-    int f32_tpt = 1;
-    int f32_waves = 32768;
-    // current geometry
-    Geo g{};
-    double center[3] = {0.0, 0.0, 0.0};
-    double volume = 0.0, area_sum = 0.0;
-};
-
-namespace {
-
-constexpr int HSMALL = 4 * (MAX_RESTART + 2) + 64;
-
-int fail(pb_ctx *c, int code, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    if (c)
-        c->err.msg = buf;
-    return code;
-}
-
-#define HIPCHK(expr)                                                                      \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return fail(c, e_ == hipErrorOutOfMemory ? PB_ERR_OOM : PB_ERR_HIP,           \
-                        "%s failed: %s", #expr, hipGetErrorString(e_));                   \
-    } while (0)
-
-#define LAUNCHCHK()                                                                       \
-    do {                                                                                  \
-        hipError_t e_ = hipGetLastError();                                                \
-        if (e_ != hipSuccess)                                                             \
-            return fail(c, PB_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
-    } while (0)
-
-#define TRY(expr)              \
-    do {                       \
-        int rc_ = (expr);      \
-        if (rc_ < 0)           \
-            return rc_;        \
-    } while (0)
-
-int ensure(pb_ctx *c, DevBuf &b, size_t bytes)
-{
-    if (bytes <= b.cap)
-        return PB_OK;
-    if (b.p) {
-        HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(hipFree(b.p));
-    }
-    b.p = nullptr;
-    b.cap = 0;
-    hipError_t e = hipMalloc(&b.p, bytes);
-    if (e != hipSuccess) {
-        b.p = nullptr;
-        (void)hipGetLastError();
-        return fail(c, PB_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
-    }
-    b.cap = bytes;
-    return PB_OK;
-}
-
-template <typename T>
-T *as(DevBuf &b) { return static_cast<T *>(b.p); }
-
-int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
-
-hipEvent_t pool_event(pb_ctx *c, size_t idx)
-{
-    while (c->ev_pool.size() <= idx) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess)
-            return nullptr;
-        c->ev_pool.push_back(e);
-    }
-    return c->ev_pool[idx];
-}
-
-// Brackets one kernel launch with events when profiling is on.
-struct ProfScope {
-    pb_ctx *c;
-    int kind;
-    double pairs;
-    hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(pb_ctx *c_, int kind_, double pairs_) : c(c_), kind(kind_), pairs(pairs_)
-    {
-        if (!c->prof_on)
-            return;
-        const size_t k = 2 * c->marks.size();
-        a = pool_event(c, k);
-        b = pool_event(c, k + 1);
-        if (a && b)
-            (void)hipEventRecord(a, c->stream);
-    }
-    ~ProfScope()
-    {
-        if (a && b) {
-            (void)hipEventRecord(b, c->stream);
-            c->marks.push_back({a, b, kind, pairs});
-        }
-    }
-};
-
-// Collect elapsed times of recorded launches (the stream must have drained).
-void prof_collect(pb_ctx *c)
-{
-    for (const auto &m : c->marks) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
-            c->prof_ms[m.kind] += ms;
-            c->prof_launches[m.kind] += 1;
-            c->prof_pairs[m.kind] += m.pairs;
-        }
-    }
-    c->marks.clear();
-}
 
 int check_params(pb_ctx *c, const pb_params *p, bool solving)
 {
@@ -222,7 +65,7 @@ int setup_geometry(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_ver
     const int nblk = geometry_blocks(npad);
     TRY(ensure(c, c->geo_part, sizeof(double) * GEO_RED * nblk));
     TRY(ensure(c, c->small, sizeof(double) * HSMALL));
-    launch_geometry(c->stream, n_vert, n_tri, d_vert, d_tri, as<double>(c->geo), npad,
+    launch_geometry(c->stream, n_vert, n_tri, d_vert, d_tri, as<double>(c->geo), npad, npad,
                     as<double>(c->geo_part), nblk);
     LAUNCHCHK();
     launch_reduce_cols(c->stream, as<double>(c->geo_part), nblk, GEO_RED, as<double>(c->small));
@@ -1205,6 +1048,30 @@ int pb_autotune(pb_ctx *c, const pb_surface *s, const pb_params *p, int *best_tp
                 int *best_waves)
 {
     return leave(c, pb_autotune_impl(c, s, p, best_tpt, best_waves));
+}
+
+static int pb_solve_batch_impl(pb_ctx *c, int32_t n_sys, const pb_surface *surf,
+                               const pb_charges *chg, const pb_params *p, double *e_solv,
+                               double *dE_dpos, double *dE_dq, pb_info *info)
+{
+    const double t0 = now_s();
+    TRY(enter(c));
+    TRY(check_params(c, p, true));
+    const int want = (dE_dpos != nullptr) || (dE_dq != nullptr);
+    const int st = batch_solve(c, n_sys, surf, chg, p, want, e_solv, dE_dpos, dE_dq, info);
+    if (info && st >= 0) {
+        const double dt = now_s() - t0;
+        for (int b = 0; b < n_sys; ++b)
+            info[b].seconds = dt;
+    }
+    return st;
+}
+
+int pb_solve_batch(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
+                   const pb_params *p, double *e_solv, double *dE_dpos, double *dE_dq,
+                   pb_info *info)
+{
+    return leave(c, pb_solve_batch_impl(c, n_sys, surf, chg, p, e_solv, dE_dpos, dE_dq, info));
 }
 
 int pb_profile_enable(pb_ctx *c, int enable)

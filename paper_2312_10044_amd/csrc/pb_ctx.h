@@ -1,0 +1,186 @@
+// Internal host-side state of the library: the context (pb_ctx), its device
+// buffers, error and timing helpers.  Shared by pb_capi.hip and pb_batch.hip.
+#pragma once
+
+#include "../../include/pbsolve.h"
+#include "pb_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+namespace pbk {
+
+constexpr double C_UNITS = 332.0716;      // e_c^2/A -> kcal/mol (Sec. 2.1)
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+constexpr int TARGET_WAVES = 32768;       // ~32 waves per SIMD over a launch (256 CUs x 4 SIMDs)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct ErrorState {
+    std::string msg = "no error";
+};
+
+}  // namespace pbk
+
+struct pb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    pbk::ErrorState err;
+    // device scratch
+    pbk::DevBuf geo, geo_part, src64, src32, part, vec, V, small, dpart, chg_part, chg_per;
+    pbk::DevBuf in_vert, in_tri, in_pos, in_q, io_x, io_y;
+    double *hsmall = nullptr;   // pinned host staging, HSMALL doubles
+    // kernel timing (pb_profile_*)
+    struct Mark {
+        hipEvent_t a, b;
+        int kind;
+        double pairs;
+    };
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<Mark> marks;
+    int64_t prof_launches[PB_KERNEL_COUNT] = {};
+    double prof_ms[PB_KERNEL_COUNT] = {};
+    double prof_pairs[PB_KERNEL_COUNT] = {};
+    // launch configuration of the FP32 forward sweep (pb_set_sweep_config / pb_autotune)
+    int f32_tpt = 1;
+    int f32_waves = 32768;
+    // current geometry
+    pbk::Geo g{};
+    double center[3] = {0.0, 0.0, 0.0};
+    double volume = 0.0, area_sum = 0.0;
+    // batched solves (pb_solve_batch)
+    pbk::DevBuf b_geo, b_desc, b_map, b_items, b_src, b_part, b_vec, b_V, b_state, b_red, b_chg;
+    hipGraphExec_t b_graph = nullptr;
+    uint64_t b_graph_key = 0;
+};
+
+namespace pbk {
+
+constexpr int HSMALL = 4 * (MAX_RESTART + 2) + 64;
+
+inline int fail(pb_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err.msg = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(c, e_ == hipErrorOutOfMemory ? PB_ERR_OOM : PB_ERR_HIP,           \
+                        "%s failed: %s", #expr, hipGetErrorString(e_));                   \
+    } while (0)
+
+#define LAUNCHCHK()                                                                       \
+    do {                                                                                  \
+        hipError_t e_ = hipGetLastError();                                                \
+        if (e_ != hipSuccess)                                                             \
+            return fail(c, PB_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+#define TRY(expr)              \
+    do {                       \
+        int rc_ = (expr);      \
+        if (rc_ < 0)           \
+            return rc_;        \
+    } while (0)
+
+inline int ensure(pb_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (bytes <= b.cap)
+        return PB_OK;
+    if (b.p) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipFree(b.p));
+    }
+    b.p = nullptr;
+    b.cap = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, PB_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    b.cap = bytes;
+    return PB_OK;
+}
+
+template <typename T>
+inline T *as(DevBuf &b) { return static_cast<T *>(b.p); }
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+inline hipEvent_t pool_event(pb_ctx *c, size_t idx)
+{
+    while (c->ev_pool.size() <= idx) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[idx];
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+    pb_ctx *c;
+    int kind;
+    double pairs;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(pb_ctx *c_, int kind_, double pairs_) : c(c_), kind(kind_), pairs(pairs_)
+    {
+        if (!c->prof_on)
+            return;
+        const size_t k = 2 * c->marks.size();
+        a = pool_event(c, k);
+        b = pool_event(c, k + 1);
+        if (a && b)
+            (void)hipEventRecord(a, c->stream);
+    }
+    ~ProfScope()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, c->stream);
+            c->marks.push_back({a, b, kind, pairs});
+        }
+    }
+};
+
+// Collect elapsed times of recorded launches (the stream must have drained).
+inline void prof_collect(pb_ctx *c)
+{
+    for (const auto &m : c->marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+            c->prof_ms[m.kind] += ms;
+            c->prof_launches[m.kind] += 1;
+            c->prof_pairs[m.kind] += m.pairs;
+        }
+    }
+    c->marks.clear();
+}
+
+
+// Batched solve of independent systems (pb_batch.hip).
+int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
+                const pb_params *p, int want_forces, double *e_solv, double *dE_dpos,
+                double *dE_dq, pb_info *info);
+
+}  // namespace pbk

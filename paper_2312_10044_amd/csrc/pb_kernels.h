@@ -41,8 +41,10 @@ Sweep plan_sweep(int64_t n_targets, int64_t n_sources, int target_waves, int tpt
 
 // geometry + per-block partial reductions (GEO_RED columns x nblk)
 int geometry_blocks(int64_t n_tri);
+// Writes entries [0, npad) of the seven arrays g + k * ld.
 void launch_geometry(hipStream_t s, int64_t n_vert, int64_t n_tri, const double *vert,
-                     const int32_t *tri, double *g, int64_t npad, double *part, int nblk);
+                     const int32_t *tri, double *g, int64_t npad, int64_t ld, double *part,
+                     int nblk);
 
 // Packed source stream: 8 values per source (x, y, z, w, mx, my, mz, pad).
 // mode 0 (forward): w = a_j psi_j, m = a_j phi_j n_j.

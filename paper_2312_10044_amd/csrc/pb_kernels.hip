@@ -45,7 +45,7 @@ __global__ __launch_bounds__(TPB) void k_geometry(int64_t n_vert, int64_t n_tri,
                                                   const double *__restrict__ vert,
                                                   const int32_t *__restrict__ tri,
                                                   double *__restrict__ g, int64_t npad,
-                                                  double *__restrict__ part, int nblk)
+                                                  int64_t ld, double *__restrict__ part, int nblk)
 {
 #pragma clang fp contract(off)
     __shared__ double sh[TPB / 64];
@@ -91,12 +91,12 @@ __global__ __launch_bounds__(TPB) void k_geometry(int64_t n_vert, int64_t n_tri,
             }
         }
         g[i] = c[0];
-        g[npad + i] = c[1];
-        g[2 * npad + i] = c[2];
-        g[3 * npad + i] = nn[0];
-        g[4 * npad + i] = nn[1];
-        g[5 * npad + i] = nn[2];
-        g[6 * npad + i] = a;
+        g[ld + i] = c[1];
+        g[2 * ld + i] = c[2];
+        g[3 * ld + i] = nn[0];
+        g[4 * ld + i] = nn[1];
+        g[5 * ld + i] = nn[2];
+        g[6 * ld + i] = a;
     }
     for (int k = 0; k < GEO_RED; ++k) {
         const double s = block_sum(acc[k], sh);
@@ -645,10 +645,11 @@ int geometry_blocks(int64_t n_tri)
 }
 
 void launch_geometry(hipStream_t s, int64_t n_vert, int64_t n_tri, const double *vert,
-                     const int32_t *tri, double *g, int64_t npad, double *part, int nblk)
+                     const int32_t *tri, double *g, int64_t npad, int64_t ld, double *part,
+                     int nblk)
 {
     hipLaunchKernelGGL(k_geometry, dim3(nblk), dim3(TPB), 0, s, n_vert, n_tri, vert, tri, g, npad,
-                       part, nblk);
+                       ld, part, nblk);
 }
 
 void launch_pack_f64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode)

@@ -83,6 +83,9 @@ _PROTOS = {
                          ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
     "pb_forces_dev": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp,
                              ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
+    "pb_solve_batch": (_int, [_vp, ctypes.c_int32, ctypes.POINTER(_Surface),
+                              ctypes.POINTER(_Charges), ctypes.POINTER(_Params), _vp, _vp, _vp,
+                              ctypes.POINTER(_Info)]),
     "pb_set_sweep_config": (_int, [_vp, _int, _int]),
     "pb_get_sweep_config": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
     "pb_autotune": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params),
@@ -286,6 +289,32 @@ class Context:
                                       _vp(gpos.ctypes.data), _vp(gq.ctypes.data),
                                       ctypes.byref(info)))
         return Info.of(info), gpos, gq
+
+    def pb_solve_batch(self, systems, params: Params, forces: bool = False):
+        """systems: list of (verts, tris, pos, q).  Returns (e [n_sys], infos,
+        dE_dpos [sum n_b, 3] or None, dE_dq [sum n_b] or None)."""
+        n = len(systems)
+        surfs = (_Surface * n)()
+        chgs = (_Charges * n)()
+        keep = []
+        nct = 0
+        for b, (v, t, pos, q) in enumerate(systems):
+            s, k1 = self._surface(v, t)
+            c, k2 = self._charges(pos, q)
+            surfs[b] = s
+            chgs[b] = c
+            keep += [k1, k2]
+            nct += c.n
+        e = np.empty(n)
+        infos = (_Info * n)()
+        gpos = np.empty((nct, 3)) if forces else None
+        gq = np.empty(nct) if forces else None
+        p = params.c()
+        self._check(self._L.pb_solve_batch(self._h, n, surfs, chgs, ctypes.byref(p),
+                                           _vp(e.ctypes.data),
+                                           _vp(gpos.ctypes.data) if forces else None,
+                                           _vp(gq.ctypes.data) if forces else None, infos))
+        return e, [Info.of(infos[b]) for b in range(n)], gpos, gq
 
     # -- device-pointer entry points (torch tensors) --------------------------
     def pb_matvec_dev(self, verts, tris, x, y, params: Params, transpose=False,

@@ -1,0 +1,95 @@
+"""Batched solves (pb_solve_batch) against one-at-a-time solves and the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dsbi
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2312_10044_amd as m
+    ctx = m.Context(0)
+    yield m, ctx
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    """Six systems of uneven size: 320 to 3,920 triangles, 7 to 300 charges."""
+    specs = [(4, 6.0, 7, 51), (14, 12.0, 300, 52), (6, 8.0, 40, 53), (9, 9.0, 120, 54),
+             (5, 7.0, 20, 55), (12, 10.0, 257, 56)]
+    out = []
+    for f, r0, nc, seed in specs:
+        w = synth.star_protein(freq=f, r0=r0, n_charges=nc, seed=seed)
+        out.append((w.verts, w.tris, w.pos, w.q))
+    return out
+
+
+def test_batch_fp64_matches_single_solves_and_oracle(pb, small_batch):
+    m, ctx = pb
+    _say(f"batch fp64: {len(small_batch)} systems")
+    P = m.Params(tol=1e-12)
+    e, infos, _g, _q = ctx.pb_solve_batch(small_batch, P)
+    for b, (v, t, pos, q) in enumerate(small_batch):
+        info, _p, _d = ctx.pb_solve(v, t, pos, q, P)
+        assert infos[b].status == m.PB_OK
+        assert abs(e[b] - info.e_solv) <= 1e-10 * abs(info.e_solv), b
+    v, t, pos, q = small_batch[2]
+    ref = dsbi.solve(v, t, pos, q, tol=1e-12)
+    assert abs(e[2] - ref.e_solv) <= 1e-10 * abs(ref.e_solv)
+
+
+def test_batch_forces_match_single_forces(pb, small_batch):
+    m, ctx = pb
+    P = m.Params(tol=1e-12)
+    e, infos, gpos, gq = ctx.pb_solve_batch(small_batch, P, forces=True)
+    off = 0
+    for b, (v, t, pos, q) in enumerate(small_batch):
+        info, dpos, dq = ctx.pb_forces(v, t, pos, q, P)
+        n = q.shape[0]
+        assert infos[b].adjoint_iters > 0
+        assert abs(e[b] - info.e_solv) <= 1e-10 * abs(info.e_solv)
+        assert np.abs(gpos[off:off + n] - dpos).max() <= 1e-8 * np.abs(dpos).max()
+        assert np.abs(gq[off:off + n] - dq).max() <= 1e-8 * np.abs(dq).max()
+        off += n
+
+
+def test_batch_fp32_refined_energies(pb, small_batch):
+    m, ctx = pb
+    e64, _i, _g, _q = ctx.pb_solve_batch(small_batch, m.Params(tol=1e-12))
+    e32, infos, _g, _q = ctx.pb_solve_batch(small_batch,
+                                            m.Params(tol=1e-8, precision=m.PB_FP32_IR))
+    for b in range(len(small_batch)):
+        assert infos[b].status == m.PB_OK and infos[b].matvecs_fp32 > 0
+        assert abs(e32[b] - e64[b]) <= 1e-6 * abs(e64[b])
+
+
+def test_batch_rejects_a_bad_system_by_name(pb, small_batch):
+    m, ctx = pb
+    bad = list(small_batch)
+    v, t, pos, q = bad[3]
+    t = t.copy()
+    t[0, 0] = v.shape[0] + 5
+    bad[3] = (v, t, pos, q)
+    with pytest.raises(m.PbError) as e:
+        ctx.pb_solve_batch(bad, m.Params())
+    assert e.value.status == m.PB_ERR_GEOMETRY and "system 3" in e.value.message
+    e2, infos, _g, _q = ctx.pb_solve_batch(small_batch[:2], m.Params(tol=1e-8))
+    assert all(i.status == m.PB_OK for i in infos)
+
+
+def test_batch_single_system_and_repeat_determinism(pb, small_batch):
+    m, ctx = pb
+    one = small_batch[1:2]
+    a, _i, _g, _q = ctx.pb_solve_batch(one, m.Params(tol=1e-10))
+    b, _i, _g, _q = ctx.pb_solve_batch(one, m.Params(tol=1e-10))
+    assert a[0] == b[0]
