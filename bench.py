@@ -4,7 +4,8 @@
 One step = one whole solve of the star-shaped synthetic protein surface
 (81,920 triangles, 2,000 interior charges): collocation geometry, source
 terms, restarted GMRES(10) with the refined-FP32 matvec (FP64 outer
-residuals, FP64 Arnoldi), solvation energy.  Inputs are device-resident
+residuals, FP64 Arnoldi) and the block-diagonal leaf preconditioner (leaf
+size 16 by default), solvation energy.  Inputs are device-resident
 before the timed region starts.  The solve tolerance is the loosest of a
 fixed ladder whose energy is within 1e-6 (relative) of an FP64 solve at
 tol 1e-12; the ladder search runs before timing.
@@ -77,6 +78,8 @@ def main():
                          "(for counter runs); copy: a device copy of --copy-mib MiB (the "
                          "reference kernel that calibrates FETCH_SIZE/WRITE_SIZE)")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--precond-leaf", type=int, default=16,
+                    help="leaf size of the block-diagonal preconditioner (0 = none)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the FP32 sweep configurations first and use the fastest")
     args = ap.parse_args()
@@ -152,23 +155,37 @@ def main():
     e_ref = ref.e_solv
     _log(f"bench: FP64 reference E={e_ref:.10f} (tol 1e-12, {ref.iters} iterations)")
 
-    def pick(precision):
+    def pick(precision, leaf):
         for tol in TOL_LADDER:
             if precision == PB_FP32_IR:
                 p = Params(tol=tol, precision=PB_FP32_IR, inner_tol=0.3 * tol,
-                           max_refine=20, **base)
+                           max_refine=20, precond_leaf=leaf, **base)
             else:
-                p = Params(tol=tol, precision=PB_FP64, **base)
+                p = Params(tol=tol, precision=PB_FP64, precond_leaf=leaf, **base)
             info = solve(p)
             err = abs(info.e_solv - e_ref) / abs(e_ref)
-            _log(f"bench: precision={precision} tol={tol:g} E err={err:.2e} iters={info.iters} "
-                 f"t={info.seconds:.3f}s")
+            _log(f"bench: precision={precision} leaf={leaf} tol={tol:g} E err={err:.2e} "
+                 f"iters={info.iters} t={info.seconds:.3f}s")
             if err <= E_TARGET and info.status == 0:
                 return p, err
         raise RuntimeError("no tolerance on the ladder reached the energy target")
 
+    def timed_once(p):
+        solve(p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = solve(p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return {"time_to_solution_s": dt, "tol": p.tol, "iters": info.iters,
+                "matvecs_fp32": info.matvecs_fp32, "matvecs_fp64": info.matvecs_fp64,
+                "e_rel_err": abs(info.e_solv - e_ref) / abs(e_ref),
+                "gpairs_per_s": (info.matvecs_fp32 + info.matvecs_fp64) * float(N) * (N - 1)
+                / dt / 1e9}
+
     prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
-    params, err_pick = pick(prec)
+    leaf = args.precond_leaf
+    params, err_pick = pick(prec, leaf)
 
     for _ in range(args.warmup):
         solve(params)
@@ -203,18 +220,16 @@ def main():
             kernel_rows[name] = {"launches": n_l, "avg_ms": ms_l / n_l,
                                  "gpairs_per_s": pr_l / (ms_l * 1e-3) / 1e9}
 
-    fp64_path = None
-    if not args.no_fp64_compare and prec == PB_FP32_IR:
-        p64, err64 = pick(PB_FP64)
-        solve(p64)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        i64 = solve(p64)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t0
-        fp64_path = {"time_to_solution_s": t64, "tol": p64.tol, "e_rel_err": err64,
-                     "iters": i64.iters,
-                     "gpairs_per_s": i64.matvecs_fp64 * pairs_per_mv / t64 / 1e9}
+    compare = {}
+    if not args.no_fp64_compare:
+        variants = [("fp64_same_preconditioner", PB_FP64, leaf),
+                    ("fp32_ir_no_preconditioner", PB_FP32_IR, 0),
+                    ("fp64_no_preconditioner", PB_FP64, 0)]
+        for name, pr, lf in variants:
+            if pr == prec and lf == leaf:
+                continue
+            pv, _e = pick(pr, lf)
+            compare[name] = timed_once(pv)
 
     out = {
         "metric": "BIE matvec G-pair-interactions/s; time to E_solv at 1e-6 rel. error",
@@ -235,6 +250,7 @@ def main():
             "n_tri": N,
             "n_charges": w.n_charges,
             "precision": "FP32 matvec + FP64 refinement" if prec == PB_FP32_IR else "FP64",
+            "precond_leaf": leaf,
             "tol": params.tol,
             "inner_tol": params.inner_tol if prec == PB_FP32_IR else None,
             "gmres_restart": 10,
@@ -248,7 +264,7 @@ def main():
         "matvecs_fp64": infos[-1].matvecs_fp64,
         "refinements": infos[-1].refinements,
         "kernels": kernel_rows,
-        "fp64_path": fp64_path,
+        "compare": compare,
         "roofline": {
             "bound": "alu",
             "kernel": "k_pairs<float,false>" if prec == PB_FP32_IR else "k_pairs<double,false>",

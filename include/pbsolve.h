@@ -81,6 +81,14 @@ typedef struct {
     double inner_tol;           /* IR: relative tolerance of each inner FP32 GMRES solve;
                                    values below 1e-6 (beyond what FP32 pair arithmetic
                                    resolves) are raised to 1e-6 */
+    int32_t precond_leaf;       /* 0: no preconditioner.  1..32: block-diagonal leaf
+                                   preconditioner of Sec. 2.2.4 with at most this many
+                                   elements per octree leaf; GMRES then runs on the left-
+                                   preconditioned system M^-1 A x = M^-1 b and tol applies
+                                   to its residual |M^-1 (b - A x)| / |M^-1 b| (FP64 path and
+                                   IR inner solves; the IR outer test stays unpreconditioned).
+                                   Not used by pb_solve_batch. */
+    int32_t reserved;           /* set to 0 */
 } pb_params;
 
 typedef struct {
@@ -182,6 +190,17 @@ int pb_forces_dev(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_ve
                   const int32_t *d_tri, int64_t n_charges, const double *d_pos,
                   const double *d_q, const pb_params *p, double *d_dE_dpos, double *d_dE_dq,
                   pb_info *info);
+
+/* ---- preconditioner hooks (tests) ------------------------------------- */
+/* The octree leaves used by the preconditioner for leaf size `leaf` (1..32):
+ * perm [n_tri] lists the elements leaf by leaf, leaf_start [n_tri + 1] (only
+ * the first *n_leaves + 1 entries are written) the leaf boundaries. */
+int pb_precond_leaves(pb_ctx *ctx, const pb_surface *s, int leaf, int32_t *perm,
+                      int32_t *leaf_start, int64_t *n_leaves);
+/* y = M^-1 x (transpose != 0: M^-T x) for the preconditioner that p->precond_leaf
+ * selects; x, y: [2 n_tri]. */
+int pb_precond_apply(pb_ctx *ctx, const pb_surface *s, const pb_params *p, const double *x,
+                     double *y, int transpose);
 
 /* ---- launch configuration and autotuning ------------------------------- */
 /* The FP32 forward pair sweep (the hot loop of PB_FP32_IR solves) keeps

@@ -40,7 +40,10 @@ def leaves(cen: np.ndarray, n0: int):
 
     def split(idx, c, h, depth):
         if idx.shape[0] <= n0 or depth >= MAX_DEPTH:
-            out.append(idx)
+            # at the depth limit (coincident points) the leaf is cut into
+            # consecutive runs of at most n0 points
+            for a in range(0, idx.shape[0], n0):
+                out.append(idx[a:a + n0])
             return
         p = cen[idx]
         octant = ((p[:, 0] >= c[0]).astype(np.int64) + 2 * (p[:, 1] >= c[1]).astype(np.int64)

@@ -39,6 +39,8 @@ int check_params(pb_ctx *c, const pb_params *p, bool solving)
             return fail(c, PB_ERR_ARG, "max_iter must be >= 1");
         if (p->precision != PB_FP64 && p->precision != PB_FP32_IR)
             return fail(c, PB_ERR_ARG, "precision must be PB_FP64 or PB_FP32_IR");
+        if (p->precond_leaf < 0 || p->precond_leaf > PC_MAX_LEAF)
+            return fail(c, PB_ERR_ARG, "precond_leaf must be in [0, %d]", PC_MAX_LEAF);
         if (p->precision == PB_FP32_IR) {
             if (p->max_refine < 1)
                 return fail(c, PB_ERR_ARG, "max_refine must be >= 1");
@@ -54,6 +56,7 @@ int check_params(pb_ctx *c, const pb_params *p, bool solving)
 int setup_geometry(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
                    const int32_t *d_tri)
 {
+    c->pc_leaves = 0;   // a preconditioner belongs to one geometry
     if (n_tri <= 0 || n_vert < 3)
         return fail(c, PB_ERR_ARG, "need n_tri > 0 and n_vert >= 3");
     if (n_tri > (int64_t)1 << 30)
@@ -148,12 +151,134 @@ int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
     return PB_OK;
 }
 
+// ---- block-diagonal leaf preconditioner (Sec. 2.2.4) -------------------------
+
+// Leaves of the octree over the collocation points (Sec. 2.2.3): the root is
+// the cube around the bounding box of the points; a cluster with more than n0
+// points splits into its eight child cubes (octant = (x >= cx) + 2 (y >= cy)
+// + 4 (z >= cz), child centres c +- h/2), empty children are dropped, leaves
+// are listed depth first in octant order, points in increasing index order.
+void build_leaves(const double *x, const double *y, const double *z, int64_t n, int n0,
+                  std::vector<int32_t> &perm, std::vector<int32_t> &start)
+{
+    double lo[3] = {x[0], y[0], z[0]}, hi[3] = {x[0], y[0], z[0]};
+    for (int64_t i = 1; i < n; ++i) {
+        const double p[3] = {x[i], y[i], z[i]};
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], p[k]);
+            hi[k] = std::max(hi[k], p[k]);
+        }
+    }
+    double c0[3], h0 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        c0[k] = 0.5 * (lo[k] + hi[k]);
+        h0 = std::max(h0, 0.5 * (hi[k] - lo[k]));
+    }
+    perm.clear();
+    start.assign(1, 0);
+    std::vector<int32_t> all(n);
+    for (int64_t i = 0; i < n; ++i)
+        all[i] = (int32_t)i;
+    struct Frame {
+        std::vector<int32_t> idx;
+        double c[3], h;
+        int depth;
+    };
+    // explicit stack; children pushed in reverse so they pop in octant order
+    std::vector<Frame> stack;
+    stack.push_back({std::move(all), {c0[0], c0[1], c0[2]}, h0, 0});
+    while (!stack.empty()) {
+        Frame f = std::move(stack.back());
+        stack.pop_back();
+        if ((int64_t)f.idx.size() <= n0 || f.depth >= 40) {
+            // at the depth limit (coincident points) the leaf is cut into
+            // consecutive runs of at most n0 points
+            for (size_t a = 0; a < f.idx.size(); a += (size_t)n0) {
+                const size_t b = std::min(f.idx.size(), a + (size_t)n0);
+                perm.insert(perm.end(), f.idx.begin() + a, f.idx.begin() + b);
+                start.push_back((int32_t)perm.size());
+            }
+            continue;
+        }
+        std::vector<int32_t> sub[8];
+        for (int32_t i : f.idx) {
+            const int o = (x[i] >= f.c[0] ? 1 : 0) + (y[i] >= f.c[1] ? 2 : 0) +
+                          (z[i] >= f.c[2] ? 4 : 0);
+            sub[o].push_back(i);
+        }
+        for (int o = 7; o >= 0; --o) {
+            if (sub[o].empty())
+                continue;
+            Frame ch;
+            ch.idx = std::move(sub[o]);
+            const double hh = 0.5 * f.h;
+            ch.c[0] = f.c[0] + ((o & 1) ? 1.0 : -1.0) * hh;
+            ch.c[1] = f.c[1] + ((o & 2) ? 1.0 : -1.0) * hh;
+            ch.c[2] = f.c[2] + ((o & 4) ? 1.0 : -1.0) * hh;
+            ch.h = hh;
+            ch.depth = f.depth + 1;
+            stack.push_back(std::move(ch));
+        }
+    }
+}
+
+// Leaves of the current geometry and the inverses of their blocks.
+int setup_precond(pb_ctx *c, const pb_params *p)
+{
+    c->pc_leaves = 0;
+    if (p->precond_leaf <= 0)
+        return PB_OK;
+    const Geo &g = c->g;
+    std::vector<double> h(3 * g.n);
+    for (int k = 0; k < 3; ++k)
+        HIPCHK(hipMemcpyAsync(h.data() + k * g.n, g.g + k * g.npad, sizeof(double) * g.n,
+                              hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::vector<int32_t> perm, start;
+    build_leaves(h.data(), h.data() + g.n, h.data() + 2 * g.n, g.n, p->precond_leaf, perm, start);
+    const int64_t L = (int64_t)start.size() - 1;
+    std::vector<int64_t> boff(L + 1, 0);
+    for (int64_t l = 0; l < L; ++l) {
+        const int64_t m2 = 2 * (int64_t)(start[l + 1] - start[l]);
+        boff[l + 1] = boff[l] + m2 * m2;
+    }
+    TRY(ensure(c, c->pc_idx, sizeof(int32_t) * (g.n + L + 1) + sizeof(int64_t) * (L + 2)));
+    TRY(ensure(c, c->pc_inv, sizeof(double) * std::max<int64_t>(boff[L], 1)));
+    int32_t *dperm = as<int32_t>(c->pc_idx);
+    int32_t *dstart = dperm + g.n;
+    int64_t *dboff = reinterpret_cast<int64_t *>(
+        static_cast<char *>(c->pc_idx.p) + round_up(sizeof(int32_t) * (g.n + L + 1), 8));
+    HIPCHK(hipMemcpyAsync(dperm, perm.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(dstart, start.data(), sizeof(int32_t) * (L + 1), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(dboff, boff.data(), sizeof(int64_t) * (L + 1), hipMemcpyHostToDevice,
+                          c->stream));
+    launch_pc_build(c->stream, g, dperm, dstart, dboff, L, p->eps_out / p->eps_in, p->kappa,
+                    as<double>(c->pc_inv));
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(c->stream));   // host vectors go out of scope
+    c->pc_leaves = L;
+    c->pc_perm = dperm;
+    c->pc_start = dstart;
+    c->pc_boff = dboff;
+    return PB_OK;
+}
+
+int pc_apply(pb_ctx *c, int transpose, const double *x, double *y)
+{
+    launch_pc_apply(c->stream, as<double>(c->pc_inv), c->pc_boff, c->pc_perm, c->pc_start,
+                    c->pc_leaves, c->g.n, x, transpose, y);
+    LAUNCHCHK();
+    return PB_OK;
+}
+
 // ---- vectors -------------------------------------------------------------------
 
 struct Vecs {
     int64_t n2 = 0, ld = 0;
     double *x = nullptr, *b = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *t = nullptr;
-    double *lam = nullptr, *aux = nullptr;
+    double *lam = nullptr, *aux = nullptr, *pw = nullptr, *pb = nullptr;
     double *V = nullptr;
 };
 
@@ -161,7 +286,7 @@ int setup_vectors(pb_ctx *c, int m, Vecs &v)
 {
     v.n2 = 2 * c->g.n;
     v.ld = round_up(v.n2, 64);
-    TRY(ensure(c, c->vec, sizeof(double) * 8 * v.ld));
+    TRY(ensure(c, c->vec, sizeof(double) * 10 * v.ld));
     TRY(ensure(c, c->V, sizeof(double) * (m + 1) * v.ld));
     double *base = as<double>(c->vec);
     v.x = base;
@@ -172,6 +297,8 @@ int setup_vectors(pb_ctx *c, int m, Vecs &v)
     v.t = base + 5 * v.ld;
     v.lam = base + 6 * v.ld;
     v.aux = base + 7 * v.ld;
+    v.pw = base + 8 * v.ld;
+    v.pb = base + 9 * v.ld;
     v.V = as<double>(c->V);
     const int nblk = dot_blocks(v.n2);
     TRY(ensure(c, c->dpart, sizeof(double) * (MAX_RESTART + 2) * nblk));
@@ -227,8 +354,17 @@ int gmres(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
     double *small = as<double>(c->small);
     double *h1 = small, *h2 = small + (m + 1), *nb2 = small + 2 * (m + 1);
     double *yv = small + 2 * (m + 1) + 1;
+    // Left preconditioning (Sec. 2.2.4): GMRES on M^-1 A x = M^-1 rhs.
+    const bool pc = c->pc_leaves > 0;
+    const double *prhs = rhs;
+    if (pc) {
+        TRY(pc_apply(c, transpose, rhs, v.pb));
+        prhs = v.pb;
+    }
+    double *rr = pc ? v.pw : v.r;   // (preconditioned) residual
+    double *ww = pc ? v.pw : v.w;   // (preconditioned) new Krylov direction
     double bnorm;
-    TRY(norm_host(c, rhs, n2, &bnorm));
+    TRY(norm_host(c, prhs, n2, &bnorm));
     st = GmresStats();
     if (!std::isfinite(bnorm))
         return fail(c, PB_ERR_GEOMETRY, "non-finite right-hand side");
@@ -249,7 +385,7 @@ int gmres(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
         // r0 = rhs - A x  (r0 = rhs when starting from zero)
         double beta;
         if (zero_start) {
-            HIPCHK(hipMemcpyAsync(v.r, rhs, sizeof(double) * n2, hipMemcpyDeviceToDevice,
+            HIPCHK(hipMemcpyAsync(rr, prhs, sizeof(double) * n2, hipMemcpyDeviceToDevice,
                                   c->stream));
             beta = bnorm;
         } else {
@@ -257,7 +393,9 @@ int gmres(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
             if (precision == PB_FP64) st.mv64++; else st.mv32++;
             launch_sub(c->stream, rhs, v.w, v.r, n2);
             LAUNCHCHK();
-            TRY(norm_host(c, v.r, n2, &beta));
+            if (pc)
+                TRY(pc_apply(c, transpose, v.r, rr));
+            TRY(norm_host(c, rr, n2, &beta));
         }
         zero_start = false;
         if (!std::isfinite(beta))
@@ -278,8 +416,8 @@ int gmres(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
             return PB_OK;
         prev_rel = st.rel;
         // V_0 = r0 / beta
-        TRY(norm2_dev(c, v.r, n2, 2 * (m + 1)));
-        launch_scale_inv_sqrt(c->stream, v.r, nb2, v.V, n2);
+        TRY(norm2_dev(c, rr, n2, 2 * (m + 1)));
+        launch_scale_inv_sqrt(c->stream, rr, nb2, v.V, n2);
         LAUNCHCHK();
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(gv.begin(), gv.end(), 0.0);
@@ -290,21 +428,23 @@ int gmres(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
             TRY(apply(c, p, precision, transpose, vj, v.w));
             st.iters++;
             if (precision == PB_FP64) st.mv64++; else st.mv32++;
+            if (pc)
+                TRY(pc_apply(c, transpose, v.w, ww));
             // CGS pass 1 and 2
-            launch_dots(c->stream, v.V, v.ld, j + 1, v.w, n2, as<double>(c->dpart), nblk);
+            launch_dots(c->stream, v.V, v.ld, j + 1, ww, n2, as<double>(c->dpart), nblk);
             LAUNCHCHK();
             launch_reduce_cols(c->stream, as<double>(c->dpart), nblk, j + 1, h1);
             LAUNCHCHK();
-            launch_sub_basis(c->stream, v.V, v.ld, j + 1, h1, v.w, n2);
+            launch_sub_basis(c->stream, v.V, v.ld, j + 1, h1, ww, n2);
             LAUNCHCHK();
-            launch_dots(c->stream, v.V, v.ld, j + 1, v.w, n2, as<double>(c->dpart), nblk);
+            launch_dots(c->stream, v.V, v.ld, j + 1, ww, n2, as<double>(c->dpart), nblk);
             LAUNCHCHK();
             launch_reduce_cols(c->stream, as<double>(c->dpart), nblk, j + 1, h2);
             LAUNCHCHK();
-            launch_sub_basis(c->stream, v.V, v.ld, j + 1, h2, v.w, n2);
+            launch_sub_basis(c->stream, v.V, v.ld, j + 1, h2, ww, n2);
             LAUNCHCHK();
-            TRY(norm2_dev(c, v.w, n2, 2 * (m + 1)));
-            launch_scale_inv_sqrt(c->stream, v.w, nb2, v.V + (int64_t)(j + 1) * v.ld, n2);
+            TRY(norm2_dev(c, ww, n2, 2 * (m + 1)));
+            launch_scale_inv_sqrt(c->stream, ww, nb2, v.V + (int64_t)(j + 1) * v.ld, n2);
             LAUNCHCHK();
             TRY(fetch_small(c, 0, 2 * (m + 1) + 1));
             const double *hh = c->hsmall;
@@ -493,6 +633,7 @@ int forward_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
     TRY(setup_geometry(c, n_vert, n_tri, d_vert, d_tri));
     TRY(setup_vectors(c, p->restart, v));
     TRY(check_charges_inside(c, p, nc, d_pos, v));
+    TRY(setup_precond(c, p));
     {
         ProfScope ps(c, PB_KERNEL_SOURCE, (double)c->g.n * (double)nc);
         launch_source(c->stream, c->g, nc, d_pos, d_q, p->eps_in, v.b);
@@ -699,7 +840,9 @@ void pb_destroy(pb_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     DevBuf *bufs[] = {&c->geo, &c->geo_part, &c->src64, &c->src32, &c->part, &c->vec,
                       &c->V, &c->small, &c->dpart, &c->chg_part, &c->chg_per, &c->in_vert,
-                      &c->in_tri, &c->in_pos, &c->in_q, &c->io_x, &c->io_y};
+                      &c->in_tri, &c->in_pos, &c->in_q, &c->io_x, &c->io_y, &c->pc_idx,
+                      &c->pc_inv, &c->b_geo, &c->b_desc, &c->b_map, &c->b_items, &c->b_src,
+                      &c->b_part, &c->b_vec, &c->b_V, &c->b_state, &c->b_red, &c->b_chg};
     for (DevBuf *b : bufs)
         if (b->p)
             (void)hipFree(b->p);
@@ -960,6 +1103,69 @@ int pb_forces_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert
 {
     return leave(c, pb_forces_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p,
                                        d_dE_dpos, d_dE_dq, info));
+}
+
+static int pb_precond_leaves_impl(pb_ctx *c, const pb_surface *s, int leaf, int32_t *perm,
+                                  int32_t *leaf_start, int64_t *n_leaves)
+{
+    TRY(enter(c));
+    if (!perm || !leaf_start || !n_leaves)
+        return fail(c, PB_ERR_ARG, "output arrays are NULL");
+    if (leaf < 1 || leaf > PC_MAX_LEAF)
+        return fail(c, PB_ERR_ARG, "leaf must be in [1, %d]", PC_MAX_LEAF);
+    const double *dv;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(setup_geometry(c, s->n_vert, s->n_tri, dv, dt));
+    pb_params p{};
+    p.eps_in = 1.0;
+    p.eps_out = 1.0;
+    p.precond_leaf = leaf;
+    TRY(setup_precond(c, &p));
+    const int64_t L = c->pc_leaves;
+    HIPCHK(hipMemcpyAsync(perm, c->pc_perm, sizeof(int32_t) * s->n_tri, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(leaf_start, c->pc_start, sizeof(int32_t) * (L + 1),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *n_leaves = L;
+    return PB_OK;
+}
+
+static int pb_precond_apply_impl(pb_ctx *c, const pb_surface *s, const pb_params *p,
+                                 const double *x, double *y, int transpose)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    if (!x || !y)
+        return fail(c, PB_ERR_ARG, "x or y is NULL");
+    if (p->precond_leaf < 1 || p->precond_leaf > PC_MAX_LEAF)
+        return fail(c, PB_ERR_ARG, "precond_leaf must be in [1, %d]", PC_MAX_LEAF);
+    const double *dv;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(setup_geometry(c, s->n_vert, s->n_tri, dv, dt));
+    TRY(setup_precond(c, p));
+    const int64_t n2 = 2 * s->n_tri;
+    TRY(ensure(c, c->io_x, sizeof(double) * n2));
+    TRY(ensure(c, c->io_y, sizeof(double) * n2));
+    HIPCHK(hipMemcpyAsync(c->io_x.p, x, sizeof(double) * n2, hipMemcpyHostToDevice, c->stream));
+    TRY(pc_apply(c, transpose ? 1 : 0, as<double>(c->io_x), as<double>(c->io_y)));
+    HIPCHK(hipMemcpyAsync(y, c->io_y.p, sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PB_OK;
+}
+
+int pb_precond_leaves(pb_ctx *c, const pb_surface *s, int leaf, int32_t *perm,
+                      int32_t *leaf_start, int64_t *n_leaves)
+{
+    return leave(c, pb_precond_leaves_impl(c, s, leaf, perm, leaf_start, n_leaves));
+}
+
+int pb_precond_apply(pb_ctx *c, const pb_surface *s, const pb_params *p, const double *x,
+                     double *y, int transpose)
+{
+    return leave(c, pb_precond_apply_impl(c, s, p, x, y, transpose));
 }
 
 int pb_set_sweep_config(pb_ctx *c, int targets_per_thread, int target_waves)

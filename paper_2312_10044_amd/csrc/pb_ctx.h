@@ -58,6 +58,11 @@ struct pb_ctx {
     pbk::Geo g{};
     double center[3] = {0.0, 0.0, 0.0};
     double volume = 0.0, area_sum = 0.0;
+    // block-diagonal preconditioner of the current geometry
+    pbk::DevBuf pc_idx, pc_inv;
+    int64_t pc_leaves = 0;
+    int32_t *pc_perm = nullptr, *pc_start = nullptr;
+    int64_t *pc_boff = nullptr;
     // batched solves (pb_solve_batch)
     pbk::DevBuf b_geo, b_desc, b_map, b_items, b_src, b_part, b_vec, b_V, b_state, b_red, b_chg;
     hipGraphExec_t b_graph = nullptr;

@@ -13,6 +13,7 @@ constexpr int NGEO = 7;         // cx, cy, cz, nx, ny, nz, area
 constexpr int GEO_RED = 6;      // bad, 6*volume, sum cx, sum cy, sum cz, sum area
 constexpr int MAX_RESTART = 64;
 constexpr int PADN = 512;       // collocation arrays are padded to a multiple of this
+constexpr int PC_MAX_LEAF = 32; // largest preconditioner leaf (its 2m x 2m block lives in LDS)
 
 // Device-side collocation geometry, SoA: array k at g + k * npad.
 struct Geo {
@@ -94,6 +95,16 @@ void launch_force_pairs(hipStream_t s, const double *fwd, const double *adj, int
 void launch_force_finish(hipStream_t s, const double *part, int n_chunks, int64_t nc,
                          int64_t ncpad, const double *q, double half_cu, double inv4pi_eps_in,
                          double *dpos, double *dq, double *per, double *out);
+
+// Leaf blocks of the preconditioner: assemble and invert (one workgroup per
+// leaf), and apply y = M^-1 x (trans: M^-T x).  perm lists the collocation
+// points leaf by leaf, lstart[l]..lstart[l+1] the points of leaf l, boff[l]
+// the offset of its (2m)^2 inverse block in inv.
+void launch_pc_build(hipStream_t s, const Geo &geo, const int32_t *perm, const int32_t *lstart,
+                     const int64_t *boff, int64_t n_leaves, double eps, double kappa, double *inv);
+void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, const int32_t *perm,
+                     const int32_t *lstart, int64_t n_leaves, int64_t n, const double *x,
+                     int trans, double *y);
 
 // ---- deterministic BLAS-1 on device vectors of length n ----------------
 int dot_blocks(int64_t n);

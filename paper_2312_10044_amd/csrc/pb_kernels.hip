@@ -516,6 +516,165 @@ __global__ __launch_bounds__(TPB) void k_force_finish(const double *__restrict__
         dpos[3 * k + d] = half_cu * q[k] * (v[1 + d] + inv4pi_eps_in * v[5 + d]);
 }
 
+// ---- block-diagonal leaf preconditioner (Sec. 2.2.4) -------------------------
+//
+// One workgroup per leaf of m <= PC_MAX_LEAF elements: the 2m x 2m block of A
+// on the leaf's indices (rows/columns [phi; psi] of the leaf) is assembled in
+// LDS and inverted in place by Gauss-Jordan elimination with partial (row)
+// pivoting; the inverse is stored row-major at inv + boff[leaf].  Applying
+// M^-1 is then one small dense matvec per leaf.
+
+__global__ __launch_bounds__(TPB) void k_pc_build(const double *__restrict__ g, int64_t npad,
+                                                  const int32_t *__restrict__ perm,
+                                                  const int32_t *__restrict__ lstart,
+                                                  const int64_t *__restrict__ boff, double eps,
+                                                  double kappa, double *__restrict__ inv)
+{
+    constexpr int MM = 2 * PC_MAX_LEAF;
+    __shared__ double A[MM][MM + 1];
+    __shared__ double fcol[MM];
+    __shared__ int ipiv[MM];
+    __shared__ double pinv;
+    const int l = blockIdx.x;
+    const int s0 = lstart[l];
+    const int m = lstart[l + 1] - s0;
+    const int m2 = 2 * m;
+    if (m < 1 || m > PC_MAX_LEAF)
+        return;   // the host never builds such leaves; never overrun the LDS block
+    const double epsm1 = eps - 1.0, ieps = 1.0 / eps, iepsm1 = 1.0 / eps - 1.0;
+    for (int e = threadIdx.x; e < m * m; e += TPB) {
+        const int r = e / m, q = e - r * m;
+        const int64_t i = perm[s0 + r], j = perm[s0 + q];
+        double k1 = 0.0, k2 = 0.0, k3 = 0.0, k4 = 0.0;
+        if (i != j) {
+            const double dx = g[i] - g[j], dy = g[npad + i] - g[npad + j];
+            const double dz = g[2 * npad + i] - g[2 * npad + j];
+            const double nxi = g[3 * npad + i], nyi = g[4 * npad + i], nzi = g[5 * npad + i];
+            const double nxj = g[3 * npad + j], nyj = g[4 * npad + j], nzj = g[5 * npad + j];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double ir = rsqrt(r2);
+            const double ir2 = ir * ir, u = ir2 * ir;
+            const double kr = kappa * (r2 * ir);
+            const double ee = exp(-kr);
+            const double em1 = ee - 1.0;
+            const double tm1 = fma(kr, ee, em1);
+            const double cx = nxi * dx + nyi * dy + nzi * dz;
+            const double cy = nxj * dx + nyj * dy + nzj * dz;
+            const double nn = nxi * nxj + nyi * nyj + nzi * nzj;
+            const double h = fma(tm1, 3.0 * ir2, kappa * kappa * ee);
+            k1 = -em1 * ir;
+            k2 = fma(eps, tm1, epsm1) * cy * u;
+            k3 = fma(ieps, tm1, iepsm1) * cx * u;
+            k4 = u * (tm1 * nn - cx * cy * h);
+        }
+        const double aj = g[6 * npad + j] * INV_4PI;
+        A[r][q] = -k2 * aj;
+        A[r][m + q] = -k1 * aj;
+        A[m + r][q] = -k4 * aj;
+        A[m + r][m + q] = -k3 * aj;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < m; r += TPB) {
+        A[r][r] += 0.5 * (1.0 + eps);
+        A[m + r][m + r] += 0.5 * (1.0 + 1.0 / eps);
+    }
+    __syncthreads();
+    for (int k = 0; k < m2; ++k) {
+        if (threadIdx.x == 0) {
+            int p = k;
+            double best = fabs(A[k][k]);
+            for (int i = k + 1; i < m2; ++i) {
+                const double v = fabs(A[i][k]);
+                if (v > best) {
+                    best = v;
+                    p = i;
+                }
+            }
+            ipiv[k] = p;
+        }
+        __syncthreads();
+        const int p = ipiv[k];
+        if (p != k) {
+            for (int c = threadIdx.x; c < m2; c += TPB) {
+                const double t = A[k][c];
+                A[k][c] = A[p][c];
+                A[p][c] = t;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            pinv = 1.0 / A[k][k];
+            A[k][k] = 1.0;
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < m2; c += TPB)
+            A[k][c] *= pinv;
+        for (int i = threadIdx.x; i < m2; i += TPB)
+            fcol[i] = A[i][k];
+        __syncthreads();
+        for (int e = threadIdx.x; e < m2 * m2; e += TPB) {
+            const int i = e / m2, c = e - i * m2;
+            if (i == k)
+                continue;
+            const double base = (c == k) ? 0.0 : A[i][c];
+            A[i][c] = base - fcol[i] * A[k][c];
+        }
+        __syncthreads();
+    }
+    for (int k = m2 - 1; k >= 0; --k) {
+        const int p = ipiv[k];
+        if (p != k) {
+            for (int r = threadIdx.x; r < m2; r += TPB) {
+                const double t = A[r][k];
+                A[r][k] = A[r][p];
+                A[r][p] = t;
+            }
+        }
+        __syncthreads();
+    }
+    double *out = inv + boff[l];
+    for (int e = threadIdx.x; e < m2 * m2; e += TPB) {
+        const int r = e / m2, c = e - r * m2;
+        out[e] = A[r][c];
+    }
+}
+
+// y = M^-1 x (or M^-T x): one workgroup per leaf.
+__global__ __launch_bounds__(TPB) void k_pc_apply(const double *__restrict__ inv,
+                                                  const int64_t *__restrict__ boff,
+                                                  const int32_t *__restrict__ perm,
+                                                  const int32_t *__restrict__ lstart, int64_t n,
+                                                  const double *__restrict__ x, int trans,
+                                                  double *__restrict__ y)
+{
+    constexpr int MM = 2 * PC_MAX_LEAF;
+    __shared__ double v[MM];
+    const int l = blockIdx.x;
+    const int s0 = lstart[l];
+    const int m = lstart[l + 1] - s0;
+    const int m2 = 2 * m;
+    if (m < 1 || m > PC_MAX_LEAF)
+        return;
+    for (int r = threadIdx.x; r < m2; r += TPB)
+        v[r] = (r < m) ? x[perm[s0 + r]] : x[n + perm[s0 + r - m]];
+    __syncthreads();
+    const double *B = inv + boff[l];
+    for (int r = threadIdx.x; r < m2; r += TPB) {
+        double s = 0.0;
+        if (!trans) {
+            for (int c = 0; c < m2; ++c)
+                s = fma(B[(int64_t)r * m2 + c], v[c], s);
+        } else {
+            for (int c = 0; c < m2; ++c)
+                s = fma(B[(int64_t)c * m2 + r], v[c], s);
+        }
+        if (r < m)
+            y[perm[s0 + r]] = s;
+        else
+            y[n + perm[s0 + r - m]] = s;
+    }
+}
+
 // ---- BLAS-1 ----------------------------------------------------------------
 
 __global__ __launch_bounds__(TPB) void k_dots(const double *__restrict__ V, int64_t ld, int k,
@@ -769,6 +928,21 @@ void launch_force_finish(hipStream_t s, const double *part, int n_chunks, int64_
     hipLaunchKernelGGL(k_force_finish, dim3(blocks_for(nc)), dim3(TPB), 0, s, part, n_chunks, nc,
                        ncpad, q, half_cu, inv4pi_eps_in, dpos, dq, per);
     hipLaunchKernelGGL(k_weighted_total, dim3(1), dim3(TPB), 0, s, per, q, nc, half_cu, out);
+}
+
+void launch_pc_build(hipStream_t s, const Geo &geo, const int32_t *perm, const int32_t *lstart,
+                     const int64_t *boff, int64_t n_leaves, double eps, double kappa, double *inv)
+{
+    hipLaunchKernelGGL(k_pc_build, dim3((unsigned)n_leaves), dim3(TPB), 0, s, geo.g, geo.npad, perm,
+                       lstart, boff, eps, kappa, inv);
+}
+
+void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, const int32_t *perm,
+                     const int32_t *lstart, int64_t n_leaves, int64_t n, const double *x,
+                     int trans, double *y)
+{
+    hipLaunchKernelGGL(k_pc_apply, dim3((unsigned)n_leaves), dim3(TPB), 0, s, inv, boff, perm,
+                       lstart, n, x, trans, y);
 }
 
 int dot_blocks(int64_t n)

@@ -51,7 +51,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("eps_in", _dbl), ("eps_out", _dbl), ("kappa", _dbl), ("tol", _dbl),
                 ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("max_refine", ctypes.c_int32),
-                ("inner_tol", _dbl)]
+                ("inner_tol", _dbl), ("precond_leaf", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -86,6 +87,10 @@ _PROTOS = {
     "pb_solve_batch": (_int, [_vp, ctypes.c_int32, ctypes.POINTER(_Surface),
                               ctypes.POINTER(_Charges), ctypes.POINTER(_Params), _vp, _vp, _vp,
                               ctypes.POINTER(_Info)]),
+    "pb_precond_leaves": (_int, [_vp, ctypes.POINTER(_Surface), _int, _vp, _vp,
+                                 ctypes.POINTER(_i64)]),
+    "pb_precond_apply": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params), _vp, _vp,
+                                _int]),
     "pb_set_sweep_config": (_int, [_vp, _int, _int]),
     "pb_get_sweep_config": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
     "pb_autotune": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params),
@@ -136,11 +141,12 @@ class Params:
     precision: int = PB_FP64
     max_refine: int = 20
     inner_tol: float = 1e-4
+    precond_leaf: int = 0
 
     def c(self) -> _Params:
         return _Params(float(self.eps_in), float(self.eps_out), float(self.kappa), float(self.tol),
                        int(self.restart), int(self.max_iter), int(self.precision),
-                       int(self.max_refine), float(self.inner_tol))
+                       int(self.max_refine), float(self.inner_tol), int(self.precond_leaf), 0)
 
 
 @dataclass
@@ -345,6 +351,28 @@ class Context:
                                           _dev(dE_dpos, "float64"), _dev(dE_dq, "float64"),
                                           ctypes.byref(info)))
         return Info.of(info)
+
+    # -- preconditioner hooks ----------------------------------------------------
+    def pb_precond_leaves(self, verts, tris, leaf: int):
+        """Octree leaves of the preconditioner: list of index arrays."""
+        s, keep = self._surface(verts, tris)
+        perm = np.empty(s.n_tri, dtype=np.int32)
+        start = np.empty(s.n_tri + 1, dtype=np.int32)
+        nl = _i64()
+        self._check(self._L.pb_precond_leaves(self._h, ctypes.byref(s), int(leaf),
+                                              _vp(perm.ctypes.data), _vp(start.ctypes.data),
+                                              ctypes.byref(nl)))
+        L = int(nl.value)
+        return [perm[start[k]:start[k + 1]].astype(np.int64) for k in range(L)]
+
+    def pb_precond_apply(self, verts, tris, x, params: Params, transpose=False):
+        s, keep = self._surface(verts, tris)
+        xx, px = _host(x, np.float64)
+        y = np.empty_like(xx)
+        p = params.c()
+        self._check(self._L.pb_precond_apply(self._h, ctypes.byref(s), ctypes.byref(p), px,
+                                             _vp(y.ctypes.data), int(bool(transpose))))
+        return y
 
     # -- launch configuration --------------------------------------------------
     def set_sweep_config(self, targets_per_thread: int = 0, target_waves: int = 0):

@@ -38,7 +38,7 @@ def test_struct_layouts_match_header_sizes():
     from paper_2312_10044_amd import pbsolve as b
     assert ctypes.sizeof(b._Surface) == 32
     assert ctypes.sizeof(b._Charges) == 24
-    assert ctypes.sizeof(b._Params) == 56
+    assert ctypes.sizeof(b._Params) == 64
     assert ctypes.sizeof(b._Info) == 48
 
 
@@ -81,3 +81,20 @@ def test_missing_library_fails_loudly(tmp_path):
             pbsolve.load_library(str(tmp_path / "nope.so"))
         finally:
             pbsolve._lib = saved
+
+
+def test_header_struct_sizes_match_the_binding(tmp_path):
+    """Compile the public header with gcc and compare struct sizes."""
+    import ctypes
+    import subprocess
+    from paper_2312_10044_amd import pbsolve as b
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include "pbsolve.h"\nint main(void){printf("%zu %zu %zu %zu\\n",'
+                   ' sizeof(pb_surface), sizeof(pb_charges), sizeof(pb_params), sizeof(pb_info));'
+                   ' return 0;}\n')
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                           str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert got == [ctypes.sizeof(b._Surface), ctypes.sizeof(b._Charges), ctypes.sizeof(b._Params),
+                   ctypes.sizeof(b._Info)]
