@@ -85,15 +85,17 @@ typedef struct {
                                    preconditioner of Sec. 2.2.4 with at most this many
                                    elements per octree leaf; GMRES then runs on the left-
                                    preconditioned system M^-1 A x = M^-1 b and tol applies
-                                   to its residual |M^-1 (b - A x)| / |M^-1 b| (FP64 path and
-                                   IR inner solves; the IR outer test stays unpreconditioned).
+                                   to its residual |M^-1 (b - A x)| / |M^-1 b| (FP64 path,
+                                   IR inner solves and IR outer test alike; the outer
+                                   residual b - A x itself is formed in FP64).
                                    Not used by pb_solve_batch. */
     int32_t reserved;           /* set to 0 */
 } pb_params;
 
 typedef struct {
     double e_solv;              /* solvation energy, kcal/mol */
-    double rel_residual;        /* final true relative residual (FP64) */
+    double rel_residual;        /* final relative residual (FP64); left-preconditioned
+                                   when precond_leaf > 0 */
     double seconds;             /* wall time inside the call */
     int32_t iters;              /* Arnoldi steps (one matvec each), all precisions */
     int32_t matvecs_fp64;       /* FP64 matvecs, including residual checks */
@@ -172,6 +174,21 @@ int pb_forces(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_pa
 int pb_solve_batch(pb_ctx *ctx, int32_t n_sys, const pb_surface *surfaces,
                    const pb_charges *charges, const pb_params *p, double *e_solv,
                    double *dE_dpos, double *dE_dq, pb_info *info);
+
+/* Potential inside the molecule (eq. eq_inside) at n_points points [n][3]
+ * strictly inside the surface, from a surface solution phi, dphi [n_tri]:
+ *   reaction[k] = sum_j [K1(x_k, x_j) dphi_j + K2(x_k, x_j) phi_j] a_j
+ *   total[k]    = reaction[k] + S1(x_k)
+ * in the units of phi (e_c/A divided by 4 pi; x 4 pi 332.0716 for
+ * kcal/mol/e_c).  reaction or total may be NULL. */
+int pb_potential(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_params *p,
+                 const double *phi, const double *dphi, int64_t n_points, const double *points,
+                 double *reaction, double *total);
+
+/* Coulomb energy of the charges in the solute, (332.0716/2) sum_{k != l}
+ * q_k q_l / (eps_in |y_k - y_l|) in kcal/mol: E_free of eq. free_energy is
+ * E_sol + e_coul. */
+int pb_coulomb_energy(pb_ctx *ctx, const pb_charges *c, const pb_params *p, double *e_coul);
 
 /* ---- device-pointer entry points -------------------------------------- */
 /* Same operations; every array argument is device memory laid out as above.

@@ -45,9 +45,11 @@ def lib():
         L.orc_reaction.argtypes = [i64, p, p, p, d, d, p, p, i64, p, p, p]
         L.orc_adjoint_rhs.argtypes = [i64, p, p, p, d, d, i64, p, p, p, p]
         L.orc_source_adjoint.argtypes = [i64, p, p, d, p, p, i64, p, p, p]
+        L.orc_coulomb.argtypes = [i64, p, i64, p, p, d, ctypes.c_int, p]
         for f in (L.orc_green, L.orc_kernels, L.orc_matvec, L.orc_matvec_t, L.orc_assemble,
                   L.orc_assemble_subset,
-                  L.orc_source, L.orc_reaction, L.orc_adjoint_rhs, L.orc_source_adjoint):
+                  L.orc_source, L.orc_reaction, L.orc_adjoint_rhs, L.orc_source_adjoint,
+                  L.orc_coulomb):
             f.restype = None
         _lib = L
     return _lib

@@ -276,3 +276,30 @@ def forces(sol: Solution, pos, q, eps_in=1.0, eps_out=80.0, kappa=0.1257, tol=1e
     dE_dq = k * (P + c)
     dE_dpos = k * q[:, None] * (gP + gc)
     return dE_dpos, dE_dq, lam, info
+
+
+def potential(g: Geometry, eps: float, kappa: float, xi: np.ndarray, pos, q, eps_in: float,
+              points):
+    """Potential inside the molecule (eq. eq_inside) at points [M, 3]:
+    reaction part sum_j [K1(x, x_j) psi_j + K2(x, x_j) phi_j] a_j and total
+    = reaction + S1(x).  BIE units (physical e_c/A divided by 4 pi)."""
+    pts = f64(points)
+    reac = energy_terms(g, eps, kappa, xi, pts)
+    coul = np.empty(pts.shape[0])
+    pos = f64(pos)
+    q = f64(q)
+    lib().orc_coulomb(pts.shape[0], ptr(pts), q.shape[0], ptr(pos), ptr(q), float(eps_in), 0,
+                      ptr(coul))
+    return reac, reac + coul
+
+
+def coulomb_energy(pos, q, eps_in: float) -> float:
+    """(1/2) sum_k q_k S1(y_k) without the self terms, in kcal/mol: the
+    difference between E_free (eq. free_energy) and E_sol."""
+    pos = f64(pos)
+    q = f64(q)
+    out = np.empty(q.shape[0])
+    lib().orc_coulomb(q.shape[0], ptr(pos), q.shape[0], ptr(pos), ptr(q), float(eps_in), 1,
+                      ptr(out))
+    return float(C_UNITS * 4.0 * math.pi * 0.5 * np.sum(q * out))
+

@@ -341,3 +341,25 @@ void orc_source_adjoint(int64_t n, const double *cen, const double *nrm, double 
         grad[3 * k + 2] = g[2] / eps_in;
     }
 }
+
+/* Coulomb potential of the charges, S1 of eq. source_terms at arbitrary
+ * points: out_k = (1/eps_in) sum_l q_l G0(x_k, y_l), skipping l == k when
+ * skip_self (x = the charge positions themselves). */
+void orc_coulomb(int64_t npts, const double *pts, int64_t nc, const double *pos,
+                 const double *q, double eps_in, int skip_self, double *out)
+{
+    double zero[3] = {0.0, 0.0, 0.0};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < npts; ++k) {
+        double s = 0.0;
+        for (int64_t l = 0; l < nc; ++l) {
+            if (skip_self && l == k)
+                continue;
+            double o[4];
+            green_normal(pts + 3 * k, zero, pos + 3 * l, zero, 0.0, o);
+            s += q[l] * o[0];
+        }
+        out[k] = s / eps_in;
+    }
+}
+

@@ -587,8 +587,16 @@ int solve_system(pb_ctx *c, const pb_params *p, int transpose, const double *rhs
         out.status = st.converged ? PB_OK : PB_NOT_CONVERGED;
         return PB_OK;
     }
+    // With the preconditioner on, the outer test uses the same left-
+    // preconditioned norm |M^-1 (rhs - A x)| / |M^-1 rhs| as the inner solves.
+    const bool pc = c->pc_leaves > 0;
     double bnorm;
-    TRY(norm_host(c, rhs, v.n2, &bnorm));
+    if (pc) {
+        TRY(pc_apply(c, transpose, rhs, v.pw));
+        TRY(norm_host(c, v.pw, v.n2, &bnorm));
+    } else {
+        TRY(norm_host(c, rhs, v.n2, &bnorm));
+    }
     launch_fill(c->stream, x, 0.0, v.n2);
     LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(v.r, rhs, sizeof(double) * v.n2, hipMemcpyDeviceToDevice, c->stream));
@@ -615,7 +623,12 @@ int solve_system(pb_ctx *c, const pb_params *p, int transpose, const double *rhs
         out.mv64++;
         launch_sub(c->stream, rhs, v.w, v.r, v.n2);
         LAUNCHCHK();
-        TRY(norm_host(c, v.r, v.n2, &rnorm));
+        if (pc) {
+            TRY(pc_apply(c, transpose, v.r, v.pw));
+            TRY(norm_host(c, v.pw, v.n2, &rnorm));
+        } else {
+            TRY(norm_host(c, v.r, v.n2, &rnorm));
+        }
         if (!std::isfinite(rnorm))
             return fail(c, PB_ERR_GEOMETRY, "non-finite residual in refinement");
     }
@@ -1103,6 +1116,97 @@ int pb_forces_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert
 {
     return leave(c, pb_forces_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p,
                                        d_dE_dpos, d_dE_dq, info));
+}
+
+static int pb_potential_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q,
+                             const pb_params *p, const double *phi, const double *dphi,
+                             int64_t n_points, const double *points, double *reaction,
+                             double *total)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    if (!phi || !dphi || !points || n_points <= 0)
+        return fail(c, PB_ERR_ARG, "phi, dphi or points missing");
+    const double *dv, *dp, *dq;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(upload_charges(c, q, &dp, &dq));
+    TRY(setup_geometry(c, s->n_vert, s->n_tri, dv, dt));
+    const Geo &g = c->g;
+    const int64_t n = s->n_tri;
+    TRY(ensure(c, c->io_x, sizeof(double) * (2 * n + 3 * n_points)));
+    double *dx = as<double>(c->io_x), *dpts = dx + 2 * n;
+    HIPCHK(hipMemcpyAsync(dx, phi, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dx + n, dphi, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dpts, points, sizeof(double) * 3 * n_points, hipMemcpyHostToDevice,
+                          c->stream));
+    const Sweep sw = plan_sweep(n_points, g.npad, TARGET_WAVES);
+    const int64_t ncpad = (int64_t)sw.n_tblocks * TPB;
+    TRY(ensure(c, c->chg_part, sizeof(double) * sw.n_chunks * ncpad));
+    TRY(ensure(c, c->chg_per, sizeof(double) * ncpad));
+    TRY(ensure(c, c->src64, sizeof(double) * 8 * g.npad));
+    TRY(ensure(c, c->io_y, sizeof(double) * 2 * n_points));
+    double *reac = as<double>(c->io_y), *coul = reac + n_points;
+    launch_pack_f64(c->stream, g, dx, as<double>(c->src64), 0);
+    LAUNCHCHK();
+    launch_charge_pairs(c->stream, g, as<double>(c->src64), n_points, dpts, sw, pair_params(c, p),
+                        0, as<double>(c->chg_part), ncpad);
+    LAUNCHCHK();
+    launch_charge_finish(c->stream, as<double>(c->chg_part), sw.n_chunks, n_points, ncpad, nullptr,
+                         1.0, reac, nullptr);
+    LAUNCHCHK();
+    launch_point_coulomb(c->stream, n_points, dpts, q->n, dp, dq,
+                         1.0 / (4.0 * M_PI * p->eps_in), 0, coul);
+    LAUNCHCHK();
+    std::vector<double> hr(n_points), hc(n_points);
+    HIPCHK(hipMemcpyAsync(hr.data(), reac, sizeof(double) * n_points, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(hc.data(), coul, sizeof(double) * n_points, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int64_t k = 0; k < n_points; ++k) {
+        const double r = hr[k] / (4.0 * M_PI);   // the sweep sums 4 pi K
+        if (reaction)
+            reaction[k] = r;
+        if (total)
+            total[k] = r + hc[k];
+    }
+    return PB_OK;
+}
+
+static int pb_coulomb_energy_impl(pb_ctx *c, const pb_charges *q, const pb_params *p,
+                                  double *e_coul)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    if (!e_coul)
+        return fail(c, PB_ERR_ARG, "e_coul is NULL");
+    const double *dp, *dq;
+    TRY(upload_charges(c, q, &dp, &dq));
+    TRY(ensure(c, c->chg_per, sizeof(double) * q->n));
+    TRY(ensure(c, c->small, sizeof(double) * HSMALL));
+    launch_point_coulomb(c->stream, q->n, dp, q->n, dp, dq, 1.0 / p->eps_in, 1,
+                         as<double>(c->chg_per));
+    LAUNCHCHK();
+    const int slot = HSMALL - 4;
+    launch_weighted_total(c->stream, as<double>(c->chg_per), dq, q->n, 0.5 * C_UNITS,
+                          as<double>(c->small) + slot);
+    LAUNCHCHK();
+    TRY(fetch_small(c, slot, 1));
+    *e_coul = c->hsmall[slot];
+    return PB_OK;
+}
+
+int pb_potential(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
+                 const double *phi, const double *dphi, int64_t n_points, const double *points,
+                 double *reaction, double *total)
+{
+    return leave(c, pb_potential_impl(c, s, q, p, phi, dphi, n_points, points, reaction, total));
+}
+
+int pb_coulomb_energy(pb_ctx *c, const pb_charges *q, const pb_params *p, double *e_coul)
+{
+    return leave(c, pb_coulomb_energy_impl(c, q, p, e_coul));
 }
 
 static int pb_precond_leaves_impl(pb_ctx *c, const pb_surface *s, int leaf, int32_t *perm,

@@ -106,6 +106,14 @@ void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, cons
                      const int32_t *lstart, int64_t n_leaves, int64_t n, const double *x,
                      int trans, double *y);
 
+// out_k = scale * sum_l q_l / |x_k - y_l| over npts points (skip l == k).
+void launch_point_coulomb(hipStream_t s, int64_t npts, const double *pts, int64_t nc,
+                          const double *pos, const double *q, double scale, int skip_self,
+                          double *out);
+// out[0] = scale * sum_k q_k per[k] (fixed order, one block).
+void launch_weighted_total(hipStream_t s, const double *per, const double *q, int64_t nc,
+                           double scale, double *out);
+
 // ---- deterministic BLAS-1 on device vectors of length n ----------------
 int dot_blocks(int64_t n);
 // part[j * nblk + b] = block b's share of <V_j, w> for j < k, and of <w, w> at j = k.

@@ -675,6 +675,38 @@ __global__ __launch_bounds__(TPB) void k_pc_apply(const double *__restrict__ inv
     }
 }
 
+// ---- Coulomb potential of the charges at arbitrary points --------------------
+// out_k = scale * sum_l q_l / |x_k - y_l|, l == k skipped when skip_self
+// (x = the charges themselves).
+__global__ __launch_bounds__(TPB) void k_point_coulomb(int64_t npts, const double *__restrict__ pts,
+                                                       int64_t nc, const double *__restrict__ pos,
+                                                       const double *__restrict__ q, double scale,
+                                                       int skip_self, double *__restrict__ out)
+{
+    __shared__ double4 sh[TILE];
+    const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const int64_t kk = k < npts ? k : npts - 1;
+    const double x = pts[3 * kk], y = pts[3 * kk + 1], z = pts[3 * kk + 2];
+    double s = 0.0;
+    for (int64_t t0 = 0; t0 < nc; t0 += TILE) {
+        __syncthreads();
+        const int64_t l = t0 + threadIdx.x;
+        sh[threadIdx.x] = (l < nc) ? make_double4(pos[3 * l], pos[3 * l + 1], pos[3 * l + 2], q[l])
+                                   : make_double4(FAR_SRC, 0.0, 0.0, 0.0);
+        __syncthreads();
+        const int cnt = (int)min((int64_t)TILE, nc - t0);
+        for (int ll = 0; ll < cnt; ++ll) {
+            if (skip_self && t0 + ll == k)
+                continue;
+            const double4 c = sh[ll];
+            const double dx = x - c.x, dy = y - c.y, dz = z - c.z;
+            s += c.w * rsqrt(dx * dx + dy * dy + dz * dz);
+        }
+    }
+    if (k < npts)
+        out[k] = scale * s;
+}
+
 // ---- BLAS-1 ----------------------------------------------------------------
 
 __global__ __launch_bounds__(TPB) void k_dots(const double *__restrict__ V, int64_t ld, int k,
@@ -943,6 +975,20 @@ void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, cons
 {
     hipLaunchKernelGGL(k_pc_apply, dim3((unsigned)n_leaves), dim3(TPB), 0, s, inv, boff, perm,
                        lstart, n, x, trans, y);
+}
+
+void launch_point_coulomb(hipStream_t s, int64_t npts, const double *pts, int64_t nc,
+                          const double *pos, const double *q, double scale, int skip_self,
+                          double *out)
+{
+    hipLaunchKernelGGL(k_point_coulomb, dim3(blocks_for(npts)), dim3(TPB), 0, s, npts, pts, nc, pos,
+                       q, scale, skip_self, out);
+}
+
+void launch_weighted_total(hipStream_t s, const double *per, const double *q, int64_t nc,
+                           double scale, double *out)
+{
+    hipLaunchKernelGGL(k_weighted_total, dim3(1), dim3(TPB), 0, s, per, q, nc, scale, out);
 }
 
 int dot_blocks(int64_t n)

@@ -87,6 +87,10 @@ _PROTOS = {
     "pb_solve_batch": (_int, [_vp, ctypes.c_int32, ctypes.POINTER(_Surface),
                               ctypes.POINTER(_Charges), ctypes.POINTER(_Params), _vp, _vp, _vp,
                               ctypes.POINTER(_Info)]),
+    "pb_potential": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
+                            ctypes.POINTER(_Params), _vp, _vp, _i64, _vp, _vp, _vp]),
+    "pb_coulomb_energy": (_int, [_vp, ctypes.POINTER(_Charges), ctypes.POINTER(_Params),
+                                 ctypes.POINTER(_dbl)]),
     "pb_precond_leaves": (_int, [_vp, ctypes.POINTER(_Surface), _int, _vp, _vp,
                                  ctypes.POINTER(_i64)]),
     "pb_precond_apply": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params), _vp, _vp,
@@ -351,6 +355,30 @@ class Context:
                                           _dev(dE_dpos, "float64"), _dev(dE_dq, "float64"),
                                           ctypes.byref(info)))
         return Info.of(info)
+
+    def pb_potential(self, verts, tris, pos, q, phi, dphi, points, params: Params):
+        """(reaction, total) potential at interior points (BIE units)."""
+        s, k1 = self._surface(verts, tris)
+        c, k2 = self._charges(pos, q)
+        a, pa = _host(phi, np.float64)
+        b, pb = _host(dphi, np.float64)
+        pts, pp = _host(points, np.float64)
+        npts = pts.shape[0]
+        reac = np.empty(npts)
+        tot = np.empty(npts)
+        p = params.c()
+        self._check(self._L.pb_potential(self._h, ctypes.byref(s), ctypes.byref(c), ctypes.byref(p),
+                                         pa, pb, npts, pp, _vp(reac.ctypes.data),
+                                         _vp(tot.ctypes.data)))
+        return reac, tot
+
+    def pb_coulomb_energy(self, pos, q, params: Params) -> float:
+        c, k = self._charges(pos, q)
+        e = _dbl()
+        p = params.c()
+        self._check(self._L.pb_coulomb_energy(self._h, ctypes.byref(c), ctypes.byref(p),
+                                              ctypes.byref(e)))
+        return float(e.value)
 
     # -- preconditioner hooks ----------------------------------------------------
     def pb_precond_leaves(self, verts, tris, leaf: int):

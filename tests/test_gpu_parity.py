@@ -291,3 +291,25 @@ def test_device_entry_points_match_host_ones(pb, star12):
     info_h, ph, dh = ctx.pb_solve(w.verts, w.tris, w.pos, w.q, _params(m, tol=1e-8))
     assert info.e_solv == info_h.e_solv
     assert np.array_equal(phi.cpu().numpy(), ph)
+
+
+def test_interior_potential_and_coulomb_energy(pb, star12):
+    """Eq. eq_inside at interior points and E_free - E_sol against the oracle."""
+    m, ctx = pb
+    w = star12
+    info, phi, dphi = ctx.pb_solve(w.verts, w.tris, w.pos, w.q, _params(m, tol=1e-12))
+    g = dsbi.geometry(w.verts, w.tris)
+    pts = w.pos[:40] + 0.25   # points near the charges, inside the surface
+    xi = np.concatenate([phi, dphi])
+    ref_r, ref_t = dsbi.potential(g, 80.0, KAPPA, xi, w.pos, w.q, 1.0, pts)
+    reac, tot = ctx.pb_potential(w.verts, w.tris, w.pos, w.q, phi, dphi, pts, _params(m))
+    assert np.abs(reac - ref_r).max() <= 1e-12 * np.abs(ref_r).max()
+    assert np.abs(tot - ref_t).max() <= 1e-12 * np.abs(ref_t).max()
+    ec = ctx.pb_coulomb_energy(w.pos, w.q, _params(m))
+    ref_c = dsbi.coulomb_energy(w.pos, w.q, 1.0)
+    assert abs(ec - ref_c) <= 1e-12 * abs(ref_c)
+    # at the charges themselves (self term excluded) the reaction part of
+    # (1/2) sum q phi_1 is E_sol
+    reac_k, _t = ctx.pb_potential(w.verts, w.tris, w.pos, w.q, phi, dphi, w.pos, _params(m))
+    e_sol = 332.0716 * 4 * np.pi * 0.5 * np.sum(w.q * reac_k)
+    assert abs(e_sol - info.e_solv) <= 1e-11 * abs(info.e_solv)

@@ -354,3 +354,28 @@ def test_adjoint_force_on_off_centre_kirkwood_charge():
         dpos, _dq, _l, _ = dsbi.forces(s, w.pos, w.q, tol=1e-9)
         errs.append(abs(dpos[0, 2] - ref) / abs(ref))
     assert errs[1] < errs[0] < 0.1
+
+
+def test_interior_reaction_potential_is_kirkwood_constant_for_central_charge():
+    """Central charge: the reaction potential inside the sphere is the
+    constant (q/a)(1/(eps_out(1+kappa a)) - 1/eps_in) (Gaussian units), i.e.
+    that divided by 4 pi in BIE units; the discrete value converges to it."""
+    a, qv = 2.0, 1.0
+    exact = qv / a * (1.0 / (80.0 * (1.0 + KAPPA * a)) - 1.0) / (4.0 * math.pi)
+    pts = np.array([[0.0, 0.0, 0.0], [0.3, -0.2, 0.1], [0.0, 0.7, -0.4]])
+    errs = []
+    for f in (8, 16):
+        w = synth.kirkwood_sphere(freq=f)
+        s = dsbi.solve(w.verts, w.tris, w.pos, w.q, tol=1e-10)
+        reac, total = dsbi.potential(s.geom, 80.0, KAPPA, s.xi, w.pos, w.q, 1.0, pts)
+        errs.append(np.abs(reac - exact).max() / abs(exact))
+        r = np.linalg.norm(pts[1:], axis=1)
+        assert np.allclose(total[1:] - reac[1:], qv / (4 * math.pi * r), rtol=1e-14)
+    assert errs[1] < errs[0] < 0.05
+
+
+def test_coulomb_energy_of_two_charges():
+    pos = np.array([[0.0, 0.0, 0.0], [0.0, 3.0, 4.0]])
+    q = np.array([1.5, -0.5])
+    e = dsbi.coulomb_energy(pos, q, eps_in=2.0)
+    assert e == pytest.approx(332.0716 * 1.5 * -0.5 / (2.0 * 5.0), rel=1e-14)
