@@ -93,6 +93,68 @@ def cpu_baseline(w, seconds=12.0):
     }
 
 
+def run_batch(args):
+    """64 star surfaces of uneven size (5,120-81,920 triangles, 100-2,000
+    charges): E_sol plus forces for all of them in one pb_solve_batch call
+    (shared persistent launches, hipGraph-replayed restart cycles) against
+    the same 64 solves one at a time with pb_forces in FP64."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2312_10044_amd import Context, Params, PB_FP64, PB_FP32_IR
+
+    systems = synth.batch_conformations()
+    sys_list = [(w.verts, w.tris, w.pos, w.q) for w in systems]
+    n_tri = [w.n_tri for w in systems]
+    pairs = float(sum(float(n) * (n - 1) for n in n_tri))
+    _log(f"bench batch: {len(systems)} systems, {sum(n_tri)} triangles, "
+         f"{pairs:.3g} pairs per batched matvec")
+    ctx = Context(0)
+    tol = 1e-6
+    prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
+    pb = Params(tol=tol, precision=prec, restart=10, max_iter=2000)
+    e_b, inf_b, g_b, q_b = ctx.pb_solve_batch(sys_list, pb, forces=True)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps)):
+        e_b, inf_b, g_b, q_b = ctx.pb_solve_batch(sys_list, pb, forces=True)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / max(1, args.steps)
+    p1 = Params(tol=tol, precision=PB_FP64, restart=10, max_iter=2000)
+    ctx.pb_forces(*sys_list[0], p1)
+    t0 = time.perf_counter()
+    e_s = []
+    for sysd in sys_list:
+        info, _gp, _gq = ctx.pb_forces(*sysd, p1)
+        e_s.append(info.e_solv)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    rel = float(np.max(np.abs(np.asarray(e_b) - np.asarray(e_s)) / np.abs(e_s)))
+    out = {
+        "mode": "batch",
+        "metric": "solves/s (E_sol + forces), batched vs one-at-a-time FP64",
+        "n_sys": len(systems),
+        "total_triangles": int(sum(n_tri)),
+        "pairs_per_batched_matvec": pairs,
+        "precision": "FP32 matvec + FP64 restart residuals" if prec == PB_FP32_IR else "FP64",
+        "tol": tol,
+        "batched_s": t_batch,
+        "batched_solves_per_s": len(systems) / t_batch,
+        "sequential_fp64_s": t_seq,
+        "sequential_solves_per_s": len(systems) / t_seq,
+        "speedup": t_seq / t_batch,
+        "max_rel_energy_diff_vs_sequential": rel,
+        "arnoldi_steps_forward_max": max(i.iters for i in inf_b),
+        "arnoldi_steps_adjoint_max": max(i.adjoint_iters for i in inf_b),
+        "matvec_gpairs_per_s_batched": sum(
+            (i.matvecs_fp32 + i.matvecs_fp64) * float(n) * (n - 1)
+            for i, n in zip(inf_b, n_tri)) / t_batch / 1e9,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,7 +164,7 @@ def main():
     ap.add_argument("--workload", choices=["star81920", "star327680"], default="star81920")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--mode", choices=["solve", "matvec", "copy"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "matvec", "copy", "batch"], default="solve",
                     help="solve: the benchmark; matvec: only --steps matvecs of --precision "
                          "(for counter runs); copy: a device copy of --copy-mib MiB (the "
                          "reference kernel that calibrates FETCH_SIZE/WRITE_SIZE)")
@@ -136,6 +198,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read": n * 8, "bytes_written": n * 8,
                           "launches": max(1, args.steps)}), flush=True)
+        return
+    if args.mode == "batch":
+        run_batch(args)
         return
     if args.workload == "star81920":
         w = synth.star_protein()
@@ -188,7 +253,9 @@ def main():
     def pick(precision, leaf):
         for tol in TOL_LADDER:
             if precision == PB_FP32_IR:
-                p = Params(tol=tol, precision=PB_FP32_IR, inner_tol=0.3 * tol,
+                # each inner FP32 solve goes as far as FP32 pair arithmetic
+                # resolves (1e-6); the outer tolerance sets the refinements
+                p = Params(tol=tol, precision=PB_FP32_IR, inner_tol=min(0.3 * tol, 1e-6),
                            max_refine=20, precond_leaf=leaf, **base)
             else:
                 p = Params(tol=tol, precision=PB_FP64, precond_leaf=leaf, **base)
