@@ -112,8 +112,9 @@ def run_batch(args):
          f"{pairs:.3g} pairs per batched matvec")
     ctx = Context(0)
     tol = 1e-6
+    leaf = args.precond_leaf
     prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
-    pb = Params(tol=tol, precision=prec, restart=10, max_iter=2000)
+    pb = Params(tol=tol, precision=prec, restart=10, max_iter=2000, precond_leaf=leaf)
     e_b, inf_b, g_b, q_b = ctx.pb_solve_batch(sys_list, pb, forces=True)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -121,16 +122,25 @@ def run_batch(args):
         e_b, inf_b, g_b, q_b = ctx.pb_solve_batch(sys_list, pb, forces=True)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / max(1, args.steps)
-    p1 = Params(tol=tol, precision=PB_FP64, restart=10, max_iter=2000)
-    ctx.pb_forces(*sys_list[0], p1)
-    t0 = time.perf_counter()
-    e_s = []
-    for sysd in sys_list:
-        info, _gp, _gq = ctx.pb_forces(*sysd, p1)
-        e_s.append(info.e_solv)
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
+    _log(f"batched: {t_batch:.3f} s")
+
+    def sequential(leaf_s):
+        p1 = Params(tol=tol, precision=PB_FP64, restart=10, max_iter=2000, precond_leaf=leaf_s)
+        ctx.pb_forces(*sys_list[0], p1)
+        t = time.perf_counter()
+        es = []
+        for sysd in sys_list:
+            info, _gp, _gq = ctx.pb_forces(*sysd, p1)
+            es.append(info.e_solv)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, es
+
+    t_seq, e_s = sequential(leaf)
+    _log(f"sequential FP64 (leaf {leaf}): {t_seq:.3f} s")
+    t_seq0, e_s0 = sequential(0) if leaf > 0 else (t_seq, e_s)
+    _log(f"sequential FP64 (no preconditioner): {t_seq0:.3f} s")
     rel = float(np.max(np.abs(np.asarray(e_b) - np.asarray(e_s)) / np.abs(e_s)))
+    rel0 = float(np.max(np.abs(np.asarray(e_b) - np.asarray(e_s0)) / np.abs(e_s0)))
     out = {
         "mode": "batch",
         "metric": "solves/s (E_sol + forces), batched vs one-at-a-time FP64",
@@ -138,13 +148,17 @@ def run_batch(args):
         "total_triangles": int(sum(n_tri)),
         "pairs_per_batched_matvec": pairs,
         "precision": "FP32 matvec + FP64 restart residuals" if prec == PB_FP32_IR else "FP64",
+        "precond_leaf": leaf,
         "tol": tol,
         "batched_s": t_batch,
         "batched_solves_per_s": len(systems) / t_batch,
-        "sequential_fp64_s": t_seq,
+        "sequential_fp64_same_preconditioner_s": t_seq,
         "sequential_solves_per_s": len(systems) / t_seq,
         "speedup": t_seq / t_batch,
+        "sequential_fp64_no_preconditioner_s": t_seq0,
+        "speedup_vs_unpreconditioned_fp64": t_seq0 / t_batch,
         "max_rel_energy_diff_vs_sequential": rel,
+        "max_rel_energy_diff_vs_unpreconditioned": rel0,
         "arnoldi_steps_forward_max": max(i.iters for i in inf_b),
         "arnoldi_steps_adjoint_max": max(i.adjoint_iters for i in inf_b),
         "matvec_gpairs_per_s_batched": sum(
@@ -253,9 +267,7 @@ def main():
     def pick(precision, leaf):
         for tol in TOL_LADDER:
             if precision == PB_FP32_IR:
-                # each inner FP32 solve goes as far as FP32 pair arithmetic
-                # resolves (1e-6); the outer tolerance sets the refinements
-                p = Params(tol=tol, precision=PB_FP32_IR, inner_tol=min(0.3 * tol, 1e-6),
+                p = Params(tol=tol, precision=PB_FP32_IR, inner_tol=0.1 * tol,
                            max_refine=20, precond_leaf=leaf, **base)
             else:
                 p = Params(tol=tol, precision=PB_FP64, precond_leaf=leaf, **base)

@@ -78,17 +78,21 @@ typedef struct {
     int32_t max_iter;           /* cap on Arnoldi steps (FP64) / outer refinements x inner cap (IR) */
     int32_t precision;          /* PB_FP64 or PB_FP32_IR */
     int32_t max_refine;         /* IR: cap on refinement steps */
-    double inner_tol;           /* IR: relative tolerance of each inner FP32 GMRES solve;
-                                   values below 1e-6 (beyond what FP32 pair arithmetic
-                                   resolves) are raised to 1e-6 */
+    double inner_tol;           /* IR: relative tolerance of the first inner FP32 GMRES
+                                   solve.  A later correction solve, with outer residual
+                                   r, stops at max(inner_tol, 0.3 tol |b| / |r|) (at most
+                                   0.5): just enough to bring the outer residual under
+                                   tol.  Values below 1e-7 (beyond what FP32 pair
+                                   arithmetic resolves) are raised to 1e-7, and an inner
+                                   solve also ends when a restart cycle gains less
+                                   than 10 % */
     int32_t precond_leaf;       /* 0: no preconditioner.  1..32: block-diagonal leaf
                                    preconditioner of Sec. 2.2.4 with at most this many
                                    elements per octree leaf; GMRES then runs on the left-
                                    preconditioned system M^-1 A x = M^-1 b and tol applies
                                    to its residual |M^-1 (b - A x)| / |M^-1 b| (FP64 path,
                                    IR inner solves and IR outer test alike; the outer
-                                   residual b - A x itself is formed in FP64).
-                                   Not used by pb_solve_batch. */
+                                   residual b - A x itself is formed in FP64). */
     int32_t reserved;           /* set to 0 */
 } pb_params;
 
@@ -164,6 +168,8 @@ int pb_forces(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_pa
  * device, one restart cycle captured in a hipGraph and replayed until all
  * systems converge.  Restart residuals are FP64; with PB_FP32_IR the Arnoldi
  * matvecs are FP32 (each cycle is a refinement step).  restart <= 32.
+ * precond_leaf > 0 applies the block-diagonal leaf preconditioner per system
+ * (left preconditioning, as in pb_solve).
  *   e_solv  [n_sys]                     kcal/mol
  *   dE_dpos [sum_b n_b][3], dE_dq [sum_b n_b] (charges concatenated in
  *           system order) or both NULL: when given, the adjoint solves and

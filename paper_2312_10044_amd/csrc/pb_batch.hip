@@ -709,14 +709,27 @@ struct BatchDev {
     void *src = nullptr;            // 16 doubles per collocation point
     double *part = nullptr;
     double *x = nullptr, *b = nullptr, *w = nullptr, *r = nullptr, *t = nullptr, *lam = nullptr;
+    double *pw = nullptr, *pb = nullptr;
     double *V = nullptr;
+    // block-diagonal leaf preconditioner over all systems (0 leaves: off)
+    int64_t pc_leaves = 0;
+    int32_t *pc_perm = nullptr, *pc_start = nullptr;
+    int64_t *pc_boff = nullptr, *pc_pidx = nullptr, *pc_qidx = nullptr;
+    double *pc_inv = nullptr;
     GState *st = nullptr;
     double *red = nullptr, *dpart = nullptr, *per = nullptr, *e = nullptr;
     int64_t vtot = 0, nvb = 0, ld = 0;
 };
 
+void pc_apply_batch(hipStream_t s, const BatchDev &D, int trans, const double *x, double *y)
+{
+    launch_pc_apply(s, D.pc_inv, D.pc_boff, D.pc_pidx, D.pc_qidx, D.pc_start, D.pc_leaves, x,
+                    trans, y);
+}
+
 // One restart cycle (m Arnoldi steps, update, FP64 residual, next start) on
-// the stream; captured into a graph by the caller.
+// the stream; captured into a graph by the caller.  With the preconditioner
+// the Krylov space is that of M^-1 A and residuals are M^-1 (rhs - A x).
 int enqueue_cycle(pb_ctx *c, const BatchPlan &P, BatchDev &D, const pb_params *p, int trans,
                   const double *rhs, double *x)
 {
@@ -759,21 +772,26 @@ int enqueue_cycle(pb_ctx *c, const BatchPlan &P, BatchDev &D, const pb_params *p
         hipLaunchKernelGGL(kb_finish, dim3(gb), dim3(TPB), 0, s, D.part, ni, D.g, P.gtot, D.sd,
                            D.blk2sys, D.mask_step, vj, alpha, beta, trans,
                            (f32 && !trans) ? eps : 1.0, D.w);
+        double *wv = D.w;
+        if (D.pc_leaves > 0) {
+            pc_apply_batch(s, D, trans, D.w, D.pw);
+            wv = D.pw;
+        }
         // CGS2 against V_0..V_j, then |w|^2 and V_{j+1} = w / |w|
         for (int pass = 0; pass < 2; ++pass) {
             const int off = pass == 0 ? H_OFF1 : H_OFF2;
-            hipLaunchKernelGGL(kb_dots, dim3(vb, j + 1), dim3(TPB), 0, s, D.V, D.ld, j + 1, D.w,
+            hipLaunchKernelGGL(kb_dots, dim3(vb, j + 1), dim3(TPB), 0, s, D.V, D.ld, j + 1, wv,
                                D.dpart, D.nvb);
             hipLaunchKernelGGL(kb_red, dim3(ns, j + 1), dim3(TPB), 0, s, D.dpart, D.nvb, D.sd, off,
                                D.red);
             hipLaunchKernelGGL(kb_sub_basis, dim3(vb), dim3(TPB), 0, s, D.V, D.ld, j + 1, D.red,
-                               off, D.vblk2sys, D.w);
+                               off, D.vblk2sys, wv);
         }
-        hipLaunchKernelGGL(kb_dots, dim3(vb, 1), dim3(TPB), 0, s, D.V, D.ld, 0, D.w, D.dpart,
+        hipLaunchKernelGGL(kb_dots, dim3(vb, 1), dim3(TPB), 0, s, D.V, D.ld, 0, wv, D.dpart,
                            D.nvb);
         hipLaunchKernelGGL(kb_red, dim3(ns, 1), dim3(TPB), 0, s, D.dpart, D.nvb, D.sd, H_NRM,
                            D.red);
-        hipLaunchKernelGGL(kb_scale, dim3(vb), dim3(TPB), 0, s, D.w, D.red, D.vblk2sys,
+        hipLaunchKernelGGL(kb_scale, dim3(vb), dim3(TPB), 0, s, wv, D.red, D.vblk2sys,
                            D.V + (int64_t)(j + 1) * D.ld);
         hipLaunchKernelGGL(kb_givens, dim3(sb), dim3(256), 0, s, D.st, D.red, ns, j, m, p->tol,
                            p->max_iter, D.mask_step);
@@ -793,7 +811,12 @@ int enqueue_cycle(pb_ctx *c, const BatchPlan &P, BatchDev &D, const pb_params *p
                            D.items, ni, D.mask_run, eps, kap, D.part);
     hipLaunchKernelGGL(kb_finish, dim3(gb), dim3(TPB), 0, s, D.part, ni, D.g, P.gtot, D.sd,
                        D.blk2sys, D.mask_run, x, alpha, beta, trans, 1.0, D.w);
-    hipLaunchKernelGGL(kb_axpby, dim3(vb), dim3(TPB), 0, s, rhs, D.w, -1.0, D.r);
+    if (D.pc_leaves > 0) {
+        hipLaunchKernelGGL(kb_axpby, dim3(vb), dim3(TPB), 0, s, rhs, D.w, -1.0, D.pw);
+        pc_apply_batch(s, D, trans, D.pw, D.r);
+    } else {
+        hipLaunchKernelGGL(kb_axpby, dim3(vb), dim3(TPB), 0, s, rhs, D.w, -1.0, D.r);
+    }
     hipLaunchKernelGGL(kb_dots, dim3(vb, 1), dim3(TPB), 0, s, D.V, D.ld, 0, D.r, D.dpart, D.nvb);
     hipLaunchKernelGGL(kb_red, dim3(ns, 1), dim3(TPB), 0, s, D.dpart, D.nvb, D.sd, H_NRM, D.red);
     hipLaunchKernelGGL(kb_begin, dim3(1), dim3(256), 0, s, D.st, D.red, ns, m, p->tol,
@@ -811,9 +834,14 @@ int batch_gmres(pb_ctx *c, const BatchPlan &P, BatchDev &D, const pb_params *p, 
     const int ns = P.n_sys, m = p->restart;
     const unsigned vb = (unsigned)D.nvb;
     const unsigned sb = (unsigned)((ns + 255) / 256);
-    // x = 0, r = rhs, |rhs| -> bnorm, first start
+    // x = 0, r = M^-1 rhs (or rhs), |r| -> bnorm, first start
     hipLaunchKernelGGL(kb_fill, dim3(vb), dim3(TPB), 0, s, x, 0.0);
-    hipLaunchKernelGGL(kb_axpby, dim3(vb), dim3(TPB), 0, s, rhs, x, 0.0, D.r);
+    if (D.pc_leaves > 0) {
+        pc_apply_batch(s, D, trans, rhs, D.pb);
+        hipLaunchKernelGGL(kb_axpby, dim3(vb), dim3(TPB), 0, s, D.pb, x, 0.0, D.r);
+    } else {
+        hipLaunchKernelGGL(kb_axpby, dim3(vb), dim3(TPB), 0, s, rhs, x, 0.0, D.r);
+    }
     hipLaunchKernelGGL(kb_dots, dim3(vb, 1), dim3(TPB), 0, s, D.V, D.ld, 0, D.r, D.dpart, D.nvb);
     hipLaunchKernelGGL(kb_red, dim3(ns, 1), dim3(TPB), 0, s, D.dpart, D.nvb, D.sd, H_NRM, D.red);
     hipLaunchKernelGGL(kb_init, dim3(sb), dim3(256), 0, s, D.st, D.red, ns);
@@ -901,7 +929,7 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     TRY(ensure(c, c->b_items, sizeof(Item) * (ni + nci)));
     TRY(ensure(c, c->b_src, sizeof(double) * 16 * P.gtot));
     TRY(ensure(c, c->b_part, sizeof(double) * TPB * std::max<int64_t>(2 * ni, 8 * nci)));
-    TRY(ensure(c, c->b_vec, sizeof(double) * 6 * D.vtot));
+    TRY(ensure(c, c->b_vec, sizeof(double) * 8 * D.vtot));
     TRY(ensure(c, c->b_V, sizeof(double) * (m + 1) * D.vtot));
     TRY(ensure(c, c->b_red, sizeof(double) * ((int64_t)HB * n_sys + (int64_t)(m + 2) * D.nvb +
                                               8 * P.ctot + n_sys)));
@@ -929,6 +957,8 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     D.r = vp + 3 * D.vtot;
     D.t = vp + 4 * D.vtot;
     D.lam = vp + 5 * D.vtot;
+    D.pw = vp + 6 * D.vtot;
+    D.pb = vp + 7 * D.vtot;
     D.V = as<double>(c->b_V);
     D.red = as<double>(c->b_red);
     D.dpart = D.red + (int64_t)HB * n_sys;
@@ -993,6 +1023,59 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     }
     const double eps = p->eps_out / p->eps_in, kap = p->kappa;
     const unsigned gb = nblk(P.gtot), vb = (unsigned)D.nvb, cbk = nblk(P.ctot);
+    // preconditioned vectors: the apply writes real entries only, so the
+    // padding of these two must start (and stay) zero
+    hipLaunchKernelGGL(kb_fill, dim3(vb), dim3(TPB), 0, s, D.pw, 0.0);
+    hipLaunchKernelGGL(kb_fill, dim3(vb), dim3(TPB), 0, s, D.pb, 0.0);
+    LAUNCHCHK();
+    if (p->precond_leaf > 0) {
+        std::vector<double> hg(3 * P.gtot);
+        HIPCHK(hipMemcpyAsync(hg.data(), D.g, sizeof(double) * 3 * P.gtot, hipMemcpyDeviceToHost,
+                              s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<int32_t> gperm, gstart(1, 0);
+        std::vector<int64_t> gboff(1, 0), pidx, qidx;
+        for (int b = 0; b < n_sys; ++b) {
+            const SysDesc &d = P.sd[b];
+            std::vector<int32_t> perm, start;
+            build_leaves(hg.data() + d.goff, hg.data() + P.gtot + d.goff,
+                         hg.data() + 2 * P.gtot + d.goff, d.n, p->precond_leaf, perm, start);
+            const int32_t base = (int32_t)gperm.size();
+            for (int32_t e : perm) {
+                gperm.push_back((int32_t)(d.goff + e));
+                pidx.push_back(2 * d.goff + e);
+                qidx.push_back(2 * d.goff + d.npad + e);
+            }
+            for (size_t l = 1; l < start.size(); ++l) {
+                gstart.push_back(base + start[l]);
+                const int64_t m2 = 2 * (int64_t)(start[l] - start[l - 1]);
+                gboff.push_back(gboff.back() + m2 * m2);
+            }
+        }
+        const int64_t L = (int64_t)gstart.size() - 1, ne = (int64_t)gperm.size();
+        const size_t off64 = round_up(sizeof(int32_t) * (ne + L + 1), 8);
+        TRY(ensure(c, c->b_pc_idx, off64 + sizeof(int64_t) * (L + 1 + 2 * ne)));
+        TRY(ensure(c, c->b_pc_inv, sizeof(double) * std::max<int64_t>(gboff.back(), 1)));
+        D.pc_perm = as<int32_t>(c->b_pc_idx);
+        D.pc_start = D.pc_perm + ne;
+        D.pc_boff = reinterpret_cast<int64_t *>(static_cast<char *>(c->b_pc_idx.p) + off64);
+        D.pc_pidx = D.pc_boff + (L + 1);
+        D.pc_qidx = D.pc_pidx + ne;
+        D.pc_inv = as<double>(c->b_pc_inv);
+        TRY(upload(c, D.pc_perm, gperm.data(), sizeof(int32_t) * ne));
+        TRY(upload(c, D.pc_start, gstart.data(), sizeof(int32_t) * (L + 1)));
+        TRY(upload(c, D.pc_boff, gboff.data(), sizeof(int64_t) * (L + 1)));
+        TRY(upload(c, D.pc_pidx, pidx.data(), sizeof(int64_t) * ne));
+        TRY(upload(c, D.pc_qidx, qidx.data(), sizeof(int64_t) * ne));
+        Geo gall;
+        gall.g = D.g;
+        gall.n = P.gtot;
+        gall.npad = P.gtot;   // array stride of the concatenated geometry
+        launch_pc_build(s, gall, D.pc_perm, D.pc_start, D.pc_boff, L, eps, kap, D.pc_inv);
+        LAUNCHCHK();
+        HIPCHK(hipStreamSynchronize(s));   // host index vectors go out of scope
+        D.pc_leaves = L;
+    }
     const unsigned cgrid = (unsigned)std::min<int64_t>(nci, BATCH_GRID);
     // charges inside: solid angle with phi = 1, psi = 0
     {

@@ -153,6 +153,10 @@ int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
 
 // ---- block-diagonal leaf preconditioner (Sec. 2.2.4) -------------------------
 
+}  // namespace
+
+namespace pbk {
+
 // Leaves of the octree over the collocation points (Sec. 2.2.3): the root is
 // the cube around the bounding box of the points; a cluster with more than n0
 // points splits into its eight child cubes (octant = (x >= cx) + 2 (y >= cy)
@@ -222,6 +226,10 @@ void build_leaves(const double *x, const double *y, const double *z, int64_t n, 
     }
 }
 
+}  // namespace pbk
+
+namespace {
+
 // Leaves of the current geometry and the inverses of their blocks.
 int setup_precond(pb_ctx *c, const pb_params *p)
 {
@@ -242,17 +250,25 @@ int setup_precond(pb_ctx *c, const pb_params *p)
         const int64_t m2 = 2 * (int64_t)(start[l + 1] - start[l]);
         boff[l + 1] = boff[l] + m2 * m2;
     }
-    TRY(ensure(c, c->pc_idx, sizeof(int32_t) * (g.n + L + 1) + sizeof(int64_t) * (L + 2)));
+    std::vector<int64_t> pq(2 * g.n);
+    for (int64_t e = 0; e < g.n; ++e) {
+        pq[e] = perm[e];              // phi of the element
+        pq[g.n + e] = g.n + perm[e];  // psi of the element
+    }
+    const size_t off64 = round_up(sizeof(int32_t) * (g.n + L + 1), 8);
+    TRY(ensure(c, c->pc_idx, off64 + sizeof(int64_t) * (L + 1 + 2 * g.n)));
     TRY(ensure(c, c->pc_inv, sizeof(double) * std::max<int64_t>(boff[L], 1)));
     int32_t *dperm = as<int32_t>(c->pc_idx);
     int32_t *dstart = dperm + g.n;
-    int64_t *dboff = reinterpret_cast<int64_t *>(
-        static_cast<char *>(c->pc_idx.p) + round_up(sizeof(int32_t) * (g.n + L + 1), 8));
+    int64_t *dboff = reinterpret_cast<int64_t *>(static_cast<char *>(c->pc_idx.p) + off64);
+    int64_t *dpq = dboff + (L + 1);
     HIPCHK(hipMemcpyAsync(dperm, perm.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice,
                           c->stream));
     HIPCHK(hipMemcpyAsync(dstart, start.data(), sizeof(int32_t) * (L + 1), hipMemcpyHostToDevice,
                           c->stream));
     HIPCHK(hipMemcpyAsync(dboff, boff.data(), sizeof(int64_t) * (L + 1), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(dpq, pq.data(), sizeof(int64_t) * 2 * g.n, hipMemcpyHostToDevice,
                           c->stream));
     launch_pc_build(c->stream, g, dperm, dstart, dboff, L, p->eps_out / p->eps_in, p->kappa,
                     as<double>(c->pc_inv));
@@ -262,13 +278,15 @@ int setup_precond(pb_ctx *c, const pb_params *p)
     c->pc_perm = dperm;
     c->pc_start = dstart;
     c->pc_boff = dboff;
+    c->pc_pidx = dpq;
+    c->pc_qidx = dpq + g.n;
     return PB_OK;
 }
 
 int pc_apply(pb_ctx *c, int transpose, const double *x, double *y)
 {
-    launch_pc_apply(c->stream, as<double>(c->pc_inv), c->pc_boff, c->pc_perm, c->pc_start,
-                    c->pc_leaves, c->g.n, x, transpose, y);
+    launch_pc_apply(c->stream, as<double>(c->pc_inv), c->pc_boff, c->pc_pidx, c->pc_qidx,
+                    c->pc_start, c->pc_leaves, x, transpose, y);
     LAUNCHCHK();
     return PB_OK;
 }
@@ -409,9 +427,9 @@ int gmres(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
         }
         if (st.iters >= max_iter)
             return PB_OK;
-        // An FP32 operator resolves the residual only to about 1e-6 of |rhs|:
-        // a restart cycle that no longer gains 10 % ends the inner solve and
-        // leaves the rest to the FP64 refinement around it.
+        // An FP32 operator resolves the residual only to about 1e-6..1e-7 of
+        // |rhs|: a restart cycle that no longer gains 10 % ends the inner
+        // solve and leaves the rest to the FP64 refinement around it.
         if (precision == PB_FP32_IR && prev_rel > 0.0 && st.rel > 0.9 * prev_rel)
             return PB_OK;
         prev_rel = st.rel;
@@ -612,8 +630,12 @@ int solve_system(pb_ctx *c, const pb_params *p, int transpose, const double *rhs
             break;
         HIPCHK(hipMemcpyAsync(v.t, v.r, sizeof(double) * v.n2, hipMemcpyDeviceToDevice,
                               c->stream));
-        TRY(gmres(c, p, PB_FP32_IR, transpose, v.t, v.d, true, std::max(p->inner_tol, 1e-6),
-                  p->max_iter - out.iters, v, st));
+        // a correction solve only has to close the gap between |r| and tol |b|
+        double eta = std::max(p->inner_tol, 1e-7);
+        if (out.refinements > 0 && rnorm > 0.0)
+            eta = std::max(eta, std::min(0.5, 0.3 * p->tol * bnorm / rnorm));
+        TRY(gmres(c, p, PB_FP32_IR, transpose, v.t, v.d, true, eta, p->max_iter - out.iters, v,
+                  st));
         out.iters += st.iters;
         out.mv32 += st.mv32;
         launch_add(c->stream, x, v.d, v.n2);
@@ -855,7 +877,8 @@ void pb_destroy(pb_ctx *c)
                       &c->V, &c->small, &c->dpart, &c->chg_part, &c->chg_per, &c->in_vert,
                       &c->in_tri, &c->in_pos, &c->in_q, &c->io_x, &c->io_y, &c->pc_idx,
                       &c->pc_inv, &c->b_geo, &c->b_desc, &c->b_map, &c->b_items, &c->b_src,
-                      &c->b_part, &c->b_vec, &c->b_V, &c->b_state, &c->b_red, &c->b_chg};
+                      &c->b_part, &c->b_vec, &c->b_V, &c->b_state, &c->b_red, &c->b_chg,
+                      &c->b_pc_idx, &c->b_pc_inv};
     for (DevBuf *b : bufs)
         if (b->p)
             (void)hipFree(b->p);

@@ -63,8 +63,10 @@ struct pb_ctx {
     int64_t pc_leaves = 0;
     int32_t *pc_perm = nullptr, *pc_start = nullptr;
     int64_t *pc_boff = nullptr;
+    int64_t *pc_pidx = nullptr, *pc_qidx = nullptr;
     // batched solves (pb_solve_batch)
     pbk::DevBuf b_geo, b_desc, b_map, b_items, b_src, b_part, b_vec, b_V, b_state, b_red, b_chg;
+    pbk::DevBuf b_pc_idx, b_pc_inv;
     hipGraphExec_t b_graph = nullptr;
     uint64_t b_graph_key = 0;
 };
@@ -182,6 +184,10 @@ inline void prof_collect(pb_ctx *c)
     c->marks.clear();
 }
 
+
+// Octree leaves of n points for the block-diagonal preconditioner (pb_capi.hip).
+void build_leaves(const double *x, const double *y, const double *z, int64_t n, int n0,
+                  std::vector<int32_t> &perm, std::vector<int32_t> &start);
 
 // Batched solve of independent systems (pb_batch.hip).
 int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,

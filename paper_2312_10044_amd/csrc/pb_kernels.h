@@ -98,13 +98,15 @@ void launch_force_finish(hipStream_t s, const double *part, int n_chunks, int64_
 
 // Leaf blocks of the preconditioner: assemble and invert (one workgroup per
 // leaf), and apply y = M^-1 x (trans: M^-T x).  perm lists the collocation
-// points leaf by leaf, lstart[l]..lstart[l+1] the points of leaf l, boff[l]
-// the offset of its (2m)^2 inverse block in inv.
+// points leaf by leaf as indices into geo (arrays of stride geo.npad),
+// lstart[l]..lstart[l+1] the points of leaf l, boff[l] the offset of its
+// (2m)^2 inverse block in inv; pidx/qidx the vector positions of each
+// point's phi and psi unknowns.
 void launch_pc_build(hipStream_t s, const Geo &geo, const int32_t *perm, const int32_t *lstart,
                      const int64_t *boff, int64_t n_leaves, double eps, double kappa, double *inv);
-void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, const int32_t *perm,
-                     const int32_t *lstart, int64_t n_leaves, int64_t n, const double *x,
-                     int trans, double *y);
+void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, const int64_t *pidx,
+                     const int64_t *qidx, const int32_t *lstart, int64_t n_leaves,
+                     const double *x, int trans, double *y);
 
 // out_k = scale * sum_l q_l / |x_k - y_l| over npts points (skip l == k).
 void launch_point_coulomb(hipStream_t s, int64_t npts, const double *pts, int64_t nc,

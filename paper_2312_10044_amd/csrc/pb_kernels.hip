@@ -639,11 +639,13 @@ __global__ __launch_bounds__(TPB) void k_pc_build(const double *__restrict__ g, 
     }
 }
 
-// y = M^-1 x (or M^-T x): one workgroup per leaf.
+// y = M^-1 x (or M^-T x): one workgroup per leaf.  pidx/qidx give the
+// vector positions of the phi and psi unknowns of the leaf's elements.
 __global__ __launch_bounds__(TPB) void k_pc_apply(const double *__restrict__ inv,
                                                   const int64_t *__restrict__ boff,
-                                                  const int32_t *__restrict__ perm,
-                                                  const int32_t *__restrict__ lstart, int64_t n,
+                                                  const int64_t *__restrict__ pidx,
+                                                  const int64_t *__restrict__ qidx,
+                                                  const int32_t *__restrict__ lstart,
                                                   const double *__restrict__ x, int trans,
                                                   double *__restrict__ y)
 {
@@ -656,7 +658,7 @@ __global__ __launch_bounds__(TPB) void k_pc_apply(const double *__restrict__ inv
     if (m < 1 || m > PC_MAX_LEAF)
         return;
     for (int r = threadIdx.x; r < m2; r += TPB)
-        v[r] = (r < m) ? x[perm[s0 + r]] : x[n + perm[s0 + r - m]];
+        v[r] = (r < m) ? x[pidx[s0 + r]] : x[qidx[s0 + r - m]];
     __syncthreads();
     const double *B = inv + boff[l];
     for (int r = threadIdx.x; r < m2; r += TPB) {
@@ -669,9 +671,9 @@ __global__ __launch_bounds__(TPB) void k_pc_apply(const double *__restrict__ inv
                 s = fma(B[(int64_t)c * m2 + r], v[c], s);
         }
         if (r < m)
-            y[perm[s0 + r]] = s;
+            y[pidx[s0 + r]] = s;
         else
-            y[n + perm[s0 + r - m]] = s;
+            y[qidx[s0 + r - m]] = s;
     }
 }
 
@@ -969,12 +971,12 @@ void launch_pc_build(hipStream_t s, const Geo &geo, const int32_t *perm, const i
                        lstart, boff, eps, kappa, inv);
 }
 
-void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, const int32_t *perm,
-                     const int32_t *lstart, int64_t n_leaves, int64_t n, const double *x,
-                     int trans, double *y)
+void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, const int64_t *pidx,
+                     const int64_t *qidx, const int32_t *lstart, int64_t n_leaves,
+                     const double *x, int trans, double *y)
 {
-    hipLaunchKernelGGL(k_pc_apply, dim3((unsigned)n_leaves), dim3(TPB), 0, s, inv, boff, perm,
-                       lstart, n, x, trans, y);
+    hipLaunchKernelGGL(k_pc_apply, dim3((unsigned)n_leaves), dim3(TPB), 0, s, inv, boff, pidx,
+                       qidx, lstart, x, trans, y);
 }
 
 void launch_point_coulomb(hipStream_t s, int64_t npts, const double *pts, int64_t nc,

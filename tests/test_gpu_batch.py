@@ -93,3 +93,36 @@ def test_batch_single_system_and_repeat_determinism(pb, small_batch):
     a, _i, _g, _q = ctx.pb_solve_batch(one, m.Params(tol=1e-10))
     b, _i, _g, _q = ctx.pb_solve_batch(one, m.Params(tol=1e-10))
     assert a[0] == b[0]
+
+
+@pytest.mark.parametrize("leaf", [1, 16])
+def test_batch_preconditioned_matches_single_preconditioned(pb, small_batch, leaf):
+    """Per-system leaf blocks in the concatenated layout give the single-system
+    preconditioned energies and forces; leaf 1 (2x2 blocks) included."""
+    m, ctx = pb
+    _say(f"batch precond leaf {leaf}")
+    P = m.Params(tol=1e-12, precond_leaf=leaf)
+    e, infos, gpos, gq = ctx.pb_solve_batch(small_batch, P, forces=True)
+    e0, infos0, _g, _q = ctx.pb_solve_batch(small_batch, m.Params(tol=1e-12))
+    off = 0
+    for b, (v, t, pos, q) in enumerate(small_batch):
+        info, dpos, dq = ctx.pb_forces(v, t, pos, q, P)
+        n = q.shape[0]
+        assert infos[b].status == m.PB_OK
+        assert abs(e[b] - info.e_solv) <= 1e-10 * abs(info.e_solv), b
+        assert abs(e[b] - e0[b]) <= 1e-10 * abs(e0[b]), b
+        assert np.abs(gpos[off:off + n] - dpos).max() <= 1e-8 * np.abs(dpos).max()
+        assert np.abs(gq[off:off + n] - dq).max() <= 1e-8 * np.abs(dq).max()
+        off += n
+    if leaf == 16:
+        assert sum(i.iters for i in infos) < sum(i.iters for i in infos0)
+
+
+def test_batch_preconditioned_fp32_refined(pb, small_batch):
+    m, ctx = pb
+    e64, _i, _g, _q = ctx.pb_solve_batch(small_batch, m.Params(tol=1e-12))
+    e32, infos, _g, _q = ctx.pb_solve_batch(
+        small_batch, m.Params(tol=1e-8, precision=m.PB_FP32_IR, precond_leaf=16))
+    for b in range(len(small_batch)):
+        assert infos[b].status == m.PB_OK and infos[b].matvecs_fp32 > 0
+        assert abs(e32[b] - e64[b]) <= 1e-6 * abs(e64[b])
