@@ -91,8 +91,8 @@ __global__ __launch_bounds__(TPB) void kb_pack(const double *__restrict__ g, int
         } else {
             const double ap = a * xv[d.npad + j];
             w = (1.0 - 1.0 / eps) * ap;
-            pad = ap / eps;
-            f = 3.0 * a * xv[j];
+            pad = -ap / eps;
+            f = -3.0 * a * xv[j];
         }
         s.x = T(g[gi] - cx);
         s.y = T(g[gtot + gi] - cy);
@@ -143,9 +143,9 @@ __global__ __launch_bounds__(TPB) void kb_pairs_f32_fwd(const Src8<float> *__res
         tg[0][3] = float(nx);
         tg[0][4] = float(ny);
         tg[0][5] = float(nz);
-        tg[0][6] = float(nx / 3.0);
-        tg[0][7] = float(ny / 3.0);
-        tg[0][8] = float(nz / 3.0);
+        tg[0][6] = float(-nx / 3.0);
+        tg[0][7] = float(-ny / 3.0);
+        tg[0][8] = float(-nz / 3.0);
         Acc<float> aP, aQ;
         for (int t = w.t0; t < w.t1; ++t) {
             __syncthreads();

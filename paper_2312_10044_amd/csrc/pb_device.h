@@ -125,14 +125,18 @@ __device__ __forceinline__ void sweep_tile(const Src8<T> *sh, int self, T xi, T 
 }
 
 // FP32 forward sweep in reduced form.  Stream entries (mode 2):
-//   (x, y, z, w1 = (1 - 1/eps) a psi, 3 a phi n, w2 = a psi / eps),
-// targets keep n_i and n_i/3 in registers.  With md3 = 3 (a phi n_j).d,
+//   (x, y, z, w1 = (1 - 1/eps) a psi, m = -3 a phi n, w2n = -a psi / eps),
+// targets keep n_i and -n_i/3 in registers, and the separation is taken as
+// d = x_j - x_i.  With md3 = m.d (= 3 a phi n_j.(x_i - x_j)),
 // b = (tm1 + 1 - 1/eps)/3 and h3 = tm1/r^2 + kappa^2 e/3:
-//   row 1 / eps: sum_j [-(e-1)/r w2 + b md3 u]
-//   row 2:       sum_j u [tm1 (n_i/3).(3 a phi n_j) - c_x (md3 h3 + w1 - tm1 w2)]
-// which is the same algebra as the generic kernel with two multiplies
-// folded into the stream (36 VALU operations per pair).  TPT targets per
-// thread share every LDS read.
+//   row 1 / eps: sum_j [(e-1) w2n / r + b md3 u]
+//   row 2:       sum_j u [tm1 (-n_i/3).m + (n_i.d) (md3 h3 + w1 + tm1 w2n)]
+// which is the generic kernel's algebra with two multiplies folded into the
+// stream.  The signs are placed so that every fused multiply-add accumulates
+// into a dead register with no operand negated: gfx950 issues those (VOP2
+// encoding, VGPR operands) at twice the rate of three-address or negated
+// forms.  36 VALU operations per pair; TPT targets per thread share every
+// LDS read.
 struct CoefF32 {
     float kappa, kexp, c13, k23;
 };
@@ -146,7 +150,7 @@ __device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&t
         const Src8<float> s = sh[jj];
 #pragma unroll
         for (int t = 0; t < TPT; ++t) {
-            const float dx = tg[t][0] - s.x, dy = tg[t][1] - s.y, dz = tg[t][2] - s.z;
+            const float dx = s.x - tg[t][0], dy = s.y - tg[t][1], dz = s.z - tg[t][2];
             const float r2 = dx * dx + dy * dy + dz * dz;
             float ir = __builtin_amdgcn_rsqf(r2);
             if (DSLOT == t)
@@ -157,17 +161,17 @@ __device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&t
             const float kr = cf.kappa * r;
             const float e = __builtin_amdgcn_exp2f(cf.kexp * r);
             const float em1 = e - 1.f;
+            P[t] = fmaf(em1, ir * s.pad, P[t]);
             const float tm1 = fmaf(kr, e, em1);
             const float cxd = tg[t][3] * dx + tg[t][4] * dy + tg[t][5] * dz;
             const float md3 = s.mx * dx + s.my * dy + s.mz * dz;
             const float nm = tg[t][6] * s.mx + tg[t][7] * s.my + tg[t][8] * s.mz;
             const float b = fmaf(tm1, 0.333333343f, cf.c13);
-            P[t] = fmaf(-em1, ir * s.pad, P[t]);
             P[t] = fmaf(b * md3, u, P[t]);
             const float h3 = fmaf(tm1, ir2, cf.k23 * e);
-            const float cqw = fmaf(-tm1, s.pad, s.w);
+            const float cqw = fmaf(tm1, s.pad, s.w);
             const float inner = fmaf(md3, h3, cqw);
-            Q[t] = fmaf(u, fmaf(-cxd, inner, tm1 * nm), Q[t]);
+            Q[t] = fmaf(u, fmaf(cxd, inner, tm1 * nm), Q[t]);
         }
     }
 }

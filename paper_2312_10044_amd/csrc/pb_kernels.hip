@@ -130,8 +130,8 @@ __global__ __launch_bounds__(TPB) void k_pack(const double *__restrict__ g, int6
         } else {
             const double ap = a * x[n + j];
             w = (1.0 - 1.0 / eps) * ap;   // w1
-            pad = ap / eps;               // w2
-            f = 3.0 * a * x[j];
+            pad = -ap / eps;              // w2n
+            f = -3.0 * a * x[j];
         }
         s.x = T(g[j] - cx);
         s.y = T(g[npad + j] - cy);
@@ -208,9 +208,9 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_fwd(const Src8<float> *__rest
         tg[t][3] = float(nx);
         tg[t][4] = float(ny);
         tg[t][5] = float(nz);
-        tg[t][6] = float(nx / 3.0);
-        tg[t][7] = float(ny / 3.0);
-        tg[t][8] = float(nz / 3.0);
+        tg[t][6] = float(-nx / 3.0);
+        tg[t][7] = float(-ny / 3.0);
+        tg[t][8] = float(-nz / 3.0);
     }
     CoefF32 cf;
     cf.kappa = float(pp.kappa);
