@@ -153,9 +153,9 @@ __global__ __launch_bounds__(TPB) void kb_pairs_f32_fwd(const Src8<float> *__res
             __syncthreads();
             float P[1] = {0.f}, Q[1] = {0.f};
             if (t == w.tb)
-                sweep_f32<1, 0>(sh, tg, cf, P, Q);
+                sweep_f32<1, 0, false>(sh, tg, cf, P, Q);
             else
-                sweep_f32<1, -1>(sh, tg, cf, P, Q);
+                sweep_f32<1, -1, false>(sh, tg, cf, P, Q);
             aP.add(P[0]);
             aQ.add(Q[0]);
         }

@@ -120,18 +120,21 @@ int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
     const PairParams pp = pair_params(c, p);
     const double eps = pp.eps;
     const double npairs = (double)g.n * (double)(g.n - 1);
-    double scale1 = 1.0;
+    double scale1 = 1.0, scale2 = 1.0;
     if (fast32) {
+        const double sig = f32_sigma(pp.kappa);
         TRY(ensure(c, c->src32, sizeof(float) * 8 * g.npad));
-        launch_pack_f32(c->stream, g, x, as<float>(c->src32), 2, pp.cx, pp.cy, pp.cz, eps);
+        launch_pack_f32(c->stream, g, x, as<float>(c->src32), 2, pp.cx, pp.cy, pp.cz, eps, sig);
         LAUNCHCHK();
         ProfScope ps(c, PB_KERNEL_PAIRS_FP32, npairs);
         launch_pairs_f32_fwd(c->stream, g, as<float>(c->src32), sw, pp, c->f32_tpt,
                              as<double>(c->part));
-        scale1 = eps;   // the reduced form sums row 1 divided by eps
+        // the reduced form sums row 1 divided by eps, in units of 1/kappa
+        scale1 = eps * sig * sig;
+        scale2 = sig * sig * sig;
     } else if (precision == PB_FP32_IR) {
         TRY(ensure(c, c->src32, sizeof(float) * 8 * g.npad));
-        launch_pack_f32(c->stream, g, x, as<float>(c->src32), 1, pp.cx, pp.cy, pp.cz, eps);
+        launch_pack_f32(c->stream, g, x, as<float>(c->src32), 1, pp.cx, pp.cy, pp.cz, eps, 1.0);
         LAUNCHCHK();
         ProfScope ps(c, PB_KERNEL_PAIRS_FP32_T, npairs);
         launch_pairs_f32(c->stream, g, as<float>(c->src32), sw, pp, transpose,
@@ -146,7 +149,7 @@ int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
     }
     LAUNCHCHK();
     launch_matvec_finish(c->stream, g, as<double>(c->part), sw.n_chunks, x, 0.5 * (1.0 + eps),
-                         0.5 * (1.0 + 1.0 / eps), transpose, scale1, y);
+                         0.5 * (1.0 + 1.0 / eps), transpose, scale1, scale2, y);
     LAUNCHCHK();
     return PB_OK;
 }

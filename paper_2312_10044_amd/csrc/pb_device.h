@@ -124,7 +124,8 @@ __device__ __forceinline__ void sweep_tile(const Src8<T> *sh, int self, T xi, T 
     }
 }
 
-// FP32 forward sweep in reduced form.  Stream entries (mode 2):
+// FP32 forward sweep in reduced form.  Lengths are in units of 1/kappa
+// (SCALED, kappa > 0) or plain (kappa = 0).  Stream entries (mode 2):
 //   (x, y, z, w1 = (1 - 1/eps) a psi, m = -3 a phi n, w2n = -a psi / eps),
 // targets keep n_i and -n_i/3 in registers, and the separation is taken as
 // d = x_j - x_i.  With md3 = m.d (= 3 a phi n_j.(x_i - x_j)),
@@ -132,16 +133,16 @@ __device__ __forceinline__ void sweep_tile(const Src8<T> *sh, int self, T xi, T 
 //   row 1 / eps: sum_j [(e-1) w2n / r + b md3 u]
 //   row 2:       sum_j u [tm1 (-n_i/3).m + (n_i.d) (md3 h3 + w1 + tm1 w2n)]
 // which is the generic kernel's algebra with two multiplies folded into the
-// stream.  The signs are placed so that every fused multiply-add accumulates
-// into a dead register with no operand negated: gfx950 issues those (VOP2
-// encoding, VGPR operands) at twice the rate of three-address or negated
-// forms.  36 VALU operations per pair; TPT targets per thread share every
-// LDS read.
+// stream.  Scaling lengths by kappa multiplies row 1 by kappa^2 and row 2 by
+// kappa^3 (applied by the caller) and makes kappa r the distance itself.
+// The signs are placed so that every fused multiply-add accumulates into a
+// dead register with no operand negated.  35 VALU operations per pair (36
+// unscaled); TPT targets per thread share every LDS read.
 struct CoefF32 {
     float kappa, kexp, c13, k23;
 };
 
-template <int TPT, int DSLOT>
+template <int TPT, int DSLOT, bool SCALED>
 __device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&tg)[TPT][9],
                                           const CoefF32 &cf, float (&P)[TPT], float (&Q)[TPT])
 {
@@ -158,7 +159,7 @@ __device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&t
             const float ir2 = ir * ir;
             const float u = ir2 * ir;
             const float r = r2 * ir;
-            const float kr = cf.kappa * r;
+            const float kr = SCALED ? r : cf.kappa * r;
             const float e = __builtin_amdgcn_exp2f(cf.kexp * r);
             const float em1 = e - 1.f;
             P[t] = fmaf(em1, ir * s.pad, P[t]);

@@ -50,11 +50,15 @@ void launch_geometry(hipStream_t s, int64_t n_vert, int64_t n_tri, const double 
 // Packed source stream: 8 values per source (x, y, z, w, mx, my, mz, pad).
 // mode 0 (forward): w = a_j psi_j, m = a_j phi_j n_j.
 // mode 1 (transpose): w = l1_j, m = l2_j n_j.
-// mode 2 (FP32 forward, reduced form): w = (1-1/eps) a psi, m = 3 a phi n,
-//        pad = a psi / eps.
+// mode 2 (FP32 forward, reduced form): w = (1-1/eps) a psi / sigma,
+//        m = -3 a phi n, pad = -a psi / (eps sigma), positions times sigma.
 void launch_pack_f64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode);
 void launch_pack_f32(hipStream_t s, const Geo &geo, const double *x, float *src, int mode,
-                     double cx, double cy, double cz, double eps);
+                     double cx, double cy, double cz, double eps, double sigma);
+// Length scale of the reduced FP32 form: coordinates are measured in units of
+// 1/kappa, so kappa r is the distance itself (1 when kappa = 0).  Row 1 of
+// the sweep then carries a factor sigma^2 and row 2 a factor sigma^3.
+inline double f32_sigma(double kappa) { return kappa > 0.0 ? kappa : 1.0; }
 
 // Pair sweep of the matvec: part[(o * n_chunks + c) * npad + i], o in {0,1}.
 void launch_pairs_f64(hipStream_t s, const Geo &geo, const double *src, const Sweep &sw,
@@ -64,10 +68,11 @@ void launch_pairs_f32(hipStream_t s, const Geo &geo, const float *src, const Swe
 // FP32 forward sweep (mode-2 stream), tpt in {1, 2} targets per thread.
 void launch_pairs_f32_fwd(hipStream_t s, const Geo &geo, const float *src, const Sweep &sw,
                           const PairParams &pp, int tpt, double *part);
-// y = diag * x - (1/4pi) [scale1 * sum_c part0; sum_c part1]  (times a_i when transposed)
+// y = diag * x - (1/4pi) [scale1 * sum_c part0; scale2 * sum_c part1]
+// (times a_i when transposed)
 void launch_matvec_finish(hipStream_t s, const Geo &geo, const double *part, int n_chunks,
                           const double *x, double alpha, double beta, int transpose,
-                          double scale1, double *y);
+                          double scale1, double scale2, double *y);
 
 // Source terms b = [S1; S2].
 void launch_source(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,

@@ -111,7 +111,7 @@ template <typename T>
 __global__ __launch_bounds__(TPB) void k_pack(const double *__restrict__ g, int64_t n,
                                               int64_t npad, const double *__restrict__ x,
                                               Src8<T> *__restrict__ src, int mode, double cx,
-                                              double cy, double cz, double eps)
+                                              double cy, double cz, double eps, double sigma)
 {
     const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (j >= npad)
@@ -128,21 +128,21 @@ __global__ __launch_bounds__(TPB) void k_pack(const double *__restrict__ g, int6
             w = x[j];           // l1_j
             f = x[n + j];       // l2_j
         } else {
-            const double ap = a * x[n + j];
+            const double ap = a * x[n + j] / sigma;
             w = (1.0 - 1.0 / eps) * ap;   // w1
             pad = -ap / eps;              // w2n
             f = -3.0 * a * x[j];
         }
-        s.x = T(g[j] - cx);
-        s.y = T(g[npad + j] - cy);
-        s.z = T(g[2 * npad + j] - cz);
+        s.x = T((g[j] - cx) * sigma);
+        s.y = T((g[npad + j] - cy) * sigma);
+        s.z = T((g[2 * npad + j] - cz) * sigma);
         s.w = T(w);
         s.mx = T(f * g[3 * npad + j]);
         s.my = T(f * g[4 * npad + j]);
         s.mz = T(f * g[5 * npad + j]);
         s.pad = T(pad);
     } else {
-        s.x = T(FAR_SRC - cx);
+        s.x = T((FAR_SRC - cx) * sigma);
         s.y = T(0.0);
         s.z = T(0.0);
         s.w = s.mx = s.my = s.mz = T(0.0);
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(TPB) void k_pairs(const Src8<T> *__restrict__ src,
     part[(int64_t)(sw.n_chunks + chunk) * npad + i] = TRANS ? P : Q;
 }
 
-template <int TPT>
+template <int TPT, bool SCALED>
 __global__ __launch_bounds__(TPB) void k_pairs_f32_fwd(const Src8<float> *__restrict__ src,
                                                        const double *__restrict__ g, int64_t npad,
                                                        Sweep sw, PairParams pp,
@@ -197,13 +197,15 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_fwd(const Src8<float> *__rest
     const int b = blockIdx.x;
     const int chunk = b % sw.n_chunks;
     const int tb = b / sw.n_chunks;
+    const double sig = SCALED ? pp.kappa : 1.0;   // f32_sigma(pp.kappa)
+    const double kap = pp.kappa / sig;             // kappa in scaled units
     float tg[TPT][9];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
         const int64_t i = ((int64_t)tb * TPT + t) * TPB + threadIdx.x;
-        tg[t][0] = float(g[i] - pp.cx);
-        tg[t][1] = float(g[npad + i] - pp.cy);
-        tg[t][2] = float(g[2 * npad + i] - pp.cz);
+        tg[t][0] = float((g[i] - pp.cx) * sig);
+        tg[t][1] = float((g[npad + i] - pp.cy) * sig);
+        tg[t][2] = float((g[2 * npad + i] - pp.cz) * sig);
         const double nx = g[3 * npad + i], ny = g[4 * npad + i], nz = g[5 * npad + i];
         tg[t][3] = float(nx);
         tg[t][4] = float(ny);
@@ -213,10 +215,10 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_fwd(const Src8<float> *__rest
         tg[t][8] = float(-nz / 3.0);
     }
     CoefF32 cf;
-    cf.kappa = float(pp.kappa);
-    cf.kexp = float(-pp.kappa * 1.4426950408889634074);
+    cf.kappa = float(kap);
+    cf.kexp = float(-kap * 1.4426950408889634074);
     cf.c13 = float((1.0 - 1.0 / pp.eps) / 3.0);
-    cf.k23 = float(pp.kappa * pp.kappa / 3.0);
+    cf.k23 = float(kap * kap / 3.0);
     Acc<float> aP[TPT], aQ[TPT];
     const int t0 = chunk * sw.tiles_per_chunk;
     const int t1 = min(sw.n_tiles, t0 + sw.tiles_per_chunk);
@@ -230,11 +232,11 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_fwd(const Src8<float> *__rest
             P[k] = Q[k] = 0.f;
         const int ds = t - tb * TPT;   // slot whose target lies in this tile
         if (ds == 0)
-            sweep_f32<TPT, 0>(sh, tg, cf, P, Q);
+            sweep_f32<TPT, 0, SCALED>(sh, tg, cf, P, Q);
         else if (TPT > 1 && ds == 1)
-            sweep_f32<TPT, 1>(sh, tg, cf, P, Q);
+            sweep_f32<TPT, 1, SCALED>(sh, tg, cf, P, Q);
         else
-            sweep_f32<TPT, -1>(sh, tg, cf, P, Q);
+            sweep_f32<TPT, -1, SCALED>(sh, tg, cf, P, Q);
 #pragma unroll
         for (int k = 0; k < TPT; ++k) {
             aP[k].add(P[k]);
@@ -254,7 +256,8 @@ __global__ __launch_bounds__(TPB) void k_matvec_finish(const double *__restrict_
                                                        const double *__restrict__ area,
                                                        const double *__restrict__ x,
                                                        double alpha, double beta, int trans,
-                                                       double scale1, double *__restrict__ y)
+                                                       double scale1, double scale2,
+                                                       double *__restrict__ y)
 {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (i >= n)
@@ -266,7 +269,7 @@ __global__ __launch_bounds__(TPB) void k_matvec_finish(const double *__restrict_
     }
     const double sc = trans ? area[i] * INV_4PI : INV_4PI;
     y[i] = alpha * x[i] - sc * scale1 * s1;
-    y[n + i] = beta * x[n + i] - sc * s2;
+    y[n + i] = beta * x[n + i] - sc * scale2 * s2;
 }
 
 // ---- source terms ----------------------------------------------------------
@@ -849,14 +852,15 @@ void launch_pack_f64(hipStream_t s, const Geo &geo, const double *x, double *src
 {
     hipLaunchKernelGGL(k_pack<double>, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
                        geo.npad, x, reinterpret_cast<Src8<double> *>(src), mode, 0.0, 0.0, 0.0,
-                       1.0);
+                       1.0, 1.0);
 }
 
 void launch_pack_f32(hipStream_t s, const Geo &geo, const double *x, float *src, int mode,
-                     double cx, double cy, double cz, double eps)
+                     double cx, double cy, double cz, double eps, double sigma)
 {
     hipLaunchKernelGGL(k_pack<float>, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
-                       geo.npad, x, reinterpret_cast<Src8<float> *>(src), mode, cx, cy, cz, eps);
+                       geo.npad, x, reinterpret_cast<Src8<float> *>(src), mode, cx, cy, cz, eps,
+                       sigma);
 }
 
 void launch_pairs_f32_fwd(hipStream_t s, const Geo &geo, const float *src, const Sweep &sw,
@@ -864,12 +868,19 @@ void launch_pairs_f32_fwd(hipStream_t s, const Geo &geo, const float *src, const
 {
     const dim3 grid(sw.n_tblocks * sw.n_chunks);
     const auto *p = reinterpret_cast<const Src8<float> *>(src);
-    if (tpt == 2)
-        hipLaunchKernelGGL(k_pairs_f32_fwd<2>, grid, dim3(TPB), 0, s, p, geo.g, geo.npad, sw, pp,
-                           part);
+    const bool scaled = pp.kappa > 0.0;
+    if (tpt == 2 && scaled)
+        hipLaunchKernelGGL((k_pairs_f32_fwd<2, true>), grid, dim3(TPB), 0, s, p, geo.g, geo.npad,
+                           sw, pp, part);
+    else if (tpt == 2)
+        hipLaunchKernelGGL((k_pairs_f32_fwd<2, false>), grid, dim3(TPB), 0, s, p, geo.g, geo.npad,
+                           sw, pp, part);
+    else if (scaled)
+        hipLaunchKernelGGL((k_pairs_f32_fwd<1, true>), grid, dim3(TPB), 0, s, p, geo.g, geo.npad,
+                           sw, pp, part);
     else
-        hipLaunchKernelGGL(k_pairs_f32_fwd<1>, grid, dim3(TPB), 0, s, p, geo.g, geo.npad, sw, pp,
-                           part);
+        hipLaunchKernelGGL((k_pairs_f32_fwd<1, false>), grid, dim3(TPB), 0, s, p, geo.g, geo.npad,
+                           sw, pp, part);
 }
 
 void launch_pairs_f64(hipStream_t s, const Geo &geo, const double *src, const Sweep &sw,
@@ -902,10 +913,11 @@ void launch_pairs_f32(hipStream_t s, const Geo &geo, const float *src, const Swe
 
 void launch_matvec_finish(hipStream_t s, const Geo &geo, const double *part, int n_chunks,
                           const double *x, double alpha, double beta, int transpose,
-                          double scale1, double *y)
+                          double scale1, double scale2, double *y)
 {
     hipLaunchKernelGGL(k_matvec_finish, dim3(blocks_for(geo.n)), dim3(TPB), 0, s, part, n_chunks,
-                       geo.npad, geo.n, geo.g + 6 * geo.npad, x, alpha, beta, transpose, scale1, y);
+                       geo.npad, geo.n, geo.g + 6 * geo.npad, x, alpha, beta, transpose, scale1,
+                       scale2, y);
 }
 
 void launch_source(hipStream_t s, const Geo &geo, int64_t nc, const double *pos,
