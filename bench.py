@@ -40,15 +40,24 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_digest() -> str:
+PAIRWISE = 8   # pb_set_sweep_config kind of the pairwise sweep (PB_SWEEP_PAIRWISE)
+
+
+def fp32_kernel_name(kind: int) -> str:
+    return "k_pairs_f32_sym" if kind == PAIRWISE else "k_pairs_f32_fwd"
+
+
+def kernel_digest(kind: int) -> str:
     """SHA-256 of the FP32 forward sweep's source: the shared device header
-    plus the text of the k_pairs_f32_fwd kernel."""
+    plus the text of the sweep kernel that `kind` selects."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2312_10044_amd", "csrc")
     dev = open(os.path.join(csrc, "pb_device.h")).read()
     ker = open(os.path.join(csrc, "pb_kernels.hip")).read()
-    a = ker.index("template <int TPT>\n__global__ __launch_bounds__(TPB) void k_pairs_f32_fwd(")
-    b = ker.index("\n}\n", a) + 3
+    name = fp32_kernel_name(kind)
+    b0 = ker.index(f" void {name}(")
+    a = ker.rindex("template <", 0, b0)
+    b = ker.index("\n}\n", b0) + 3
     return hashlib.sha256((dev + ker[a:b]).encode()).hexdigest()
 
 
@@ -59,7 +68,7 @@ def measured_traffic(n_tri, sweep):
         rec = json.load(open(TRAFFIC_RECORD))
     except (OSError, ValueError):
         return None
-    if (rec.get("kernel_digest") != kernel_digest() or rec.get("n_tri") != n_tri
+    if (rec.get("kernel_digest") != kernel_digest(sweep[0]) or rec.get("n_tri") != n_tri
             or [rec.get("targets_per_thread"), rec.get("target_waves")] != list(sweep)):
         return None
     return float(rec["bytes_per_launch"])
@@ -169,6 +178,62 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_tree(args):
+    """Treecode matvec (theta 0.8, p 3, N0 100 unless given) against the
+    direct sums on the same surface: kernel time per matvec (cluster moments
+    plus tree walk; the host-side tree build is reported separately as part
+    of the call's wall time) and the error against the FP64 direct matvec."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2312_10044_amd import Context, Params, PB_FP64, PB_FP32_IR, PB_SWEEP_PAIRWISE
+    from paper_2312_10044_amd import pbsolve as pbs
+
+    w = synth.star_protein() if args.workload == "star81920" else synth.large_star_protein()
+    N = w.n_tri
+    ctx = Context(0)
+    base = Params(eps_in=w.eps_in, eps_out=w.eps_out, kappa=w.kappa)
+    x = np.random.default_rng(0).normal(size=2 * N)
+    out = {"mode": "tree", "n_tri": N, "theta": args.theta, "order": args.order,
+           "leaf_size": args.leaf}
+    y64 = ctx.pb_matvec(w.verts, w.tris, x, base, precision=PB_FP64)
+    ctx.set_sweep_config(PB_SWEEP_PAIRWISE, 0)
+    ctx.pb_matvec(w.verts, w.tris, x, base, precision=PB_FP32_IR)
+    rows = []
+    for kid, prec, label in ((pbs.PB_KERNEL_PAIRS_FP64, PB_FP64, "direct_fp64"),
+                             (pbs.PB_KERNEL_PAIRS_FP32, PB_FP32_IR, "direct_fp32_pairwise")):
+        ctx.profile_reset()
+        ctx.profile_enable(True)
+        for _ in range(max(1, args.steps)):
+            y = ctx.pb_matvec(w.verts, w.tris, x, base, precision=prec)
+        ctx.profile_enable(False)
+        n_l, ms_l, _p = ctx.profile_read(kid)
+        out[label] = {"ms": ms_l / n_l,
+                      "rel_err_vs_fp64": float(np.abs(y - y64).max() / np.abs(y64).max())}
+    y, cnt = ctx.pb_matvec_tree(w.verts, w.tris, x, base, theta=args.theta, order=args.order,
+                                leaf_size=args.leaf, with_counts=True)
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps)):
+        y = ctx.pb_matvec_tree(w.verts, w.tris, x, base, theta=args.theta, order=args.order,
+                               leaf_size=args.leaf)
+    wall = (time.perf_counter() - t0) / max(1, args.steps)
+    ctx.profile_enable(False)
+    n_l, ms_l, _p = ctx.profile_read(pbs.PB_KERNEL_TREE)
+    out["treecode"] = {"ms": ms_l / n_l, "call_wall_ms": wall * 1e3,
+                       "rel_err_vs_fp64": float(np.abs(y - y64).max() / np.abs(y64).max()),
+                       "particle_cluster": cnt[0], "particle_particle": cnt[1],
+                       "nodes": cnt[2]}
+    out["speedup_tree_vs_fp64_direct"] = out["direct_fp64"]["ms"] / out["treecode"]["ms"]
+    out["speedup_tree_vs_fp32_pairwise"] = (out["direct_fp32_pairwise"]["ms"]
+                                            / out["treecode"]["ms"])
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,10 +243,15 @@ def main():
     ap.add_argument("--workload", choices=["star81920", "star327680"], default="star81920")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--mode", choices=["solve", "matvec", "copy", "batch"], default="solve",
+    ap.add_argument("--theta", type=float, default=0.8, help="treecode MAC parameter (mode tree)")
+    ap.add_argument("--order", type=int, default=3, help="treecode Taylor order (mode tree)")
+    ap.add_argument("--leaf", type=int, default=100, help="treecode leaf size N0 (mode tree)")
+    ap.add_argument("--mode", choices=["solve", "matvec", "copy", "batch", "tree"],
+                    default="solve",
                     help="solve: the benchmark; matvec: only --steps matvecs of --precision "
                          "(for counter runs); copy: a device copy of --copy-mib MiB (the "
-                         "reference kernel that calibrates FETCH_SIZE/WRITE_SIZE)")
+                         "reference kernel that calibrates FETCH_SIZE/WRITE_SIZE); batch: 64 "
+                         "uneven systems in one call; tree: treecode matvec vs the direct sums")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--precond-leaf", type=int, default=16,
                     help="leaf size of the block-diagonal preconditioner (0 = none)")
@@ -215,6 +285,9 @@ def main():
         return
     if args.mode == "batch":
         run_batch(args)
+        return
+    if args.mode == "tree":
+        run_tree(args)
         return
     if args.workload == "star81920":
         w = synth.star_protein()
@@ -253,7 +326,8 @@ def main():
         kid = pbs.PB_KERNEL_PAIRS_FP32 if prec == PB_FP32_IR else pbs.PB_KERNEL_PAIRS_FP64
         n_l, ms_l, pr_l = ctx.profile_read(kid)
         print(json.dumps({"mode": "matvec", "precision": args.precision, "n_tri": N,
-                          "kernel_digest": kernel_digest(),
+                          "kernel": fp32_kernel_name(tuned[0]),
+                          "kernel_digest": kernel_digest(tuned[0]),
                           "launches": n_l, "avg_ms": ms_l / n_l,
                           "pairs_per_launch": pr_l / n_l,
                           "tflops_algorithmic": FLOP_PER_PAIR * pr_l / (ms_l * 1e-3) / 1e12,
@@ -376,7 +450,8 @@ def main():
         "compare": compare,
         "roofline": {
             "bound": "alu",
-            "kernel": "k_pairs<float,false>" if prec == PB_FP32_IR else "k_pairs<double,false>",
+            "kernel": (fp32_kernel_name(tuned[0]) if prec == PB_FP32_IR
+                       else "k_pairs<double,false>"),
             "achieved": achieved / 1e12,
             "peak": peak / 1e12,
             "unit": "TFLOP/s",

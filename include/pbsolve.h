@@ -225,15 +225,38 @@ int pb_precond_leaves(pb_ctx *ctx, const pb_surface *s, int leaf, int32_t *perm,
 int pb_precond_apply(pb_ctx *ctx, const pb_surface *s, const pb_params *p, const double *x,
                      double *y, int transpose);
 
+/* ---- treecode matvec (Sec. 2.2.3) ----------------------------------------- */
+/* y = A x with the pair sums evaluated by the treecode of Sec. 2.2.3 (eq.
+ * particle_cluster_form) instead of the direct sum: octree leaves of at most
+ * `leaf_size` points (N0), multipole acceptance criterion r_c / R <= theta
+ * (0 <= theta < 1), and the Taylor polynomial of order `order` (p, 0..5) of
+ * each kernel K1..K4 in the source position about the cluster centre.  The
+ * result approximates pb_matvec(..., transpose = 0, PB_FP64); theta = 0
+ * reproduces it up to rounding.  FP64 throughout.  p->eps_in, eps_out and
+ * kappa are used.  x, y: [2 n_tri] host arrays.  counts (may be NULL), if
+ * given, receives {particle-cluster interactions, particle-particle pairs,
+ * tree nodes} of this matvec.  The paper's setting is theta = 0.8, p = 3,
+ * N0 = 100. */
+int pb_matvec_tree(pb_ctx *ctx, const pb_surface *s, const pb_params *p, double theta,
+                   int order, int leaf_size, const double *x, double *y, int64_t *counts);
+
 /* ---- launch configuration and autotuning ------------------------------- */
-/* The FP32 forward pair sweep (the hot loop of PB_FP32_IR solves) keeps
- * `targets_per_thread` collocation points (1 or 2) in registers per thread
- * and splits the source range into chunks so that one launch holds about
- * `target_waves` wavefronts.  0 leaves a value unchanged.  Defaults: 1, 32768. */
+/* The FP32 forward pair sweep (the hot loop of PB_FP32_IR solves) comes in
+ * two kinds, selected by `targets_per_thread`:
+ *   1 or 2             per-target sweep: that many collocation points per
+ *                      thread, the source range split into chunks;
+ *   PB_SWEEP_PAIRWISE  pairwise sweep: each unordered pair (i, j) is
+ *                      evaluated once and feeds both row i and row j (the
+ *                      distance, exp(-kappa r) and the kernel factors they
+ *                      share are computed once).
+ * Either kind sizes one launch to about `target_waves` wavefronts.  0 leaves a
+ * value unchanged.  Defaults: PB_SWEEP_PAIRWISE, 131072.  Both kinds give the
+ * same matvec up to FP32 rounding; only the summation order differs. */
+#define PB_SWEEP_PAIRWISE 8
 int pb_set_sweep_config(pb_ctx *ctx, int targets_per_thread, int target_waves);
 int pb_get_sweep_config(pb_ctx *ctx, int *targets_per_thread, int *target_waves);
-/* Time every candidate configuration (targets_per_thread in {1, 2} x
- * target_waves in {8192, 16384, 32768, 65536, 131072}) on this surface with HIP events
+/* Time every candidate configuration (kind in {PB_SWEEP_PAIRWISE, 1, 2} x
+ * target_waves in {8192, 16384, 32768, 65536, 131072, 262144}) on this surface with HIP events
  * and keep the fastest in the context.  best_* may be NULL. */
 int pb_autotune(pb_ctx *ctx, const pb_surface *s, const pb_params *p, int *best_tpt,
                 int *best_waves);
@@ -250,7 +273,8 @@ int pb_autotune(pb_ctx *ctx, const pb_surface *s, const pb_params *p, int *best_
 #define PB_KERNEL_PAIRS_FP32_T 3    /* transpose sweep, FP32 */
 #define PB_KERNEL_SOURCE 4          /* source terms */
 #define PB_KERNEL_CHARGE 5          /* reaction potential / solid angle at the charges */
-#define PB_KERNEL_COUNT 6
+#define PB_KERNEL_TREE 6            /* treecode matvec: cluster moments + tree walk */
+#define PB_KERNEL_COUNT 7
 
 int pb_profile_enable(pb_ctx *ctx, int enable);
 int pb_profile_reset(pb_ctx *ctx);

@@ -178,14 +178,15 @@ def build_tree(cen: np.ndarray, n0: int) -> Node:
                 float(np.max(0.5 * (hi - lo))), 0)
 
 
-def interaction_lists(tree: Node, cen: np.ndarray, theta: float):
-    """For every target: the clusters accepted by the MAC (far) and the
-    leaves summed directly (near), from a walk that starts at the root."""
+def interaction_lists(tree: Node, cen: np.ndarray, theta: float, rows=None):
+    """For every target (or those in `rows`): the clusters accepted by the MAC
+    (far) and the leaves summed directly (near), from a walk that starts at
+    the root."""
     cen = f64(cen)
     n = cen.shape[0]
     far = [[] for _ in range(n)]
     near = [[] for _ in range(n)]
-    for i in range(n):
+    for i in (range(n) if rows is None else rows):
         x = cen[i]
         stack = [tree]
         while stack:
@@ -274,16 +275,18 @@ def far_rows(T0, Tk, alg: SeriesAlgebra, M, D, nrm_t, eps: float, p: int):
 
 
 def matvec(g: Geometry, eps: float, kappa: float, xi: np.ndarray, theta: float, p: int,
-           n0: int):
-    """y = A xi with the pair sums replaced by the treecode approximation."""
+           n0: int, rows=None):
+    """y = A xi with the pair sums replaced by the treecode approximation.
+    With `rows`, only those rows of both blocks are formed and (y1, y2) for
+    them is returned."""
     n = g.n
     xi = f64(xi)
     phi, psi = xi[:n], xi[n:]
     tree = build_tree(g.cen, n0)
-    far, near = interaction_lists(tree, g.cen, theta)
+    far, near = interaction_lists(tree, g.cen, theta, rows)
     s1 = np.zeros(n)
     s2 = np.zeros(n)
-    for i in range(n):
+    for i in (range(n) if rows is None else rows):
         if near[i]:
             j = np.concatenate([c.idx for c in near[i]])
             a1, a2 = _direct_rows(g, eps, kappa, phi, psi, i, j)
@@ -302,6 +305,10 @@ def matvec(g: Geometry, eps: float, kappa: float, xi: np.ndarray, theta: float, 
         np.add.at(s1, tl, r1)
         np.add.at(s2, tl, r2)
     inv4pi = 1.0 / (4.0 * np.pi)
+    if rows is not None:
+        rows = np.asarray(rows)
+        return (0.5 * (1.0 + eps) * phi[rows] - inv4pi * s1[rows],
+                0.5 * (1.0 + 1.0 / eps) * psi[rows] - inv4pi * s2[rows])
     y = np.empty(2 * n)
     y[:n] = 0.5 * (1.0 + eps) * phi - inv4pi * s1
     y[n:] = 0.5 * (1.0 + 1.0 / eps) * psi - inv4pi * s2

@@ -17,6 +17,7 @@ from .pbsolve import (  # noqa: F401
     PB_ERR_OOM,
     PB_FP64,
     PB_FP32_IR,
+    PB_SWEEP_PAIRWISE,
     load_library,
     exported_symbols,
 )

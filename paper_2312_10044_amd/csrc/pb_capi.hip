@@ -110,9 +110,53 @@ PairParams pair_params(pb_ctx *c, const pb_params *p)
 
 // ---- matvec (steps 3 and 6) -----------------------------------------------------
 
+// Pairwise FP32 sweep: every unordered pair once, both directions.
+int apply_pairwise(pb_ctx *c, const pb_params *p, const double *x, double *y)
+{
+    const Geo &g = c->g;
+    if (c->sym_plan.npad != g.npad || c->sym_waves != c->f32_waves) {
+        std::vector<int32_t> items, row_start;
+        const SymPlan pl = plan_sym(g.npad, c->f32_waves, items, row_start);
+        TRY(ensure(c, c->sym_items, sizeof(int32_t) * items.size()));
+        TRY(ensure(c, c->sym_rowstart, sizeof(int32_t) * row_start.size()));
+        HIPCHK(hipMemcpyAsync(c->sym_items.p, items.data(), sizeof(int32_t) * items.size(),
+                              hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->sym_rowstart.p, row_start.data(),
+                              sizeof(int32_t) * row_start.size(), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));   // host vectors go out of scope
+        c->sym_plan = pl;
+        c->sym_waves = c->f32_waves;
+    }
+    const SymPlan &pl = c->sym_plan;
+    const int64_t T = pl.n_tiles;
+    TRY(ensure(c, c->sym_src, sizeof(float) * 12 * g.npad));
+    TRY(ensure(c, c->sym_rowpart, sizeof(double) * 2 * TILE * (size_t)pl.n_items));
+    TRY(ensure(c, c->sym_colpart,
+               sizeof(float) * 2 * TILE * (size_t)std::max<int64_t>(T * (T - 1) / 2, 1)));
+    const PairParams pp = pair_params(c, p);
+    const double eps = pp.eps, sig = f32_sigma(pp.kappa);
+    launch_pack_sym(c->stream, g, x, as<float>(c->sym_src), pp.cx, pp.cy, pp.cz, eps, sig);
+    LAUNCHCHK();
+    {
+        ProfScope ps(c, PB_KERNEL_PAIRS_FP32, (double)g.n * (double)(g.n - 1));
+        launch_pairs_f32_sym(c->stream, as<float>(c->sym_src), as<int32_t>(c->sym_items),
+                             pl.n_items, pl.n_tiles, pp, as<double>(c->sym_rowpart),
+                             as<float>(c->sym_colpart));
+    }
+    LAUNCHCHK();
+    launch_sym_finish(c->stream, g, as<double>(c->sym_rowpart), as<float>(c->sym_colpart),
+                      as<int32_t>(c->sym_rowstart), pl.n_tiles, x, 0.5 * (1.0 + eps),
+                      0.5 * (1.0 + 1.0 / eps), eps * sig * sig, sig * sig * sig, y);
+    LAUNCHCHK();
+    return PB_OK;
+}
+
 int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const double *x, double *y)
 {
     const Geo &g = c->g;
+    if (precision == PB_FP32_IR && !transpose && c->f32_tpt == PB_SWEEP_PAIRWISE)
+        return apply_pairwise(c, p, x, y);
     const bool fast32 = precision == PB_FP32_IR && !transpose;
     const Sweep sw = fast32 ? plan_sweep(g.npad, g.npad, c->f32_waves, c->f32_tpt)
                             : plan_sweep(g.npad, g.npad, TARGET_WAVES);
@@ -881,7 +925,10 @@ void pb_destroy(pb_ctx *c)
                       &c->in_tri, &c->in_pos, &c->in_q, &c->io_x, &c->io_y, &c->pc_idx,
                       &c->pc_inv, &c->b_geo, &c->b_desc, &c->b_map, &c->b_items, &c->b_src,
                       &c->b_part, &c->b_vec, &c->b_V, &c->b_state, &c->b_red, &c->b_chg,
-                      &c->b_pc_idx, &c->b_pc_inv};
+                      &c->b_pc_idx, &c->b_pc_inv, &c->sym_src, &c->sym_items,
+                      &c->sym_rowstart, &c->sym_rowpart, &c->sym_colpart, &c->t_nodes,
+                      &c->t_ctr, &c->t_perm, &c->t_geo, &c->t_wv, &c->t_out, &c->t_mom,
+                      &c->t_cnt};
     for (DevBuf *b : bufs)
         if (b->p)
             (void)hipFree(b->p);
@@ -963,6 +1010,35 @@ static int pb_matvec_impl(pb_ctx *c, const pb_surface *s, const pb_params *p, co
     TRY(ensure(c, c->io_y, sizeof(double) * n2));
     HIPCHK(hipMemcpyAsync(c->io_x.p, x, sizeof(double) * n2, hipMemcpyHostToDevice, c->stream));
     TRY(apply(c, p, precision, transpose ? 1 : 0, as<double>(c->io_x), as<double>(c->io_y)));
+    HIPCHK(hipMemcpyAsync(y, c->io_y.p, sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PB_OK;
+}
+
+static int pb_matvec_tree_impl(pb_ctx *c, const pb_surface *s, const pb_params *p, double theta,
+                               int order, int leaf_size, const double *x, double *y,
+                               int64_t *counts)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    if (!x || !y)
+        return fail(c, PB_ERR_ARG, "x or y is NULL");
+    if (!(theta >= 0.0 && theta < 1.0))
+        return fail(c, PB_ERR_ARG, "theta must lie in [0, 1)");
+    if (order < 0 || order > 5)
+        return fail(c, PB_ERR_ARG, "treecode order must be 0..5");
+    if (leaf_size < 1)
+        return fail(c, PB_ERR_ARG, "leaf_size must be >= 1");
+    const double *dv;
+    const int32_t *dt;
+    TRY(upload_surface(c, s, &dv, &dt));
+    TRY(setup_geometry(c, s->n_vert, s->n_tri, dv, dt));
+    const int64_t n2 = 2 * s->n_tri;
+    TRY(ensure(c, c->io_x, sizeof(double) * n2));
+    TRY(ensure(c, c->io_y, sizeof(double) * n2));
+    HIPCHK(hipMemcpyAsync(c->io_x.p, x, sizeof(double) * n2, hipMemcpyHostToDevice, c->stream));
+    TRY(tree_matvec(c, p, theta, order, leaf_size, as<double>(c->io_x), as<double>(c->io_y),
+                    counts));
     HIPCHK(hipMemcpyAsync(y, c->io_y.p, sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return PB_OK;
@@ -1101,6 +1177,12 @@ int pb_matvec(pb_ctx *c, const pb_surface *s, const pb_params *p, const double *
               int transpose, int precision)
 {
     return leave(c, pb_matvec_impl(c, s, p, x, y, transpose, precision));
+}
+
+int pb_matvec_tree(pb_ctx *c, const pb_surface *s, const pb_params *p, double theta, int order,
+                   int leaf_size, const double *x, double *y, int64_t *counts)
+{
+    return leave(c, pb_matvec_tree_impl(c, s, p, theta, order, leaf_size, x, y, counts));
 }
 
 int pb_matvec_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
@@ -1302,8 +1384,9 @@ int pb_set_sweep_config(pb_ctx *c, int targets_per_thread, int target_waves)
 {
     if (!c)
         return PB_ERR_ARG;
-    if (targets_per_thread != 0 && targets_per_thread != 1 && targets_per_thread != 2)
-        return fail(c, PB_ERR_ARG, "targets_per_thread must be 1 or 2");
+    if (targets_per_thread != 0 && targets_per_thread != 1 && targets_per_thread != 2 &&
+        targets_per_thread != PB_SWEEP_PAIRWISE)
+        return fail(c, PB_ERR_ARG, "sweep kind must be 1, 2 or PB_SWEEP_PAIRWISE");
     if (target_waves < 0 || target_waves > (1 << 22))
         return fail(c, PB_ERR_ARG, "target_waves out of range");
     if (targets_per_thread)
@@ -1338,8 +1421,8 @@ static int pb_autotune_impl(pb_ctx *c, const pb_surface *s, const pb_params *p, 
     TRY(ensure(c, c->io_y, sizeof(double) * n2));
     launch_fill(c->stream, as<double>(c->io_x), 1.0, n2);
     LAUNCHCHK();
-    static const int tpts[] = {1, 2};
-    static const int waves[] = {8192, 16384, 32768, 65536, 131072};
+    static const int tpts[] = {PB_SWEEP_PAIRWISE, 1, 2};
+    static const int waves[] = {8192, 16384, 32768, 65536, 131072, 262144};
     hipEvent_t e0 = pool_event(c, 0), e1 = pool_event(c, 1);
     if (!e0 || !e1)
         return fail(c, PB_ERR_HIP, "hipEventCreate failed");

@@ -52,8 +52,14 @@ struct pb_ctx {
     double prof_ms[PB_KERNEL_COUNT] = {};
     double prof_pairs[PB_KERNEL_COUNT] = {};
     // launch configuration of the FP32 forward sweep (pb_set_sweep_config / pb_autotune)
-    int f32_tpt = 1;
-    int f32_waves = 32768;
+    int f32_tpt = PB_SWEEP_PAIRWISE;   // 1, 2: per-target sweep; or the pairwise sweep
+    int f32_waves = 131072;
+    // pairwise sweep: packed points, work items and partial sums (plan cached)
+    pbk::DevBuf sym_src, sym_items, sym_rowstart, sym_rowpart, sym_colpart;
+    pbk::SymPlan sym_plan;
+    int sym_waves = 0;
+    // treecode: tree, permuted geometry and weights, moments, results
+    pbk::DevBuf t_nodes, t_ctr, t_perm, t_geo, t_wv, t_out, t_mom, t_cnt;
     // current geometry
     pbk::Geo g{};
     double center[3] = {0.0, 0.0, 0.0};
@@ -190,6 +196,8 @@ void build_leaves(const double *x, const double *y, const double *z, int64_t n, 
                   std::vector<int32_t> &perm, std::vector<int32_t> &start);
 
 // Batched solve of independent systems (pb_batch.hip).
+int tree_matvec(pb_ctx *c, const pb_params *p, double theta, int order, int n0, const double *x,
+                double *y, int64_t *counts);
 int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
                 const pb_params *p, int want_forces, double *e_solv, double *dE_dpos,
                 double *dE_dq, pb_info *info);

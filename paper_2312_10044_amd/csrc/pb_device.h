@@ -178,5 +178,194 @@ __device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&t
 }
 
 
+// ---- pairwise FP32 sweep: each unordered pair evaluated once ----------------
+//
+// For a pair (i, j) the distance, exp(-kappa r), tm1, b and h3 are symmetric,
+// so one evaluation yields both the contribution of source j to row i and of
+// source i to row j.  Every collocation point is a target and a source; the
+// packed entry carries both roles (reduced form, lengths in units of 1/kappa
+// when kappa > 0): position, w1 = (1 - 1/eps) a psi / sigma, m = -3 a phi n,
+// w2n = -a psi / (eps sigma) and sn = -n.
+struct alignas(16) Src12 {
+    float x, y, z, w, mx, my, mz, pad, nx, ny, nz, res;
+};
+
+// The thread's own point: target data (position, n_i) and its source weights
+// (w1, w2n and m = -3 a phi n of point i, as in the stream).
+struct OwnF32 {
+    float x, y, z;
+    float nx, ny, nz;
+    float w1, w2n;
+    float mx, my, mz;
+};
+
+__device__ __forceinline__ OwnF32 own_point(const Src12 &e)
+{
+    OwnF32 o;
+    o.x = e.x;
+    o.y = e.y;
+    o.z = e.z;
+    o.nx = -e.nx;
+    o.ny = -e.ny;
+    o.nz = -e.nz;
+    o.w1 = e.w;
+    o.w2n = e.pad;
+    o.mx = e.mx;
+    o.my = e.my;
+    o.mz = e.mz;
+    return o;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Reduce-scatter over the 16 lanes of each row, in two calls: the values
+// v0..v3 of sources k and k+2 of a group of four first meet at stage 1
+// (row mirror, lane xor 15: lanes with bit 3 set keep the second half), so
+// that stage is done as soon as both sources are evaluated.  The finishing
+// stages pair lanes by the half-row mirror (xor 7) and the quad permutations
+// xor 3 and xor 1; the masks 15, 7, 3, 1 span all 16 lane offsets.  On
+// return lane l holds the sum over its row of value (l >> 1) & 7, where value
+// 2k + c is component c of source k.
+__device__ __forceinline__ void rs_stage1(float a0, float a1, float b0, float b1, int lane,
+                                          float &s0, float &s1)
+{
+    const bool b3 = lane & 8;
+    s0 = (b3 ? b0 : a0) + dpp_f<0x140>(b3 ? a0 : b0);
+    s1 = (b3 ? b1 : a1) + dpp_f<0x140>(b3 ? a1 : b1);
+}
+
+__device__ __forceinline__ float rs_finish(const float (&a)[4], int lane)
+{
+    const bool b2 = lane & 4, b1 = lane & 2;
+    float b[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        b[k] = (b2 ? a[k + 2] : a[k]) + dpp_f<0x141>(b2 ? a[k] : a[k + 2]);
+    const float c = (b1 ? b[1] : b[0]) + dpp_f<0x1B>(b1 ? b[0] : b[1]);
+    return c + dpp_f<0xB1>(c);
+}
+
+// One pair, forward direction only (source s on the own point o); with DIAG the
+// pair is dropped when `skip` (ir = 0 zeroes every term).
+template <bool SCALED, bool DIAG>
+__device__ __forceinline__ void pair_fwd(const Src12 &s, const OwnF32 &o, const CoefF32 &cf,
+                                         bool skip, float &P, float &Q)
+{
+    const float dx = s.x - o.x, dy = s.y - o.y, dz = s.z - o.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    float ir = __builtin_amdgcn_rsqf(r2);
+    if (DIAG)
+        ir = skip ? 0.f : ir;
+    const float ir2 = ir * ir;
+    const float u = ir2 * ir;
+    const float r = r2 * ir;
+    const float kr = SCALED ? r : cf.kappa * r;
+    const float e = __builtin_amdgcn_exp2f(cf.kexp * r);
+    const float em1 = e - 1.f;
+    P = fmaf(em1, ir * s.pad, P);
+    const float tm1 = fmaf(kr, e, em1);
+    const float t3 = tm1 * 0.333333343f;
+    const float cxd = o.nx * dx + o.ny * dy + o.nz * dz;
+    const float md3 = s.mx * dx + s.my * dy + s.mz * dz;
+    const float nsm = o.nx * s.mx + o.ny * s.my + o.nz * s.mz;   // -3 (-n_i/3).m
+    const float b = t3 + cf.c13;
+    P = fmaf(b * md3, u, P);
+    const float h3 = fmaf(tm1, ir2, cf.k23 * e);
+    const float cqw = fmaf(tm1, s.pad, s.w);
+    const float inner = fmaf(md3, h3, cqw);
+    Q = fmaf(u, fmaf(cxd, inner, -(t3 * nsm)), Q);
+}
+
+// One pair, both directions: P, Q accumulate row i; cp, cq receive the
+// contribution of point i to row j.  The reverse direction is the forward
+// formula with i and j exchanged and d negated: its md3 is -m_i.d, its
+// c_x is sn_j.d, and its n.m term n_j.m_i equals -sn_j.m_i.
+template <bool SCALED>
+__device__ __forceinline__ void pair_both(const Src12 &s, const OwnF32 &o, const CoefF32 &cf,
+                                          float &P, float &Q, float &cp, float &cq)
+{
+    const float dx = s.x - o.x, dy = s.y - o.y, dz = s.z - o.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float ir = __builtin_amdgcn_rsqf(r2);
+    const float ir2 = ir * ir;
+    const float u = ir2 * ir;
+    const float r = r2 * ir;
+    const float kr = SCALED ? r : cf.kappa * r;
+    const float e = __builtin_amdgcn_exp2f(cf.kexp * r);
+    const float em1 = e - 1.f;
+    P = fmaf(em1, ir * s.pad, P);
+    float p2 = em1 * (ir * o.w2n);
+    const float tm1 = fmaf(kr, e, em1);
+    const float t3 = tm1 * 0.333333343f;
+    const float b = t3 + cf.c13;
+    const float h3 = fmaf(tm1, ir2, cf.k23 * e);
+    // source j on row i
+    const float cxd = o.nx * dx + o.ny * dy + o.nz * dz;
+    const float md3 = s.mx * dx + s.my * dy + s.mz * dz;
+    const float nsm = o.nx * s.mx + o.ny * s.my + o.nz * s.mz;
+    P = fmaf(b * md3, u, P);
+    const float cqw = fmaf(tm1, s.pad, s.w);
+    const float inner = fmaf(md3, h3, cqw);
+    Q = fmaf(u, fmaf(cxd, inner, -(t3 * nsm)), Q);
+    // source i on row j
+    const float pm = o.mx * dx + o.my * dy + o.mz * dz;      // -md3 of the reverse pair
+    const float cxdr = s.nx * dx + s.ny * dy + s.nz * dz;
+    const float spm = s.nx * o.mx + s.ny * o.my + s.nz * o.mz;
+    p2 = fmaf(-(b * pm), u, p2);
+    const float cqwr = fmaf(tm1, o.w2n, o.w1);
+    const float innerr = fmaf(-pm, h3, cqwr);
+    cp = p2;
+    cq = u * fmaf(cxdr, innerr, t3 * spm);
+}
+
+// Diagonal tile (sources = the block's own targets): forward direction, j = i
+// dropped.
+template <bool SCALED>
+__device__ __forceinline__ void sweep_diag(const Src12 *sh, const OwnF32 &o, const CoefF32 &cf,
+                                           float &P, float &Q)
+{
+#pragma unroll 2
+    for (int jj = 0; jj < TILE; ++jj)
+        pair_fwd<SCALED, true>(sh[jj], o, cf, jj == (int)threadIdx.x, P, Q);
+}
+
+// Off-diagonal tile: both directions.  The contributions to the tile's source
+// rows are summed over the wave's 64 targets in groups of 4 sources (8 values
+// per lane: reduce-scatter within rows, then across the 4 rows) and stored by
+// the even lanes 0-14 in colw[comp * TILE + j] (comp 0: row 1, 1: row 2);
+// colw holds 2 * TILE + 64 floats.
+template <bool SCALED>
+__device__ __forceinline__ void sweep_pairwise(const Src12 *sh, const OwnF32 &o,
+                                               const CoefF32 &cf, float &P, float &Q,
+                                               float *colw, int lane)
+{
+    for (int g = 0; g < TILE; g += 4) {
+        float a[4];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            float p0, q0, p2, q2;
+            pair_both<SCALED>(sh[g + k], o, cf, P, Q, p0, q0);
+            __builtin_amdgcn_sched_barrier(0);
+            pair_both<SCALED>(sh[g + k + 2], o, cf, P, Q, p2, q2);
+            rs_stage1(p0, q0, p2, q2, lane, a[2 * k], a[2 * k + 1]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        float t = rs_finish(a, lane);
+        t += __shfl_xor(t, 16, 64);
+        t += __shfl_xor(t, 32, 64);
+        // value index q: source g + q/2, row q%2.  Lanes that hold no new
+        // value write to a spare slot, which keeps the loop free of branches.
+        const int q = (lane >> 1) & 7;
+        const bool mine = lane < 16 && !(lane & 1);
+        colw[mine ? (q & 1) * TILE + g + (q >> 1) : 2 * TILE + lane] = t;
+    }
+}
+
+
 }  // namespace dev
 }  // namespace pbk

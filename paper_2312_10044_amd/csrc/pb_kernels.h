@@ -3,6 +3,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <cstdint>
 
 namespace pbk {
@@ -68,6 +70,34 @@ void launch_pairs_f32(hipStream_t s, const Geo &geo, const float *src, const Swe
 // FP32 forward sweep (mode-2 stream), tpt in {1, 2} targets per thread.
 void launch_pairs_f32_fwd(hipStream_t s, const Geo &geo, const float *src, const Sweep &sw,
                           const PairParams &pp, int tpt, double *part);
+// Pairwise FP32 forward sweep (each unordered pair once).  Work items
+// (I, J0, J1, slot): target tile I against source tiles J0..J1-1 (J0 >= I; the
+// tile J = I runs forward only).  Row sums of item k land in
+// rowpart[k][2][TILE] (FP64); the contributions of off-diagonal tile pair
+// (I, J) to the rows of tile J land in colpart[pair_index(I, J)][2][TILE]
+// (FP32).  row_start[K]..row_start[K+1] are the item slots of target tile K.
+struct SymPlan {
+    int64_t npad = 0;
+    int n_tiles = 0;      // T = npad / TILE
+    int tiles_per_item = 0;
+    int n_items = 0;
+};
+SymPlan plan_sym(int64_t npad, int target_waves, std::vector<int32_t> &items,
+                 std::vector<int32_t> &row_start);
+// Upper-triangle index of tile pair (I, J), I < J < T.
+__host__ __device__ inline int64_t sym_pair_index(int64_t I, int64_t J, int64_t T)
+{
+    return I * T - I * (I + 1) / 2 + (J - I - 1);
+}
+void launch_pack_sym(hipStream_t s, const Geo &geo, const double *x, float *src, double cx,
+                     double cy, double cz, double eps, double sigma);
+void launch_pairs_f32_sym(hipStream_t s, const float *src, const int32_t *items, int n_items,
+                          int n_tiles, const PairParams &pp, double *rowpart, float *colpart);
+void launch_sym_finish(hipStream_t s, const Geo &geo, const double *rowpart,
+                       const float *colpart, const int32_t *row_start, int n_tiles,
+                       const double *x, double alpha, double beta, double scale1, double scale2,
+                       double *y);
+
 // y = diag * x - (1/4pi) [scale1 * sum_c part0; scale2 * sum_c part1]
 // (times a_i when transposed)
 void launch_matvec_finish(hipStream_t s, const Geo &geo, const double *part, int n_chunks,

@@ -31,6 +31,8 @@
 #include "pb_kernels.h"
 #include "pb_device.h"
 
+#include <algorithm>
+
 #include <cmath>
 
 namespace pbk {
@@ -249,6 +251,115 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_fwd(const Src8<float> *__rest
         part[(int64_t)chunk * npad + i] = aP[k].value();
         part[(int64_t)(sw.n_chunks + chunk) * npad + i] = aQ[k].value();
     }
+}
+
+// ---- pairwise FP32 forward sweep ------------------------------------------
+
+__global__ __launch_bounds__(TPB) void k_pack_sym(const double *__restrict__ g, int64_t n,
+                                                  int64_t npad, const double *__restrict__ x,
+                                                  Src12 *__restrict__ src, double cx, double cy,
+                                                  double cz, double eps, double sigma)
+{
+    const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (j >= npad)
+        return;
+    Src12 s;
+    if (j < n) {
+        const double a = g[6 * npad + j];
+        const double ap = a * x[n + j] / sigma;
+        const double f = -3.0 * a * x[j];
+        const double nx = g[3 * npad + j], ny = g[4 * npad + j], nz = g[5 * npad + j];
+        s.x = float((g[j] - cx) * sigma);
+        s.y = float((g[npad + j] - cy) * sigma);
+        s.z = float((g[2 * npad + j] - cz) * sigma);
+        s.w = float((1.0 - 1.0 / eps) * ap);
+        s.mx = float(f * nx);
+        s.my = float(f * ny);
+        s.mz = float(f * nz);
+        s.pad = float(-ap / eps);
+        s.nx = float(-nx);
+        s.ny = float(-ny);
+        s.nz = float(-nz);
+    } else {
+        // padding: weightless points far away, 8 apart so no two coincide
+        s.x = float((FAR_SRC + 8.0 * double(j - n) - cx) * sigma);
+        s.y = s.z = 0.f;
+        s.w = s.mx = s.my = s.mz = s.pad = 0.f;
+        s.nx = s.ny = s.nz = 0.f;
+    }
+    s.res = 0.f;
+    src[j] = s;
+}
+
+template <bool SCALED>
+__global__ __launch_bounds__(TPB) void k_pairs_f32_sym(const Src12 *__restrict__ src,
+                                                       const int4 *__restrict__ items, int T,
+                                                       PairParams pp,
+                                                       double *__restrict__ rowpart,
+                                                       float *__restrict__ colpart)
+{
+    __shared__ Src12 sh[TILE];
+    __shared__ float colw[TPB / 64][2 * TILE + 64];
+    const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
+    const int I = it.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const OwnF32 o = own_point(src[(int64_t)I * TILE + threadIdx.x]);
+    const double kap = SCALED ? 1.0 : pp.kappa;   // kappa in the stream's length unit
+    CoefF32 cf;
+    cf.kappa = float(kap);
+    cf.kexp = float(-kap * 1.4426950408889634074);
+    cf.c13 = float((1.0 - 1.0 / pp.eps) / 3.0);
+    cf.k23 = float(kap * kap / 3.0);
+    Acc<float> aP, aQ;
+    for (int J = it.y; J < it.z; ++J) {
+        __syncthreads();
+        sh[threadIdx.x] = src[(int64_t)J * TILE + threadIdx.x];
+        __syncthreads();
+        float P = 0.f, Q = 0.f;
+        if (J == I) {
+            sweep_diag<SCALED>(sh, o, cf, P, Q);
+        } else {
+            sweep_pairwise<SCALED>(sh, o, cf, P, Q, colw[wid], lane);
+            __syncthreads();
+            float *cp = colpart + sym_pair_index(I, J, T) * (2 * TILE);
+            const int t = threadIdx.x;
+            cp[t] = ((colw[0][t] + colw[1][t]) + colw[2][t]) + colw[3][t];
+            cp[TILE + t] = ((colw[0][TILE + t] + colw[1][TILE + t]) + colw[2][TILE + t]) +
+                           colw[3][TILE + t];
+        }
+        aP.add(P);
+        aQ.add(Q);
+    }
+    double *rp = rowpart + (int64_t)it.w * (2 * TILE);
+    rp[threadIdx.x] = aP.value();
+    rp[TILE + threadIdx.x] = aQ.value();
+}
+
+// Row k = K*TILE + l: item rows of tile K, then the contributions of every tile
+// I < K, in that fixed order.
+__global__ __launch_bounds__(TPB) void k_sym_finish(const double *__restrict__ rowpart,
+                                                    const float *__restrict__ colpart,
+                                                    const int32_t *__restrict__ row_start, int T,
+                                                    int64_t n, const double *__restrict__ x,
+                                                    double alpha, double beta, double scale1,
+                                                    double scale2, double *__restrict__ y)
+{
+    const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (k >= n)
+        return;
+    const int K = (int)(k / TILE), l = (int)(k % TILE);
+    double s1 = 0.0, s2 = 0.0;
+    for (int q = row_start[K]; q < row_start[K + 1]; ++q) {
+        s1 += rowpart[(int64_t)q * (2 * TILE) + l];
+        s2 += rowpart[(int64_t)q * (2 * TILE) + TILE + l];
+    }
+    for (int I = 0; I < K; ++I) {
+        const float *cp = colpart + sym_pair_index(I, K, T) * (2 * TILE);
+        s1 += (double)cp[l];
+        s2 += (double)cp[TILE + l];
+    }
+    y[k] = alpha * x[k] - INV_4PI * scale1 * s1;
+    y[n + k] = beta * x[n + k] - INV_4PI * scale2 * s2;
 }
 
 __global__ __launch_bounds__(TPB) void k_matvec_finish(const double *__restrict__ part,
@@ -830,6 +941,48 @@ Sweep plan_sweep(int64_t n_targets, int64_t n_sources, int target_waves, int tpt
     return s;
 }
 
+SymPlan plan_sym(int64_t npad, int target_waves, std::vector<int32_t> &items,
+                 std::vector<int32_t> &row_start)
+{
+    SymPlan pl;
+    pl.npad = npad;
+    const int T = (int)(npad / TILE);
+    pl.n_tiles = T;
+    const int64_t work = (int64_t)T * (T + 1) / 2;   // tiles incl. the diagonal
+    int64_t want = target_waves / (TPB / 64);        // blocks
+    if (want < 1)
+        want = 1;
+    int L = (int)((work + want - 1) / want);
+    if (L < 1)
+        L = 1;
+    pl.tiles_per_item = L;
+    std::vector<int32_t> rows;   // (I, J0, J1, slot) in slot order
+    row_start.assign(T + 1, 0);
+    int slot = 0;
+    for (int I = 0; I < T; ++I) {
+        row_start[I] = slot;
+        for (int J0 = I; J0 < T; J0 += L) {
+            const int J1 = J0 + L < T ? J0 + L : T;
+            rows.insert(rows.end(), {I, J0, J1, slot});
+            ++slot;
+        }
+    }
+    row_start[T] = slot;
+    pl.n_items = slot;
+    // longest items first, so that the short tails fill in at the end
+    std::vector<int> order(slot);
+    for (int k = 0; k < slot; ++k)
+        order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return rows[4 * a + 2] - rows[4 * a + 1] > rows[4 * b + 2] - rows[4 * b + 1];
+    });
+    items.resize(4 * (size_t)slot);
+    for (int k = 0; k < slot; ++k)
+        for (int f = 0; f < 4; ++f)
+            items[4 * k + f] = rows[4 * order[k] + f];
+    return pl;
+}
+
 int geometry_blocks(int64_t n_tri)
 {
     int64_t b = (n_tri + TPB - 1) / TPB;
@@ -881,6 +1034,35 @@ void launch_pairs_f32_fwd(hipStream_t s, const Geo &geo, const float *src, const
     else
         hipLaunchKernelGGL((k_pairs_f32_fwd<1, false>), grid, dim3(TPB), 0, s, p, geo.g, geo.npad,
                            sw, pp, part);
+}
+
+void launch_pack_sym(hipStream_t s, const Geo &geo, const double *x, float *src, double cx,
+                     double cy, double cz, double eps, double sigma)
+{
+    hipLaunchKernelGGL(k_pack_sym, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
+                       geo.npad, x, reinterpret_cast<Src12 *>(src), cx, cy, cz, eps, sigma);
+}
+
+void launch_pairs_f32_sym(hipStream_t s, const float *src, const int32_t *items, int n_items,
+                          int n_tiles, const PairParams &pp, double *rowpart, float *colpart)
+{
+    const auto *p = reinterpret_cast<const Src12 *>(src);
+    const auto *it = reinterpret_cast<const int4 *>(items);
+    if (pp.kappa > 0.0)
+        hipLaunchKernelGGL(k_pairs_f32_sym<true>, dim3(n_items), dim3(TPB), 0, s, p, it,
+                           n_tiles, pp, rowpart, colpart);
+    else
+        hipLaunchKernelGGL(k_pairs_f32_sym<false>, dim3(n_items), dim3(TPB), 0, s, p, it,
+                           n_tiles, pp, rowpart, colpart);
+}
+
+void launch_sym_finish(hipStream_t s, const Geo &geo, const double *rowpart,
+                       const float *colpart, const int32_t *row_start, int n_tiles,
+                       const double *x, double alpha, double beta, double scale1, double scale2,
+                       double *y)
+{
+    hipLaunchKernelGGL(k_sym_finish, dim3(blocks_for(geo.n)), dim3(TPB), 0, s, rowpart, colpart,
+                       row_start, n_tiles, geo.n, x, alpha, beta, scale1, scale2, y);
 }
 
 void launch_pairs_f64(hipStream_t s, const Geo &geo, const double *src, const Sweep &sw,

@@ -25,12 +25,14 @@ PB_ERR_HIP = -4
 PB_ERR_OOM = -5
 PB_FP64 = 0
 PB_FP32_IR = 1
+PB_SWEEP_PAIRWISE = 8   # pb_set_sweep_config kind: each unordered pair once
 PB_KERNEL_PAIRS_FP64 = 0
 PB_KERNEL_PAIRS_FP32 = 1
 PB_KERNEL_PAIRS_FP64_T = 2
 PB_KERNEL_PAIRS_FP32_T = 3
 PB_KERNEL_SOURCE = 4
 PB_KERNEL_CHARGE = 5
+PB_KERNEL_TREE = 6
 
 # Every function the header declares, with its C prototype in ctypes terms.
 _vp = ctypes.c_void_p
@@ -72,6 +74,8 @@ _PROTOS = {
                          ctypes.POINTER(_Params), _vp]),
     "pb_matvec": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params), _vp, _vp,
                          _int, _int]),
+    "pb_matvec_tree": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params), _dbl,
+                              _int, _int, _vp, _vp, _vp]),
     "pb_energy": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
                          ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_dbl)]),
     "pb_solve": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
@@ -262,6 +266,20 @@ class Context:
         self._check(self._L.pb_matvec(self._h, ctypes.byref(s), ctypes.byref(p), px,
                                       _vp(y.ctypes.data), int(bool(transpose)), int(precision)))
         return y
+
+    def pb_matvec_tree(self, verts, tris, x, params: Params, theta=0.8, order=3, leaf_size=100,
+                       with_counts=False):
+        """Treecode matvec; returns y, or (y, (n_far, n_pairs, n_nodes))."""
+        s, k1 = self._surface(verts, tris)
+        xx, px = _host(x, np.float64)
+        y = np.empty_like(xx)
+        p = params.c()
+        cnt = np.zeros(3, dtype=np.int64)
+        self._check(self._L.pb_matvec_tree(self._h, ctypes.byref(s), ctypes.byref(p),
+                                           float(theta), int(order), int(leaf_size), px,
+                                           _vp(y.ctypes.data),
+                                           _vp(cnt.ctypes.data) if with_counts else None))
+        return (y, tuple(int(v) for v in cnt)) if with_counts else y
 
     def pb_energy(self, verts, tris, pos, q, phi, dphi, params: Params) -> float:
         s, k1 = self._surface(verts, tris)

@@ -1,0 +1,105 @@
+"""The FP32 forward sweep in both kinds (pairwise: each unordered pair once;
+per-target: 1 or 2 targets per thread) against the oracle's matvec."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dsbi
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = 0.1257
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2312_10044_amd as m
+    ctx = m.Context(0)
+    yield m, ctx
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def star12():
+    """2,880 triangles: 12 tiles of 256 after padding, the last one ragged."""
+    return synth.star_protein(freq=12, r0=10.0, n_charges=300, seed=41)
+
+
+def _err(m, ctx, w, kappa=KAPPA, rows=None, seed=0):
+    g = dsbi.geometry(w.verts, w.tris)
+    x = np.random.default_rng(seed).normal(size=2 * g.n)
+    y = ctx.pb_matvec(w.verts, w.tris, x, m.Params(kappa=kappa), precision=m.PB_FP32_IR)
+    if rows is None:
+        rows = np.arange(g.n)
+    y1, y2, s1, s2 = dsbi.matvec(g, 80.0, kappa, x, rows=rows, with_abs=True)
+    return max((np.abs(y[rows] - y1) / s1).max(), (np.abs(y[g.n + rows] - y2) / s2).max()), y
+
+
+@pytest.mark.parametrize("kind", ["pairwise", 1, 2])
+@pytest.mark.parametrize("kappa", [KAPPA, 0.0])
+def test_fp32_sweep_kinds_all_rows(pb, star12, kind, kappa):
+    m, ctx = pb
+    k = m.PB_SWEEP_PAIRWISE if kind == "pairwise" else kind
+    ctx.set_sweep_config(k, 32768)
+    _say(f"fp32 sweep kind={kind} kappa={kappa}: {star12.n_tri} triangles")
+    err, _y = _err(m, ctx, star12, kappa=kappa)
+    _say(f"  max |dy|/S = {err:.3e}")
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
+    assert err <= 5e-5
+
+
+@pytest.mark.parametrize("freq,r0", [(2, 3.0), (8, 2.0)])
+def test_pairwise_small_meshes(pb, freq, r0):
+    """80 triangles (one real tile, one tile of padding only) and 1,280."""
+    m, ctx = pb
+    w = synth.star_protein(freq=freq, r0=r0, n_charges=1, seed=7) if freq == 2 else \
+        synth.kirkwood_sphere()
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 32768)
+    _say(f"pairwise small mesh: {w.n_tri} triangles")
+    err, _y = _err(m, ctx, w)
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
+    assert err <= 5e-5
+
+
+@pytest.mark.parametrize("waves", [256, 8192, 131072])
+def test_pairwise_plan_sizes_and_repeat(pb, star12, waves):
+    """Items of many tiles or of one tile give the same matvec up to rounding,
+    and a repeated call is bitwise identical."""
+    m, ctx = pb
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, waves)
+    err, y = _err(m, ctx, star12, seed=4)
+    _e2, y2 = _err(m, ctx, star12, seed=4)
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
+    assert err <= 5e-5
+    assert np.array_equal(y, y2)
+
+
+def test_pairwise_full_size_sampled_rows(pb):
+    m, ctx = pb
+    w = synth.star_protein()
+    rows = np.sort(np.random.default_rng(5).choice(w.n_tri, 160, replace=False))
+    rows = np.concatenate([rows, [0, w.n_tri - 1]])
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 32768)
+    _say(f"pairwise full size: {w.n_tri} triangles, {len(rows)} rows")
+    err, _y = _err(m, ctx, w, rows=rows, seed=3)
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
+    _say(f"  max |dy|/S = {err:.3e}")
+    assert err <= 5e-5
+
+
+def test_pairwise_ir_solve_matches_fp64(pb, star12):
+    m, ctx = pb
+    w = star12
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 32768)
+    i64, _p, _d = ctx.pb_solve(w.verts, w.tris, w.pos, w.q, m.Params(tol=1e-12))
+    i32, _p, _d = ctx.pb_solve(w.verts, w.tris, w.pos, w.q,
+                               m.Params(tol=1e-8, precision=m.PB_FP32_IR))
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
+    assert i32.status == m.PB_OK and i32.matvecs_fp32 > 0
+    assert abs(i32.e_solv - i64.e_solv) <= 1e-6 * abs(i64.e_solv)
