@@ -33,7 +33,10 @@ TOL_LADDER = [1e-3, 5e-4, 2e-4, 1e-4, 5e-5, 2e-5, 1e-5, 5e-6, 2e-6, 1e-6, 5e-7, 
 E_TARGET = 1e-6
 
 
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_pairs_f32_star81920_traffic.json")
+TRAFFIC_RECORDS = {   # FETCH_SIZE/WRITE_SIZE records per FP32 sweep kind
+    8: os.path.join(ROOT, "profiles", "k_pairs_f32_sym_star81920_traffic.json"),
+    1: os.path.join(ROOT, "profiles", "k_pairs_f32_star81920_traffic.json"),
+}
 
 
 def _log(msg):
@@ -65,8 +68,8 @@ def measured_traffic(n_tri, sweep):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE record,
     or None when the kernel source or its configuration changed since."""
     try:
-        rec = json.load(open(TRAFFIC_RECORD))
-    except (OSError, ValueError):
+        rec = json.load(open(TRAFFIC_RECORDS[sweep[0]]))
+    except (KeyError, OSError, ValueError):
         return None
     if (rec.get("kernel_digest") != kernel_digest(sweep[0]) or rec.get("n_tri") != n_tri
             or [rec.get("targets_per_thread"), rec.get("target_waves")] != list(sweep)):

@@ -209,6 +209,10 @@ namespace pbk {
 // points splits into its eight child cubes (octant = (x >= cx) + 2 (y >= cy)
 // + 4 (z >= cz), child centres c +- h/2), empty children are dropped, leaves
 // are listed depth first in octant order, points in increasing index order.
+// The tree is built in place: each cluster is one range of `perm`, split by a
+// stable counting sort into its octants, so the ranges of the children follow
+// each other in octant order and the final `perm` lists the leaves depth
+// first.
 void build_leaves(const double *x, const double *y, const double *z, int64_t n, int n0,
                   std::vector<int32_t> &perm, std::vector<int32_t> &start)
 {
@@ -220,55 +224,62 @@ void build_leaves(const double *x, const double *y, const double *z, int64_t n, 
             hi[k] = std::max(hi[k], p[k]);
         }
     }
-    double c0[3], h0 = 0.0;
-    for (int k = 0; k < 3; ++k) {
-        c0[k] = 0.5 * (lo[k] + hi[k]);
-        h0 = std::max(h0, 0.5 * (hi[k] - lo[k]));
-    }
-    perm.clear();
-    start.assign(1, 0);
-    std::vector<int32_t> all(n);
-    for (int64_t i = 0; i < n; ++i)
-        all[i] = (int32_t)i;
     struct Frame {
-        std::vector<int32_t> idx;
+        int64_t a, b;   // range of perm
         double c[3], h;
         int depth;
     };
-    // explicit stack; children pushed in reverse so they pop in octant order
+    perm.resize(n);
+    for (int64_t i = 0; i < n; ++i)
+        perm[i] = (int32_t)i;
+    std::vector<int32_t> tmp(n);
+    std::vector<uint8_t> oct(n);
+    start.assign(1, 0);
     std::vector<Frame> stack;
-    stack.push_back({std::move(all), {c0[0], c0[1], c0[2]}, h0, 0});
+    Frame root{0, n, {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])}, 0.0,
+               0};
+    for (int k = 0; k < 3; ++k)
+        root.h = std::max(root.h, 0.5 * (hi[k] - lo[k]));
+    stack.push_back(root);
     while (!stack.empty()) {
-        Frame f = std::move(stack.back());
+        const Frame f = stack.back();
         stack.pop_back();
-        if ((int64_t)f.idx.size() <= n0 || f.depth >= 40) {
+        const int64_t m = f.b - f.a;
+        if (m <= n0 || f.depth >= 40) {
             // at the depth limit (coincident points) the leaf is cut into
             // consecutive runs of at most n0 points
-            for (size_t a = 0; a < f.idx.size(); a += (size_t)n0) {
-                const size_t b = std::min(f.idx.size(), a + (size_t)n0);
-                perm.insert(perm.end(), f.idx.begin() + a, f.idx.begin() + b);
-                start.push_back((int32_t)perm.size());
-            }
+            for (int64_t a = f.a; a < f.b; a += n0)
+                start.push_back((int32_t)std::min(f.b, a + (int64_t)n0));
             continue;
         }
-        std::vector<int32_t> sub[8];
-        for (int32_t i : f.idx) {
+        int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t k = f.a; k < f.b; ++k) {
+            const int32_t i = perm[k];
             const int o = (x[i] >= f.c[0] ? 1 : 0) + (y[i] >= f.c[1] ? 2 : 0) +
                           (z[i] >= f.c[2] ? 4 : 0);
-            sub[o].push_back(i);
+            oct[k] = (uint8_t)o;
+            ++cnt[o];
         }
+        int64_t off[9];
+        off[0] = f.a;
+        for (int o = 0; o < 8; ++o)
+            off[o + 1] = off[o] + cnt[o];
+        int64_t put[8];
+        for (int o = 0; o < 8; ++o)
+            put[o] = off[o];
+        for (int64_t k = f.a; k < f.b; ++k)
+            tmp[put[oct[k]]++] = perm[k];
+        std::copy(tmp.begin() + f.a, tmp.begin() + f.b, perm.begin() + f.a);
+        // children pushed in reverse so they pop in octant order
+        const double hh = 0.5 * f.h;
         for (int o = 7; o >= 0; --o) {
-            if (sub[o].empty())
+            if (cnt[o] == 0)
                 continue;
-            Frame ch;
-            ch.idx = std::move(sub[o]);
-            const double hh = 0.5 * f.h;
-            ch.c[0] = f.c[0] + ((o & 1) ? 1.0 : -1.0) * hh;
-            ch.c[1] = f.c[1] + ((o & 2) ? 1.0 : -1.0) * hh;
-            ch.c[2] = f.c[2] + ((o & 4) ? 1.0 : -1.0) * hh;
-            ch.h = hh;
-            ch.depth = f.depth + 1;
-            stack.push_back(std::move(ch));
+            Frame ch{off[o], off[o + 1],
+                     {f.c[0] + ((o & 1) ? hh : -hh), f.c[1] + ((o & 2) ? hh : -hh),
+                      f.c[2] + ((o & 4) ? hh : -hh)},
+                     hh, f.depth + 1};
+            stack.push_back(ch);
         }
     }
 }
