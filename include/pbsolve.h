@@ -255,6 +255,12 @@ int pb_matvec_tree(pb_ctx *ctx, const pb_surface *s, const pb_params *p, double 
 #define PB_SWEEP_PAIRWISE 8
 int pb_set_sweep_config(pb_ctx *ctx, int targets_per_thread, int target_waves);
 int pb_get_sweep_config(pb_ctx *ctx, int *targets_per_thread, int *target_waves);
+/* The FP64 pair sweeps (forward and transposed: FP64 solves, refinement
+ * residuals, adjoints) come in the same two kinds: 1 = one target per thread,
+ * PB_SWEEP_PAIRWISE = each unordered pair once.  0 leaves the kind unchanged.
+ * Default: PB_SWEEP_PAIRWISE.  The kinds agree up to FP64 rounding. */
+int pb_set_fp64_sweep(pb_ctx *ctx, int kind);
+int pb_get_fp64_sweep(pb_ctx *ctx, int *kind);
 /* Time every candidate configuration (kind in {PB_SWEEP_PAIRWISE, 1, 2} x
  * target_waves in {8192, 16384, 32768, 65536, 131072, 262144}) on this surface with HIP events
  * and keep the fastest in the context.  best_* may be NULL. */

@@ -110,24 +110,31 @@ PairParams pair_params(pb_ctx *c, const pb_params *p)
 
 // ---- matvec (steps 3 and 6) -----------------------------------------------------
 
+// Work items of the pairwise sweeps for the current geometry and wave target.
+int ensure_sym_plan(pb_ctx *c)
+{
+    const Geo &g = c->g;
+    if (c->sym_plan.npad == g.npad && c->sym_waves == c->f32_waves)
+        return PB_OK;
+    std::vector<int32_t> items, row_start;
+    const SymPlan pl = plan_sym(g.npad, c->f32_waves, items, row_start);
+    TRY(ensure(c, c->sym_items, sizeof(int32_t) * items.size()));
+    TRY(ensure(c, c->sym_rowstart, sizeof(int32_t) * row_start.size()));
+    HIPCHK(hipMemcpyAsync(c->sym_items.p, items.data(), sizeof(int32_t) * items.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->sym_rowstart.p, row_start.data(), sizeof(int32_t) * row_start.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));   // host vectors go out of scope
+    c->sym_plan = pl;
+    c->sym_waves = c->f32_waves;
+    return PB_OK;
+}
+
 // Pairwise FP32 sweep: every unordered pair once, both directions.
 int apply_pairwise(pb_ctx *c, const pb_params *p, const double *x, double *y)
 {
     const Geo &g = c->g;
-    if (c->sym_plan.npad != g.npad || c->sym_waves != c->f32_waves) {
-        std::vector<int32_t> items, row_start;
-        const SymPlan pl = plan_sym(g.npad, c->f32_waves, items, row_start);
-        TRY(ensure(c, c->sym_items, sizeof(int32_t) * items.size()));
-        TRY(ensure(c, c->sym_rowstart, sizeof(int32_t) * row_start.size()));
-        HIPCHK(hipMemcpyAsync(c->sym_items.p, items.data(), sizeof(int32_t) * items.size(),
-                              hipMemcpyHostToDevice, c->stream));
-        HIPCHK(hipMemcpyAsync(c->sym_rowstart.p, row_start.data(),
-                              sizeof(int32_t) * row_start.size(), hipMemcpyHostToDevice,
-                              c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));   // host vectors go out of scope
-        c->sym_plan = pl;
-        c->sym_waves = c->f32_waves;
-    }
+    TRY(ensure_sym_plan(c));
     const SymPlan &pl = c->sym_plan;
     const int64_t T = pl.n_tiles;
     TRY(ensure(c, c->sym_src, sizeof(float) * 12 * g.npad));
@@ -152,11 +159,43 @@ int apply_pairwise(pb_ctx *c, const pb_params *p, const double *x, double *y)
     return PB_OK;
 }
 
+// Pairwise FP64 sweep, forward or transposed, on the same work items.
+int apply_pairwise64(pb_ctx *c, const pb_params *p, int transpose, const double *x, double *y)
+{
+    const Geo &g = c->g;
+    TRY(ensure_sym_plan(c));
+    const SymPlan &pl = c->sym_plan;
+    const int64_t T = pl.n_tiles;
+    TRY(ensure(c, c->sym_src64, sizeof(double) * 10 * g.npad));
+    TRY(ensure(c, c->sym_rowpart, sizeof(double) * 2 * TILE * (size_t)pl.n_items));
+    TRY(ensure(c, c->sym_colpart,
+               sizeof(double) * 2 * TILE * (size_t)std::max<int64_t>(T * (T - 1) / 2, 1)));
+    const PairParams pp = pair_params(c, p);
+    const double eps = pp.eps;
+    launch_pack_sym64(c->stream, g, x, as<double>(c->sym_src64), transpose ? 1 : 0);
+    LAUNCHCHK();
+    {
+        ProfScope ps(c, transpose ? PB_KERNEL_PAIRS_FP64_T : PB_KERNEL_PAIRS_FP64,
+                     (double)g.n * (double)(g.n - 1));
+        launch_pairs_f64_sym(c->stream, as<double>(c->sym_src64), as<int32_t>(c->sym_items),
+                             pl.n_items, pl.n_tiles, pp, transpose, as<double>(c->sym_rowpart),
+                             as<double>(c->sym_colpart));
+    }
+    LAUNCHCHK();
+    launch_sym_finish64(c->stream, g, as<double>(c->sym_rowpart), as<double>(c->sym_colpart),
+                        as<int32_t>(c->sym_rowstart), pl.n_tiles, x, 0.5 * (1.0 + eps),
+                        0.5 * (1.0 + 1.0 / eps), transpose, y);
+    LAUNCHCHK();
+    return PB_OK;
+}
+
 int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const double *x, double *y)
 {
     const Geo &g = c->g;
     if (precision == PB_FP32_IR && !transpose && c->f32_tpt == PB_SWEEP_PAIRWISE)
         return apply_pairwise(c, p, x, y);
+    if (precision == PB_FP64 && c->f64_kind == PB_SWEEP_PAIRWISE)
+        return apply_pairwise64(c, p, transpose, x, y);
     const bool fast32 = precision == PB_FP32_IR && !transpose;
     const Sweep sw = fast32 ? plan_sweep(g.npad, g.npad, c->f32_waves, c->f32_tpt)
                             : plan_sweep(g.npad, g.npad, TARGET_WAVES);
@@ -937,7 +976,8 @@ void pb_destroy(pb_ctx *c)
                       &c->pc_inv, &c->b_geo, &c->b_desc, &c->b_map, &c->b_items, &c->b_src,
                       &c->b_part, &c->b_vec, &c->b_V, &c->b_state, &c->b_red, &c->b_chg,
                       &c->b_pc_idx, &c->b_pc_inv, &c->sym_src, &c->sym_items,
-                      &c->sym_rowstart, &c->sym_rowpart, &c->sym_colpart, &c->t_nodes,
+                      &c->sym_rowstart, &c->sym_rowpart, &c->sym_colpart, &c->sym_src64,
+                      &c->t_nodes,
                       &c->t_ctr, &c->t_perm, &c->t_geo, &c->t_wv, &c->t_out, &c->t_mom,
                       &c->t_cnt};
     for (DevBuf *b : bufs)
@@ -1404,6 +1444,26 @@ int pb_set_sweep_config(pb_ctx *c, int targets_per_thread, int target_waves)
         c->f32_tpt = targets_per_thread;
     if (target_waves)
         c->f32_waves = target_waves;
+    return PB_OK;
+}
+
+int pb_set_fp64_sweep(pb_ctx *c, int kind)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    if (kind != 0 && kind != 1 && kind != PB_SWEEP_PAIRWISE)
+        return fail(c, PB_ERR_ARG, "FP64 sweep kind must be 1 or PB_SWEEP_PAIRWISE");
+    if (kind)
+        c->f64_kind = kind;
+    return PB_OK;
+}
+
+int pb_get_fp64_sweep(pb_ctx *c, int *kind)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    if (kind)
+        *kind = c->f64_kind;
     return PB_OK;
 }
 

@@ -55,7 +55,8 @@ struct pb_ctx {
     int f32_tpt = PB_SWEEP_PAIRWISE;   // 1, 2: per-target sweep; or the pairwise sweep
     int f32_waves = 131072;
     // pairwise sweep: packed points, work items and partial sums (plan cached)
-    pbk::DevBuf sym_src, sym_items, sym_rowstart, sym_rowpart, sym_colpart;
+    pbk::DevBuf sym_src, sym_src64, sym_items, sym_rowstart, sym_rowpart, sym_colpart;
+    int f64_kind = PB_SWEEP_PAIRWISE;   // FP64 sweep: 1 per-target, or pairwise
     pbk::SymPlan sym_plan;
     int sym_waves = 0;
     // treecode: tree, permuted geometry and weights, moments, results

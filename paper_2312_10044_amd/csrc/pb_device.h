@@ -223,6 +223,20 @@ __device__ __forceinline__ float dpp_f(float v)
         __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float v) { return dpp_f<CTRL>(v); }
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double v) { return dpp_d<CTRL>(v); }
+
 // Reduce-scatter over the 16 lanes of each row, in two calls: the values
 // v0..v3 of sources k and k+2 of a group of four first meet at stage 1
 // (row mirror, lane xor 15: lanes with bit 3 set keep the second half), so
@@ -231,23 +245,24 @@ __device__ __forceinline__ float dpp_f(float v)
 // xor 3 and xor 1; the masks 15, 7, 3, 1 span all 16 lane offsets.  On
 // return lane l holds the sum over its row of value (l >> 1) & 7, where value
 // 2k + c is component c of source k.
-__device__ __forceinline__ void rs_stage1(float a0, float a1, float b0, float b1, int lane,
-                                          float &s0, float &s1)
+template <typename T>
+__device__ __forceinline__ void rs_stage1(T a0, T a1, T b0, T b1, int lane, T &s0, T &s1)
 {
     const bool b3 = lane & 8;
-    s0 = (b3 ? b0 : a0) + dpp_f<0x140>(b3 ? a0 : b0);
-    s1 = (b3 ? b1 : a1) + dpp_f<0x140>(b3 ? a1 : b1);
+    s0 = (b3 ? b0 : a0) + dpp_t<0x140>(b3 ? a0 : b0);
+    s1 = (b3 ? b1 : a1) + dpp_t<0x140>(b3 ? a1 : b1);
 }
 
-__device__ __forceinline__ float rs_finish(const float (&a)[4], int lane)
+template <typename T>
+__device__ __forceinline__ T rs_finish(const T (&a)[4], int lane)
 {
     const bool b2 = lane & 4, b1 = lane & 2;
-    float b[2];
+    T b[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k)
-        b[k] = (b2 ? a[k + 2] : a[k]) + dpp_f<0x141>(b2 ? a[k] : a[k + 2]);
-    const float c = (b1 ? b[1] : b[0]) + dpp_f<0x1B>(b1 ? b[0] : b[1]);
-    return c + dpp_f<0xB1>(c);
+        b[k] = (b2 ? a[k + 2] : a[k]) + dpp_t<0x141>(b2 ? a[k] : a[k + 2]);
+    const T c = (b1 ? b[1] : b[0]) + dpp_t<0x1B>(b1 ? b[0] : b[1]);
+    return c + dpp_t<0xB1>(c);
 }
 
 // One pair, forward direction only (source s on the own point o); with DIAG the
@@ -360,6 +375,105 @@ __device__ __forceinline__ void sweep_pairwise(const Src12 *sh, const OwnF32 &o,
         t += __shfl_xor(t, 32, 64);
         // value index q: source g + q/2, row q%2.  Lanes that hold no new
         // value write to a spare slot, which keeps the loop free of branches.
+        const int q = (lane >> 1) & 7;
+        const bool mine = lane < 16 && !(lane & 1);
+        colw[mine ? (q & 1) * TILE + g + (q >> 1) : 2 * TILE + lane] = t;
+    }
+}
+
+
+// ---- pairwise FP64 sweep ------------------------------------------------------
+//
+// The generic (FP64) pair algebra, with d = x_i - x_j, evaluated once per
+// unordered pair.  Forward stream: w = a psi, m = a phi n; transpose stream:
+// w = l1, m = l2 n; both also carry the point's normal n.  For source j on
+// row i (cP = g2, cQ = -g3 forward; cP = -g3, cQ = g2 transposed):
+//   P_i += -(e-1) w_j / r + cP (m_j.d) / r^3
+//   Q_i += [-(n_i.d) ((m_j.d) h + cQ w_j) + tm1 (n_i.m_j)] / r^3
+// and for source i on row j the same with i and j exchanged, d -> -d:
+//   P_j += -(e-1) w_i / r - cP (m_i.d) / r^3
+//   Q_j += [(n_j.d) (-(m_i.d) h + cQ w_i) + tm1 (n_j.m_i)] / r^3.
+// Transposed, P and Q are rows 2 and 1 of the output (swapped by the caller).
+struct alignas(16) Src10d {
+    double x, y, z, w, mx, my, mz, nx, ny, nz;
+};
+
+struct OwnF64 {
+    double x, y, z, nx, ny, nz, w, mx, my, mz;
+};
+
+__device__ __forceinline__ OwnF64 own_point64(const Src10d &e)
+{
+    return OwnF64{e.x, e.y, e.z, e.nx, e.ny, e.nz, e.w, e.mx, e.my, e.mz};
+}
+
+template <bool TRANS, bool BOTH, bool DIAG>
+__device__ __forceinline__ void pair64(const Src10d &s, const OwnF64 &o, const Coef<double> &cf,
+                                       bool skip, double &P, double &Q, double &cp, double &cq)
+{
+    const double dx = o.x - s.x, dy = o.y - s.y, dz = o.z - s.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    double ir = rsqrt(r2);
+    if (DIAG)
+        ir = skip ? 0.0 : ir;
+    const double ir2 = ir * ir;
+    const double u = ir2 * ir;
+    const double kr = cf.kappa * (r2 * ir);
+    const double e = exp(-kr);
+    const double em1 = e - 1.0;
+    const double tm1 = fma(kr, e, em1);
+    const double g2 = fma(cf.eps, tm1, cf.epsm1);
+    const double g3 = fma(cf.ieps, tm1, cf.iepsm1);
+    const double h = fma(tm1, 3.0 * ir2, cf.k2 * e);
+    const double cP = TRANS ? -g3 : g2;
+    const double cQ = TRANS ? g2 : -g3;
+    const double a = -em1 * ir;
+    const double md = s.mx * dx + s.my * dy + s.mz * dz;
+    const double cxd = o.nx * dx + o.ny * dy + o.nz * dz;
+    const double nm = o.nx * s.mx + o.ny * s.my + o.nz * s.mz;
+    P = fma(a, s.w, P);
+    P = fma(cP * md, u, P);
+    Q = fma(u, fma(-cxd, fma(md, h, cQ * s.w), tm1 * nm), Q);
+    if (BOTH) {
+        const double pm = o.mx * dx + o.my * dy + o.mz * dz;
+        const double cyd = s.nx * dx + s.ny * dy + s.nz * dz;
+        const double nmr = s.nx * o.mx + s.ny * o.my + s.nz * o.mz;
+        cp = fma(-cP * pm, u, a * o.w);
+        cq = u * fma(cyd, fma(-pm, h, cQ * o.w), tm1 * nmr);
+    }
+}
+
+template <bool TRANS>
+__device__ __forceinline__ void sweep_diag64(const Src10d *sh, const OwnF64 &o,
+                                             const Coef<double> &cf, double &P, double &Q)
+{
+    double dummy0 = 0.0, dummy1 = 0.0;
+#pragma unroll 2
+    for (int jj = 0; jj < TILE; ++jj)
+        pair64<TRANS, false, true>(sh[jj], o, cf, jj == (int)threadIdx.x, P, Q, dummy0, dummy1);
+}
+
+// Off-diagonal tile, both directions; column sums as in sweep_pairwise,
+// stored in colw[comp * TILE + j] (2 * TILE + 64 doubles).
+template <bool TRANS>
+__device__ __forceinline__ void sweep_pairwise64(const Src10d *sh, const OwnF64 &o,
+                                                 const Coef<double> &cf, double &P, double &Q,
+                                                 double *colw, int lane)
+{
+    for (int g = 0; g < TILE; g += 4) {
+        double a[4];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            double p0, q0, p2, q2;
+            pair64<TRANS, true, false>(sh[g + k], o, cf, false, P, Q, p0, q0);
+            __builtin_amdgcn_sched_barrier(0);
+            pair64<TRANS, true, false>(sh[g + k + 2], o, cf, false, P, Q, p2, q2);
+            rs_stage1(p0, q0, p2, q2, lane, a[2 * k], a[2 * k + 1]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        double t = rs_finish(a, lane);
+        t += __shfl_xor(t, 16, 64);
+        t += __shfl_xor(t, 32, 64);
         const int q = (lane >> 1) & 7;
         const bool mine = lane < 16 && !(lane & 1);
         colw[mine ? (q & 1) * TILE + g + (q >> 1) : 2 * TILE + lane] = t;

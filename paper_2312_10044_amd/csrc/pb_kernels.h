@@ -98,6 +98,15 @@ void launch_sym_finish(hipStream_t s, const Geo &geo, const double *rowpart,
                        const double *x, double alpha, double beta, double scale1, double scale2,
                        double *y);
 
+// Pairwise FP64 sweep on the same work items (forward and transposed).
+void launch_pack_sym64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode);
+void launch_pairs_f64_sym(hipStream_t s, const double *src, const int32_t *items, int n_items,
+                          int n_tiles, const PairParams &pp, int transpose, double *rowpart,
+                          double *colpart);
+void launch_sym_finish64(hipStream_t s, const Geo &geo, const double *rowpart,
+                         const double *colpart, const int32_t *row_start, int n_tiles,
+                         const double *x, double alpha, double beta, int transpose, double *y);
+
 // y = diag * x - (1/4pi) [scale1 * sum_c part0; scale2 * sum_c part1]
 // (times a_i when transposed)
 void launch_matvec_finish(hipStream_t s, const Geo &geo, const double *part, int n_chunks,

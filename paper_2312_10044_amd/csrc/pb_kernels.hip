@@ -336,12 +336,16 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_sym(const Src12 *__restrict__
 }
 
 // Row k = K*TILE + l: item rows of tile K, then the contributions of every tile
-// I < K, in that fixed order.
+// I < K, in that fixed order.  Transposed (FP64 only) the two partial rows are
+// output rows 2 and 1 and every row is scaled by its own area.
+template <typename CT>
 __global__ __launch_bounds__(TPB) void k_sym_finish(const double *__restrict__ rowpart,
-                                                    const float *__restrict__ colpart,
+                                                    const CT *__restrict__ colpart,
                                                     const int32_t *__restrict__ row_start, int T,
-                                                    int64_t n, const double *__restrict__ x,
-                                                    double alpha, double beta, double scale1,
+                                                    int64_t n, int64_t npad,
+                                                    const double *__restrict__ area,
+                                                    const double *__restrict__ x, double alpha,
+                                                    double beta, int trans, double scale1,
                                                     double scale2, double *__restrict__ y)
 {
     const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
@@ -354,12 +358,91 @@ __global__ __launch_bounds__(TPB) void k_sym_finish(const double *__restrict__ r
         s2 += rowpart[(int64_t)q * (2 * TILE) + TILE + l];
     }
     for (int I = 0; I < K; ++I) {
-        const float *cp = colpart + sym_pair_index(I, K, T) * (2 * TILE);
+        const CT *cp = colpart + sym_pair_index(I, K, T) * (2 * TILE);
         s1 += (double)cp[l];
         s2 += (double)cp[TILE + l];
     }
-    y[k] = alpha * x[k] - INV_4PI * scale1 * s1;
-    y[n + k] = beta * x[n + k] - INV_4PI * scale2 * s2;
+    if (trans) {
+        const double sc = area[k] * INV_4PI;
+        y[k] = alpha * x[k] - sc * s2;
+        y[n + k] = beta * x[n + k] - sc * s1;
+    } else {
+        y[k] = alpha * x[k] - INV_4PI * scale1 * s1;
+        y[n + k] = beta * x[n + k] - INV_4PI * scale2 * s2;
+    }
+}
+
+// ---- pairwise FP64 sweep ----------------------------------------------------
+
+// mode 0: w = a psi, m = a phi n; mode 1 (transpose): w = l1, m = l2 n.
+__global__ __launch_bounds__(TPB) void k_pack_sym64(const double *__restrict__ g, int64_t n,
+                                                    int64_t npad, const double *__restrict__ x,
+                                                    Src10d *__restrict__ src, int mode)
+{
+    const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (j >= npad)
+        return;
+    Src10d s;
+    if (j < n) {
+        const double a = g[6 * npad + j];
+        const double w = mode ? x[j] : a * x[n + j];
+        const double f = mode ? x[n + j] : a * x[j];
+        s.x = g[j];
+        s.y = g[npad + j];
+        s.z = g[2 * npad + j];
+        s.w = w;
+        s.nx = g[3 * npad + j];
+        s.ny = g[4 * npad + j];
+        s.nz = g[5 * npad + j];
+        s.mx = f * s.nx;
+        s.my = f * s.ny;
+        s.mz = f * s.nz;
+    } else {
+        // padding: weightless points far away, 8 apart
+        s.x = FAR_SRC + 8.0 * double(j - n);
+        s.y = s.z = 0.0;
+        s.w = s.mx = s.my = s.mz = s.nx = s.ny = s.nz = 0.0;
+    }
+    src[j] = s;
+}
+
+template <bool TRANS>
+__global__ __launch_bounds__(TPB) void k_pairs_f64_sym(const Src10d *__restrict__ src,
+                                                       const int4 *__restrict__ items, int T,
+                                                       PairParams pp,
+                                                       double *__restrict__ rowpart,
+                                                       double *__restrict__ colpart)
+{
+    __shared__ Src10d sh[TILE];
+    __shared__ double colw[TPB / 64][2 * TILE + 64];
+    const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
+    const int I = it.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const OwnF64 o = own_point64(src[(int64_t)I * TILE + threadIdx.x]);
+    const Coef<double> cf(pp);
+    double aP = 0.0, aQ = 0.0;
+    for (int J = it.y; J < it.z; ++J) {
+        __syncthreads();
+        sh[threadIdx.x] = src[(int64_t)J * TILE + threadIdx.x];
+        __syncthreads();
+        double P = 0.0, Q = 0.0;
+        if (J == I) {
+            sweep_diag64<TRANS>(sh, o, cf, P, Q);
+        } else {
+            sweep_pairwise64<TRANS>(sh, o, cf, P, Q, colw[wid], lane);
+            __syncthreads();
+            double *cp = colpart + sym_pair_index(I, J, T) * (2 * TILE);
+            const int t = threadIdx.x;
+            cp[t] = ((colw[0][t] + colw[1][t]) + colw[2][t]) + colw[3][t];
+            cp[TILE + t] = ((colw[0][TILE + t] + colw[1][TILE + t]) + colw[2][TILE + t]) +
+                           colw[3][TILE + t];
+        }
+        aP += P;
+        aQ += Q;
+    }
+    double *rp = rowpart + (int64_t)it.w * (2 * TILE);
+    rp[threadIdx.x] = aP;
+    rp[TILE + threadIdx.x] = aQ;
 }
 
 __global__ __launch_bounds__(TPB) void k_matvec_finish(const double *__restrict__ part,
@@ -1061,8 +1144,38 @@ void launch_sym_finish(hipStream_t s, const Geo &geo, const double *rowpart,
                        const double *x, double alpha, double beta, double scale1, double scale2,
                        double *y)
 {
-    hipLaunchKernelGGL(k_sym_finish, dim3(blocks_for(geo.n)), dim3(TPB), 0, s, rowpart, colpart,
-                       row_start, n_tiles, geo.n, x, alpha, beta, scale1, scale2, y);
+    hipLaunchKernelGGL(k_sym_finish<float>, dim3(blocks_for(geo.n)), dim3(TPB), 0, s, rowpart,
+                       colpart, row_start, n_tiles, geo.n, geo.npad, geo.g + 6 * geo.npad, x,
+                       alpha, beta, 0, scale1, scale2, y);
+}
+
+void launch_pack_sym64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode)
+{
+    hipLaunchKernelGGL(k_pack_sym64, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
+                       geo.npad, x, reinterpret_cast<Src10d *>(src), mode);
+}
+
+void launch_pairs_f64_sym(hipStream_t s, const double *src, const int32_t *items, int n_items,
+                          int n_tiles, const PairParams &pp, int transpose, double *rowpart,
+                          double *colpart)
+{
+    const auto *p = reinterpret_cast<const Src10d *>(src);
+    const auto *it = reinterpret_cast<const int4 *>(items);
+    if (transpose)
+        hipLaunchKernelGGL(k_pairs_f64_sym<true>, dim3(n_items), dim3(TPB), 0, s, p, it, n_tiles,
+                           pp, rowpart, colpart);
+    else
+        hipLaunchKernelGGL(k_pairs_f64_sym<false>, dim3(n_items), dim3(TPB), 0, s, p, it, n_tiles,
+                           pp, rowpart, colpart);
+}
+
+void launch_sym_finish64(hipStream_t s, const Geo &geo, const double *rowpart,
+                         const double *colpart, const int32_t *row_start, int n_tiles,
+                         const double *x, double alpha, double beta, int transpose, double *y)
+{
+    hipLaunchKernelGGL(k_sym_finish<double>, dim3(blocks_for(geo.n)), dim3(TPB), 0, s, rowpart,
+                       colpart, row_start, n_tiles, geo.n, geo.npad, geo.g + 6 * geo.npad, x,
+                       alpha, beta, transpose, 1.0, 1.0, y);
 }
 
 void launch_pairs_f64(hipStream_t s, const Geo &geo, const double *src, const Sweep &sw,

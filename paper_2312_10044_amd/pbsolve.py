@@ -100,6 +100,8 @@ _PROTOS = {
     "pb_precond_apply": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params), _vp, _vp,
                                 _int]),
     "pb_set_sweep_config": (_int, [_vp, _int, _int]),
+    "pb_set_fp64_sweep": (_int, [_vp, _int]),
+    "pb_get_fp64_sweep": (_int, [_vp, ctypes.POINTER(_int)]),
     "pb_get_sweep_config": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
     "pb_autotune": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params),
                            ctypes.POINTER(_int), ctypes.POINTER(_int)]),
@@ -421,6 +423,15 @@ class Context:
         return y
 
     # -- launch configuration --------------------------------------------------
+    def set_fp64_sweep(self, kind: int = 0):
+        """FP64 sweep kind: 1 (per target) or PB_SWEEP_PAIRWISE; 0 keeps it."""
+        self._check(self._L.pb_set_fp64_sweep(self._h, int(kind)))
+
+    def get_fp64_sweep(self) -> int:
+        k = _int(0)
+        self._check(self._L.pb_get_fp64_sweep(self._h, ctypes.byref(k)))
+        return int(k.value)
+
     def set_sweep_config(self, targets_per_thread: int = 0, target_waves: int = 0):
         self._check(self._L.pb_set_sweep_config(self._h, int(targets_per_thread),
                                                 int(target_waves)))

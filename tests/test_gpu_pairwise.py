@@ -103,3 +103,49 @@ def test_pairwise_ir_solve_matches_fp64(pb, star12):
     ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
     assert i32.status == m.PB_OK and i32.matvecs_fp32 > 0
     assert abs(i32.e_solv - i64.e_solv) <= 1e-6 * abs(i64.e_solv)
+
+
+def _err64(m, ctx, w, transpose, kappa=KAPPA, rows=None, seed=0):
+    g = dsbi.geometry(w.verts, w.tris)
+    x = np.random.default_rng(seed).normal(size=2 * g.n)
+    y = ctx.pb_matvec(w.verts, w.tris, x, m.Params(kappa=kappa), transpose=transpose,
+                      precision=m.PB_FP64)
+    if rows is None:
+        rows = np.arange(g.n)
+    y1, y2, s1, s2 = dsbi.matvec(g, 80.0, kappa, x, rows=rows, transpose=transpose,
+                                 with_abs=True)
+    return max((np.abs(y[rows] - y1) / s1).max(), (np.abs(y[g.n + rows] - y2) / s2).max()), y
+
+
+@pytest.mark.parametrize("kind", ["pairwise", 1])
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("kappa", [KAPPA, 0.0])
+def test_fp64_sweep_kinds_all_rows(pb, star12, kind, transpose, kappa):
+    m, ctx = pb
+    ctx.set_fp64_sweep(m.PB_SWEEP_PAIRWISE if kind == "pairwise" else kind)
+    _say(f"fp64 sweep kind={kind} transpose={transpose} kappa={kappa}")
+    err, _y = _err64(m, ctx, star12, transpose, kappa=kappa)
+    ctx.set_fp64_sweep(m.PB_SWEEP_PAIRWISE)
+    _say(f"  max |dy|/S = {err:.3e}")
+    assert err <= 2e-12
+
+
+def test_fp64_pairwise_small_mesh_and_repeat(pb):
+    m, ctx = pb
+    w = synth.star_protein(freq=2, r0=3.0, n_charges=1, seed=7)
+    ctx.set_fp64_sweep(m.PB_SWEEP_PAIRWISE)
+    for transpose in (False, True):
+        err, y = _err64(m, ctx, w, transpose)
+        _e, y2 = _err64(m, ctx, w, transpose)
+        assert err <= 2e-12 and np.array_equal(y, y2)
+
+
+def test_fp64_pairwise_full_size_sampled_rows(pb):
+    m, ctx = pb
+    w = synth.star_protein()
+    rows = np.sort(np.random.default_rng(6).choice(w.n_tri, 96, replace=False))
+    ctx.set_fp64_sweep(m.PB_SWEEP_PAIRWISE)
+    for transpose in (False, True):
+        err, _y = _err64(m, ctx, w, transpose, rows=rows, seed=2)
+        _say(f"fp64 pairwise full size transpose={transpose}: {err:.3e}")
+        assert err <= 2e-12
