@@ -50,11 +50,21 @@ struct SysDesc {
     int64_t item0, citem0;      // first matvec / charge-sweep work item
     int32_t nch, cnch;          // chunks per target block / per charge block
     double cx, cy, cz;          // origin for FP32 arithmetic
+    int32_t T, rs0;             // pairwise sweeps: tiles, first entry in the row-slot table
+    int64_t cp0;                // pairwise sweeps: first tile pair in the column partials
 };
 
 struct Item {
     int32_t sys, tb, t0, t1;
 };
+
+// Pairwise work item: target tile I of system `sys` against its source tiles
+// J0..J1-1; `slot` is its row-partial record.
+struct SItem {
+    int32_t sys, I, J0, J1, slot, pad0, pad1, pad2;
+};
+
+constexpr int SYM_TILES = 16;                 // source tiles per pairwise work item
 
 struct GState {
     double H[(BM_MAX + 1) * BM_MAX];
@@ -205,6 +215,182 @@ __global__ __launch_bounds__(TPB) void kb_pairs(const Src8<T> *__restrict__ src,
         const double P = aP.value(), Q = aQ.value();
         part[it * TPB + threadIdx.x] = TRANS ? Q : P;
         part[(n_items + it) * TPB + threadIdx.x] = TRANS ? P : Q;
+    }
+}
+
+// ---- pairwise sweeps over the batch ------------------------------------------
+
+// FP32 stream of the pairwise sweep (see k_pack_sym), per system: centred on
+// the system's origin and in units of 1/kappa.
+__global__ __launch_bounds__(TPB) void kb_pack_sym(const double *__restrict__ g, int64_t gtot,
+                                                   const SysDesc *__restrict__ sd,
+                                                   const int32_t *__restrict__ blk2sys,
+                                                   const double *__restrict__ x,
+                                                   Src12 *__restrict__ src, double eps,
+                                                   double sigma)
+{
+    const int64_t gi = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const SysDesc d = sd[blk2sys[blockIdx.x]];
+    const int64_t j = gi - d.goff;
+    const double *xv = x + 2 * d.goff;
+    Src12 s;
+    if (j < d.n) {
+        const double a = g[6 * gtot + gi];
+        const double ap = a * xv[d.npad + j] / sigma;
+        const double f = -3.0 * a * xv[j];
+        const double nx = g[3 * gtot + gi], ny = g[4 * gtot + gi], nz = g[5 * gtot + gi];
+        s.x = float((g[gi] - d.cx) * sigma);
+        s.y = float((g[gtot + gi] - d.cy) * sigma);
+        s.z = float((g[2 * gtot + gi] - d.cz) * sigma);
+        s.w = float((1.0 - 1.0 / eps) * ap);
+        s.mx = float(f * nx);
+        s.my = float(f * ny);
+        s.mz = float(f * nz);
+        s.pad = float(-ap / eps);
+        s.nx = float(-nx);
+        s.ny = float(-ny);
+        s.nz = float(-nz);
+    } else {
+        s.x = float((FAR_SRC + 8.0 * double(j - d.n) - d.cx) * sigma);
+        s.y = s.z = 0.f;
+        s.w = s.mx = s.my = s.mz = s.pad = 0.f;
+        s.nx = s.ny = s.nz = 0.f;
+    }
+    s.res = 0.f;
+    src[gi] = s;
+}
+
+// FP64 stream of the pairwise sweep (see k_pack_sym64), mode 0 forward, 1 transposed.
+__global__ __launch_bounds__(TPB) void kb_pack_sym64(const double *__restrict__ g, int64_t gtot,
+                                                     const SysDesc *__restrict__ sd,
+                                                     const int32_t *__restrict__ blk2sys,
+                                                     const double *__restrict__ x,
+                                                     Src10d *__restrict__ src, int mode)
+{
+    const int64_t gi = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const SysDesc d = sd[blk2sys[blockIdx.x]];
+    const int64_t j = gi - d.goff;
+    const double *xv = x + 2 * d.goff;
+    Src10d s;
+    if (j < d.n) {
+        const double a = g[6 * gtot + gi];
+        const double w = mode ? xv[j] : a * xv[d.npad + j];
+        const double f = mode ? xv[d.npad + j] : a * xv[j];
+        s.x = g[gi];
+        s.y = g[gtot + gi];
+        s.z = g[2 * gtot + gi];
+        s.w = w;
+        s.nx = g[3 * gtot + gi];
+        s.ny = g[4 * gtot + gi];
+        s.nz = g[5 * gtot + gi];
+        s.mx = f * s.nx;
+        s.my = f * s.ny;
+        s.mz = f * s.nz;
+    } else {
+        s.x = FAR_SRC + 8.0 * double(j - d.n);
+        s.y = s.z = 0.0;
+        s.w = s.mx = s.my = s.mz = s.nx = s.ny = s.nz = 0.0;
+    }
+    src[gi] = s;
+}
+
+template <bool SCALED>
+__global__ __launch_bounds__(TPB) void kb_pairs_f32_sym(const Src12 *__restrict__ src,
+                                                        const SysDesc *__restrict__ sd,
+                                                        const SItem *__restrict__ items,
+                                                        int64_t n_items,
+                                                        const int32_t *__restrict__ mask,
+                                                        double eps, double kappa,
+                                                        double *__restrict__ rowpart,
+                                                        float *__restrict__ colpart)
+{
+    __shared__ Src12 sh[TILE];
+    __shared__ float colw[TPB / 64][2 * TILE + 64];
+    const CoefF32 cf = coef_f32(eps, kappa, SCALED);
+    for (int64_t k = blockIdx.x; k < n_items; k += gridDim.x) {
+        const SItem w = items[k];
+        if (!mask[w.sys])
+            continue;
+        const SysDesc d = sd[w.sys];
+        sym_item_f32<SCALED>(src + d.goff, w.I, w.J0, w.J1, d.T, cf,
+                             rowpart + (int64_t)w.slot * (2 * TILE),
+                             colpart + d.cp0 * (2 * TILE), sh, colw);
+    }
+}
+
+template <bool TRANS>
+__global__ __launch_bounds__(TPB) void kb_pairs_f64_sym(const Src10d *__restrict__ src,
+                                                        const SysDesc *__restrict__ sd,
+                                                        const SItem *__restrict__ items,
+                                                        int64_t n_items,
+                                                        const int32_t *__restrict__ mask,
+                                                        double eps, double kappa,
+                                                        double *__restrict__ rowpart,
+                                                        double *__restrict__ colpart)
+{
+    __shared__ Src10d sh[TILE];
+    __shared__ double colw[TPB / 64][2 * TILE + 64];
+    PairParams pp;
+    pp.eps = eps;
+    pp.kappa = kappa;
+    pp.cx = pp.cy = pp.cz = 0.0;
+    const Coef<double> cf(pp);
+    for (int64_t k = blockIdx.x; k < n_items; k += gridDim.x) {
+        const SItem w = items[k];
+        if (!mask[w.sys])
+            continue;
+        const SysDesc d = sd[w.sys];
+        sym_item_f64<TRANS>(src + d.goff, w.I, w.J0, w.J1, d.T, cf,
+                            rowpart + (int64_t)w.slot * (2 * TILE),
+                            colpart + d.cp0 * (2 * TILE), sh, colw);
+    }
+}
+
+// Rows of masked systems from the pairwise partials: the item rows of the
+// point's tile, then the contributions of every lower tile, in that order.
+template <typename CT>
+__global__ __launch_bounds__(TPB) void kb_sym_finish(const double *__restrict__ rowpart,
+                                                     const CT *__restrict__ colpart,
+                                                     const int32_t *__restrict__ rs,
+                                                     const double *__restrict__ g, int64_t gtot,
+                                                     const SysDesc *__restrict__ sd,
+                                                     const int32_t *__restrict__ blk2sys,
+                                                     const int32_t *__restrict__ mask,
+                                                     const double *__restrict__ x, double alpha,
+                                                     double beta, int trans, double scale1,
+                                                     double scale2, double *__restrict__ y)
+{
+    const int b = blk2sys[blockIdx.x];
+    if (!mask[b])
+        return;
+    const SysDesc d = sd[b];
+    const int64_t gi = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const int64_t j = gi - d.goff;
+    const double *xv = x + 2 * d.goff;
+    double *yv = y + 2 * d.goff;
+    if (j >= d.n) {
+        yv[j] = 0.0;
+        yv[d.npad + j] = 0.0;
+        return;
+    }
+    const int K = (int)(j / TILE), l = (int)(j % TILE);
+    double s1 = 0.0, s2 = 0.0;
+    for (int q = rs[d.rs0 + K]; q < rs[d.rs0 + K + 1]; ++q) {
+        s1 += rowpart[(int64_t)q * (2 * TILE) + l];
+        s2 += rowpart[(int64_t)q * (2 * TILE) + TILE + l];
+    }
+    for (int I = 0; I < K; ++I) {
+        const CT *cp = colpart + (d.cp0 + sym_pair_index(I, K, d.T)) * (2 * TILE);
+        s1 += (double)cp[l];
+        s2 += (double)cp[TILE + l];
+    }
+    if (trans) {
+        const double sc = g[6 * gtot + gi] * INV_4PI;
+        yv[j] = alpha * xv[j] - sc * s2;
+        yv[d.npad + j] = beta * xv[d.npad + j] - sc * s1;
+    } else {
+        yv[j] = alpha * xv[j] - INV_4PI * scale1 * s1;
+        yv[d.npad + j] = beta * xv[d.npad + j] - INV_4PI * scale2 * s2;
     }
 }
 
@@ -653,6 +839,10 @@ struct BatchPlan {
     std::vector<SysDesc> sd;
     std::vector<Item> items, citems;
     std::vector<int32_t> blk2sys, vblk2sys, cblk2sys;
+    // pairwise sweeps: work items (longest first), row-slot table, tile pairs
+    std::vector<SItem> sitems;
+    std::vector<int32_t> rs;
+    int64_t n_slots = 0, cptot = 0;
 };
 
 void plan_batch(BatchPlan &P, int n_sys, const pb_surface *surf, const pb_charges *chg)
@@ -696,7 +886,24 @@ void plan_batch(BatchPlan &P, int n_sys, const pb_surface *surf, const pb_charge
             P.vblk2sys.push_back(b);
         for (int64_t k = 0; k < d.ncpad / TPB; ++k)
             P.cblk2sys.push_back(b);
+        // pairwise items: row I against tiles I.. in runs of SYM_TILES
+        d.T = nt;
+        d.rs0 = (int32_t)P.rs.size();
+        d.cp0 = P.cptot;
+        P.cptot += (int64_t)nt * (nt - 1) / 2;
+        for (int I = 0; I < nt; ++I) {
+            P.rs.push_back((int32_t)P.n_slots);
+            for (int J0 = I; J0 < nt; J0 += SYM_TILES) {
+                P.sitems.push_back({b, I, J0, std::min(nt, J0 + SYM_TILES),
+                                    (int32_t)P.n_slots, 0, 0, 0});
+                ++P.n_slots;
+            }
+        }
+        P.rs.push_back((int32_t)P.n_slots);
     }
+    std::stable_sort(P.sitems.begin(), P.sitems.end(), [](const SItem &a, const SItem &b) {
+        return a.J1 - a.J0 > b.J1 - b.J0;
+    });
 }
 
 struct BatchDev {
@@ -708,6 +915,10 @@ struct BatchDev {
     double *pos = nullptr, *q = nullptr;
     void *src = nullptr;            // 16 doubles per collocation point
     double *part = nullptr;
+    SItem *sitems = nullptr;         // pairwise sweeps
+    int32_t *rs = nullptr;
+    double *srow = nullptr;
+    void *scol = nullptr;            // FP32 or FP64 column partials
     double *x = nullptr, *b = nullptr, *w = nullptr, *r = nullptr, *t = nullptr, *lam = nullptr;
     double *pw = nullptr, *pb = nullptr;
     double *V = nullptr;
@@ -727,6 +938,81 @@ void pc_apply_batch(hipStream_t s, const BatchDev &D, int trans, const double *x
                     trans, y);
 }
 
+// y = A x (or A^T x) for the systems in `mask`, with the sweep kind the
+// context selects: pairwise (default) or per target.
+void enqueue_matvec(pb_ctx *c, const BatchPlan &P, BatchDev &D, bool f32, int trans,
+                    const int32_t *mask, double eps, double kap, const double *x, double *y)
+{
+    hipStream_t s = c->stream;
+    const int64_t ni = (int64_t)P.items.size();
+    const unsigned grid = (unsigned)std::min<int64_t>(ni, BATCH_GRID);
+    const unsigned gb = nblk(P.gtot);
+    const double alpha = 0.5 * (1.0 + eps), beta = 0.5 * (1.0 + 1.0 / eps);
+    const int64_t nsi = (int64_t)P.sitems.size();
+    const unsigned sgrid = (unsigned)std::min<int64_t>(nsi, BATCH_GRID);
+    if (f32 && !trans && c->f32_tpt == PB_SWEEP_PAIRWISE) {
+        const double sig = f32_sigma(kap);
+        hipLaunchKernelGGL(kb_pack_sym, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd, D.blk2sys,
+                           x, reinterpret_cast<Src12 *>(D.src), eps, sig);
+        if (kap > 0.0)
+            hipLaunchKernelGGL(kb_pairs_f32_sym<true>, dim3(sgrid), dim3(TPB), 0, s,
+                               reinterpret_cast<const Src12 *>(D.src), D.sd, D.sitems, nsi, mask,
+                               eps, kap, D.srow, static_cast<float *>(D.scol));
+        else
+            hipLaunchKernelGGL(kb_pairs_f32_sym<false>, dim3(sgrid), dim3(TPB), 0, s,
+                               reinterpret_cast<const Src12 *>(D.src), D.sd, D.sitems, nsi, mask,
+                               eps, kap, D.srow, static_cast<float *>(D.scol));
+        hipLaunchKernelGGL(kb_sym_finish<float>, dim3(gb), dim3(TPB), 0, s, D.srow,
+                           static_cast<const float *>(D.scol), D.rs, D.g, P.gtot, D.sd,
+                           D.blk2sys, mask, x, alpha, beta, 0, eps * sig * sig, sig * sig * sig,
+                           y);
+        return;
+    }
+    if (!f32 && c->f64_kind == PB_SWEEP_PAIRWISE) {
+        hipLaunchKernelGGL(kb_pack_sym64, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
+                           D.blk2sys, x, reinterpret_cast<Src10d *>(D.src), trans ? 1 : 0);
+        if (trans)
+            hipLaunchKernelGGL(kb_pairs_f64_sym<true>, dim3(sgrid), dim3(TPB), 0, s,
+                               reinterpret_cast<const Src10d *>(D.src), D.sd, D.sitems, nsi, mask,
+                               eps, kap, D.srow, static_cast<double *>(D.scol));
+        else
+            hipLaunchKernelGGL(kb_pairs_f64_sym<false>, dim3(sgrid), dim3(TPB), 0, s,
+                               reinterpret_cast<const Src10d *>(D.src), D.sd, D.sitems, nsi, mask,
+                               eps, kap, D.srow, static_cast<double *>(D.scol));
+        hipLaunchKernelGGL(kb_sym_finish<double>, dim3(gb), dim3(TPB), 0, s, D.srow,
+                           static_cast<const double *>(D.scol), D.rs, D.g, P.gtot, D.sd,
+                           D.blk2sys, mask, x, alpha, beta, trans, 1.0, 1.0, y);
+        return;
+    }
+    if (f32 && !trans) {
+        hipLaunchKernelGGL(kb_pack<float>, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
+                           D.blk2sys, x, reinterpret_cast<Src8<float> *>(D.src), 2, eps);
+        hipLaunchKernelGGL(kb_pairs_f32_fwd, dim3(grid), dim3(TPB), 0, s,
+                           reinterpret_cast<const Src8<float> *>(D.src), D.g, P.gtot, D.sd,
+                           D.items, ni, mask, eps, kap, D.part);
+    } else if (f32) {
+        hipLaunchKernelGGL(kb_pack<float>, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
+                           D.blk2sys, x, reinterpret_cast<Src8<float> *>(D.src), 1, eps);
+        hipLaunchKernelGGL((kb_pairs<float, true>), dim3(grid), dim3(TPB), 0, s,
+                           reinterpret_cast<const Src8<float> *>(D.src), D.g, P.gtot, D.sd,
+                           D.items, ni, mask, eps, kap, D.part);
+    } else {
+        hipLaunchKernelGGL(kb_pack<double>, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
+                           D.blk2sys, x, reinterpret_cast<Src8<double> *>(D.src), trans ? 1 : 0,
+                           eps);
+        if (trans)
+            hipLaunchKernelGGL((kb_pairs<double, true>), dim3(grid), dim3(TPB), 0, s,
+                               reinterpret_cast<const Src8<double> *>(D.src), D.g, P.gtot, D.sd,
+                               D.items, ni, mask, eps, kap, D.part);
+        else
+            hipLaunchKernelGGL((kb_pairs<double, false>), dim3(grid), dim3(TPB), 0, s,
+                               reinterpret_cast<const Src8<double> *>(D.src), D.g, P.gtot, D.sd,
+                               D.items, ni, mask, eps, kap, D.part);
+    }
+    hipLaunchKernelGGL(kb_finish, dim3(gb), dim3(TPB), 0, s, D.part, ni, D.g, P.gtot, D.sd,
+                       D.blk2sys, mask, x, alpha, beta, trans, (f32 && !trans) ? eps : 1.0, y);
+}
+
 // One restart cycle (m Arnoldi steps, update, FP64 residual, next start) on
 // the stream; captured into a graph by the caller.  With the preconditioner
 // the Krylov space is that of M^-1 A and residuals are M^-1 (rhs - A x).
@@ -736,42 +1022,12 @@ int enqueue_cycle(pb_ctx *c, const BatchPlan &P, BatchDev &D, const pb_params *p
     hipStream_t s = c->stream;
     const int m = p->restart, ns = P.n_sys;
     const double eps = p->eps_out / p->eps_in, kap = p->kappa;
-    const int64_t ni = (int64_t)P.items.size();
-    const unsigned grid = (unsigned)std::min<int64_t>(ni, BATCH_GRID);
-    const unsigned gb = nblk(P.gtot), vb = (unsigned)D.nvb;
+    const unsigned vb = (unsigned)D.nvb;
     const unsigned sb = (unsigned)((ns + 255) / 256);
-    const double alpha = 0.5 * (1.0 + eps), beta = 0.5 * (1.0 + 1.0 / eps);
     const bool f32 = p->precision == PB_FP32_IR;
     for (int j = 0; j < m; ++j) {
         const double *vj = D.V + (int64_t)j * D.ld;
-        if (f32 && !trans) {
-            hipLaunchKernelGGL(kb_pack<float>, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
-                               D.blk2sys, vj, reinterpret_cast<Src8<float> *>(D.src), 2, eps);
-            hipLaunchKernelGGL(kb_pairs_f32_fwd, dim3(grid), dim3(TPB), 0, s,
-                               reinterpret_cast<const Src8<float> *>(D.src), D.g, P.gtot, D.sd,
-                               D.items, ni, D.mask_step, eps, kap, D.part);
-        } else if (f32) {
-            hipLaunchKernelGGL(kb_pack<float>, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
-                               D.blk2sys, vj, reinterpret_cast<Src8<float> *>(D.src), 1, eps);
-            hipLaunchKernelGGL((kb_pairs<float, true>), dim3(grid), dim3(TPB), 0, s,
-                               reinterpret_cast<const Src8<float> *>(D.src), D.g, P.gtot, D.sd,
-                               D.items, ni, D.mask_step, eps, kap, D.part);
-        } else {
-            hipLaunchKernelGGL(kb_pack<double>, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
-                               D.blk2sys, vj, reinterpret_cast<Src8<double> *>(D.src),
-                               trans ? 1 : 0, eps);
-            if (trans)
-                hipLaunchKernelGGL((kb_pairs<double, true>), dim3(grid), dim3(TPB), 0, s,
-                                   reinterpret_cast<const Src8<double> *>(D.src), D.g, P.gtot,
-                                   D.sd, D.items, ni, D.mask_step, eps, kap, D.part);
-            else
-                hipLaunchKernelGGL((kb_pairs<double, false>), dim3(grid), dim3(TPB), 0, s,
-                                   reinterpret_cast<const Src8<double> *>(D.src), D.g, P.gtot,
-                                   D.sd, D.items, ni, D.mask_step, eps, kap, D.part);
-        }
-        hipLaunchKernelGGL(kb_finish, dim3(gb), dim3(TPB), 0, s, D.part, ni, D.g, P.gtot, D.sd,
-                           D.blk2sys, D.mask_step, vj, alpha, beta, trans,
-                           (f32 && !trans) ? eps : 1.0, D.w);
+        enqueue_matvec(c, P, D, f32, trans, D.mask_step, eps, kap, vj, D.w);
         double *wv = D.w;
         if (D.pc_leaves > 0) {
             pc_apply_batch(s, D, trans, D.w, D.pw);
@@ -799,18 +1055,7 @@ int enqueue_cycle(pb_ctx *c, const BatchPlan &P, BatchDev &D, const pb_params *p
     hipLaunchKernelGGL(kb_solve_y, dim3(sb), dim3(256), 0, s, D.st, ns, m);
     hipLaunchKernelGGL(kb_add_basis, dim3(vb), dim3(TPB), 0, s, D.V, D.ld, m, D.st, D.vblk2sys, x);
     // r = rhs - A x in FP64 for the systems of this cycle, then the next start
-    hipLaunchKernelGGL(kb_pack<double>, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd, D.blk2sys,
-                       x, reinterpret_cast<Src8<double> *>(D.src), trans ? 1 : 0, eps);
-    if (trans)
-        hipLaunchKernelGGL((kb_pairs<double, true>), dim3(grid), dim3(TPB), 0, s,
-                           reinterpret_cast<const Src8<double> *>(D.src), D.g, P.gtot, D.sd,
-                           D.items, ni, D.mask_run, eps, kap, D.part);
-    else
-        hipLaunchKernelGGL((kb_pairs<double, false>), dim3(grid), dim3(TPB), 0, s,
-                           reinterpret_cast<const Src8<double> *>(D.src), D.g, P.gtot, D.sd,
-                           D.items, ni, D.mask_run, eps, kap, D.part);
-    hipLaunchKernelGGL(kb_finish, dim3(gb), dim3(TPB), 0, s, D.part, ni, D.g, P.gtot, D.sd,
-                       D.blk2sys, D.mask_run, x, alpha, beta, trans, 1.0, D.w);
+    enqueue_matvec(c, P, D, false, trans, D.mask_run, eps, kap, x, D.w);
     if (D.pc_leaves > 0) {
         hipLaunchKernelGGL(kb_axpby, dim3(vb), dim3(TPB), 0, s, rhs, D.w, -1.0, D.pw);
         pc_apply_batch(s, D, trans, D.pw, D.r);
@@ -928,6 +1173,10 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
                                                P.cblk2sys.size())));
     TRY(ensure(c, c->b_items, sizeof(Item) * (ni + nci)));
     TRY(ensure(c, c->b_src, sizeof(double) * 16 * P.gtot));
+    TRY(ensure(c, c->b_sitems, sizeof(SItem) * std::max<size_t>(P.sitems.size(), 1)));
+    TRY(ensure(c, c->b_rs, sizeof(int32_t) * P.rs.size()));
+    TRY(ensure(c, c->b_srow, sizeof(double) * 2 * TILE * std::max<int64_t>(P.n_slots, 1)));
+    TRY(ensure(c, c->b_scol, sizeof(double) * 2 * TILE * std::max<int64_t>(P.cptot, 1)));
     TRY(ensure(c, c->b_part, sizeof(double) * TPB * std::max<int64_t>(2 * ni, 8 * nci)));
     TRY(ensure(c, c->b_vec, sizeof(double) * 8 * D.vtot));
     TRY(ensure(c, c->b_V, sizeof(double) * (m + 1) * D.vtot));
@@ -949,6 +1198,10 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     D.items = as<Item>(c->b_items);
     D.citems = D.items + ni;
     D.src = c->b_src.p;
+    D.sitems = as<SItem>(c->b_sitems);
+    D.rs = as<int32_t>(c->b_rs);
+    D.srow = as<double>(c->b_srow);
+    D.scol = c->b_scol.p;
     D.part = as<double>(c->b_part);
     double *vp = as<double>(c->b_vec);
     D.x = vp;
@@ -1019,6 +1272,9 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
         TRY(upload(c, D.cblk2sys, P.cblk2sys.data(), sizeof(int32_t) * P.cblk2sys.size()));
         TRY(upload(c, D.items, P.items.data(), sizeof(Item) * ni));
         TRY(upload(c, D.citems, P.citems.data(), sizeof(Item) * nci));
+        if (!P.sitems.empty())
+            TRY(upload(c, D.sitems, P.sitems.data(), sizeof(SItem) * P.sitems.size()));
+        TRY(upload(c, D.rs, P.rs.data(), sizeof(int32_t) * P.rs.size()));
         HIPCHK(hipStreamSynchronize(s));   // host staging vectors go out of scope
     }
     const double eps = p->eps_out / p->eps_in, kap = p->kappa;

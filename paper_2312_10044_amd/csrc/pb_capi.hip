@@ -979,7 +979,7 @@ void pb_destroy(pb_ctx *c)
                       &c->sym_rowstart, &c->sym_rowpart, &c->sym_colpart, &c->sym_src64,
                       &c->t_nodes,
                       &c->t_ctr, &c->t_perm, &c->t_geo, &c->t_wv, &c->t_out, &c->t_mom,
-                      &c->t_cnt};
+                      &c->t_cnt, &c->b_sitems, &c->b_rs, &c->b_srow, &c->b_scol};
     for (DevBuf *b : bufs)
         if (b->p)
             (void)hipFree(b->p);

@@ -73,6 +73,7 @@ struct pb_ctx {
     int64_t *pc_pidx = nullptr, *pc_qidx = nullptr;
     // batched solves (pb_solve_batch)
     pbk::DevBuf b_geo, b_desc, b_map, b_items, b_src, b_part, b_vec, b_V, b_state, b_red, b_chg;
+    pbk::DevBuf b_sitems, b_rs, b_srow, b_scol;   // pairwise sweeps of the batch
     pbk::DevBuf b_pc_idx, b_pc_inv;
     hipGraphExec_t b_graph = nullptr;
     uint64_t b_graph_key = 0;

@@ -481,5 +481,90 @@ __device__ __forceinline__ void sweep_pairwise64(const Src10d *sh, const OwnF64 
 }
 
 
+// ---- one work item of the pairwise sweeps ----------------------------------
+//
+// Target tile I of a system whose points start at `src` (T tiles), against its
+// source tiles J0..J1-1 (J0 >= I; the tile J = I runs forward only).  Row sums
+// go to rp[0..TILE) and rp[TILE..2 TILE), the contributions of tile pair
+// (I, J) to the rows of tile J to cp_base + pair_index(I, J) * 2 TILE.  Block
+// of TPB threads; sh and colw are the block's LDS.
+
+template <bool SCALED>
+__device__ __forceinline__ void sym_item_f32(const Src12 *__restrict__ src, int I, int J0, int J1,
+                                             int T, const CoefF32 &cf, double *__restrict__ rp,
+                                             float *__restrict__ cp_base, Src12 *sh,
+                                             float (*colw)[2 * TILE + 64])
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const OwnF32 o = own_point(src[(int64_t)I * TILE + threadIdx.x]);
+    Acc<float> aP, aQ;
+    for (int J = J0; J < J1; ++J) {
+        __syncthreads();
+        sh[threadIdx.x] = src[(int64_t)J * TILE + threadIdx.x];
+        __syncthreads();
+        float P = 0.f, Q = 0.f;
+        if (J == I) {
+            sweep_diag<SCALED>(sh, o, cf, P, Q);
+        } else {
+            sweep_pairwise<SCALED>(sh, o, cf, P, Q, colw[wid], lane);
+            __syncthreads();
+            float *cp = cp_base + sym_pair_index(I, J, T) * (2 * TILE);
+            const int t = threadIdx.x;
+            cp[t] = ((colw[0][t] + colw[1][t]) + colw[2][t]) + colw[3][t];
+            cp[TILE + t] = ((colw[0][TILE + t] + colw[1][TILE + t]) + colw[2][TILE + t]) +
+                           colw[3][TILE + t];
+        }
+        aP.add(P);
+        aQ.add(Q);
+    }
+    rp[threadIdx.x] = aP.value();
+    rp[TILE + threadIdx.x] = aQ.value();
+}
+
+template <bool TRANS>
+__device__ __forceinline__ void sym_item_f64(const Src10d *__restrict__ src, int I, int J0,
+                                             int J1, int T, const Coef<double> &cf,
+                                             double *__restrict__ rp,
+                                             double *__restrict__ cp_base, Src10d *sh,
+                                             double (*colw)[2 * TILE + 64])
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const OwnF64 o = own_point64(src[(int64_t)I * TILE + threadIdx.x]);
+    double aP = 0.0, aQ = 0.0;
+    for (int J = J0; J < J1; ++J) {
+        __syncthreads();
+        sh[threadIdx.x] = src[(int64_t)J * TILE + threadIdx.x];
+        __syncthreads();
+        double P = 0.0, Q = 0.0;
+        if (J == I) {
+            sweep_diag64<TRANS>(sh, o, cf, P, Q);
+        } else {
+            sweep_pairwise64<TRANS>(sh, o, cf, P, Q, colw[wid], lane);
+            __syncthreads();
+            double *cp = cp_base + sym_pair_index(I, J, T) * (2 * TILE);
+            const int t = threadIdx.x;
+            cp[t] = ((colw[0][t] + colw[1][t]) + colw[2][t]) + colw[3][t];
+            cp[TILE + t] = ((colw[0][TILE + t] + colw[1][TILE + t]) + colw[2][TILE + t]) +
+                           colw[3][TILE + t];
+        }
+        aP += P;
+        aQ += Q;
+    }
+    rp[threadIdx.x] = aP;
+    rp[TILE + threadIdx.x] = aQ;
+}
+
+inline __device__ CoefF32 coef_f32(double eps, double kappa, bool scaled)
+{
+    const double kap = scaled ? 1.0 : kappa;   // kappa in the stream's length unit
+    CoefF32 cf;
+    cf.kappa = float(kap);
+    cf.kexp = float(-kap * 1.4426950408889634074);
+    cf.c13 = float((1.0 - 1.0 / eps) / 3.0);
+    cf.k23 = float(kap * kap / 3.0);
+    return cf;
+}
+
+
 }  // namespace dev
 }  // namespace pbk

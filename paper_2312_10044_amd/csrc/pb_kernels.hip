@@ -301,38 +301,8 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_sym(const Src12 *__restrict__
     __shared__ Src12 sh[TILE];
     __shared__ float colw[TPB / 64][2 * TILE + 64];
     const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
-    const int I = it.x;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const OwnF32 o = own_point(src[(int64_t)I * TILE + threadIdx.x]);
-    const double kap = SCALED ? 1.0 : pp.kappa;   // kappa in the stream's length unit
-    CoefF32 cf;
-    cf.kappa = float(kap);
-    cf.kexp = float(-kap * 1.4426950408889634074);
-    cf.c13 = float((1.0 - 1.0 / pp.eps) / 3.0);
-    cf.k23 = float(kap * kap / 3.0);
-    Acc<float> aP, aQ;
-    for (int J = it.y; J < it.z; ++J) {
-        __syncthreads();
-        sh[threadIdx.x] = src[(int64_t)J * TILE + threadIdx.x];
-        __syncthreads();
-        float P = 0.f, Q = 0.f;
-        if (J == I) {
-            sweep_diag<SCALED>(sh, o, cf, P, Q);
-        } else {
-            sweep_pairwise<SCALED>(sh, o, cf, P, Q, colw[wid], lane);
-            __syncthreads();
-            float *cp = colpart + sym_pair_index(I, J, T) * (2 * TILE);
-            const int t = threadIdx.x;
-            cp[t] = ((colw[0][t] + colw[1][t]) + colw[2][t]) + colw[3][t];
-            cp[TILE + t] = ((colw[0][TILE + t] + colw[1][TILE + t]) + colw[2][TILE + t]) +
-                           colw[3][TILE + t];
-        }
-        aP.add(P);
-        aQ.add(Q);
-    }
-    double *rp = rowpart + (int64_t)it.w * (2 * TILE);
-    rp[threadIdx.x] = aP.value();
-    rp[TILE + threadIdx.x] = aQ.value();
+    sym_item_f32<SCALED>(src, it.x, it.y, it.z, T, coef_f32(pp.eps, pp.kappa, SCALED),
+                         rowpart + (int64_t)it.w * (2 * TILE), colpart, sh, colw);
 }
 
 // Row k = K*TILE + l: item rows of tile K, then the contributions of every tile
@@ -416,33 +386,8 @@ __global__ __launch_bounds__(TPB) void k_pairs_f64_sym(const Src10d *__restrict_
     __shared__ Src10d sh[TILE];
     __shared__ double colw[TPB / 64][2 * TILE + 64];
     const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
-    const int I = it.x;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const OwnF64 o = own_point64(src[(int64_t)I * TILE + threadIdx.x]);
-    const Coef<double> cf(pp);
-    double aP = 0.0, aQ = 0.0;
-    for (int J = it.y; J < it.z; ++J) {
-        __syncthreads();
-        sh[threadIdx.x] = src[(int64_t)J * TILE + threadIdx.x];
-        __syncthreads();
-        double P = 0.0, Q = 0.0;
-        if (J == I) {
-            sweep_diag64<TRANS>(sh, o, cf, P, Q);
-        } else {
-            sweep_pairwise64<TRANS>(sh, o, cf, P, Q, colw[wid], lane);
-            __syncthreads();
-            double *cp = colpart + sym_pair_index(I, J, T) * (2 * TILE);
-            const int t = threadIdx.x;
-            cp[t] = ((colw[0][t] + colw[1][t]) + colw[2][t]) + colw[3][t];
-            cp[TILE + t] = ((colw[0][TILE + t] + colw[1][TILE + t]) + colw[2][TILE + t]) +
-                           colw[3][TILE + t];
-        }
-        aP += P;
-        aQ += Q;
-    }
-    double *rp = rowpart + (int64_t)it.w * (2 * TILE);
-    rp[threadIdx.x] = aP;
-    rp[TILE + threadIdx.x] = aQ;
+    sym_item_f64<TRANS>(src, it.x, it.y, it.z, T, Coef<double>(pp),
+                        rowpart + (int64_t)it.w * (2 * TILE), colpart, sh, colw);
 }
 
 __global__ __launch_bounds__(TPB) void k_matvec_finish(const double *__restrict__ part,

@@ -126,3 +126,27 @@ def test_batch_preconditioned_fp32_refined(pb, small_batch):
     for b in range(len(small_batch)):
         assert infos[b].status == m.PB_OK and infos[b].matvecs_fp32 > 0
         assert abs(e32[b] - e64[b]) <= 1e-6 * abs(e64[b])
+
+
+def test_batch_sweep_kinds_agree(pb, small_batch):
+    """The batch with per-target sweeps (FP32 and FP64) against the default
+    pairwise sweeps: same energies and forces up to rounding."""
+    m, ctx = pb
+    P = m.Params(tol=1e-12, precond_leaf=16)
+    e_pw, _i, g_pw, q_pw = ctx.pb_solve_batch(small_batch, P, forces=True)
+    ctx.set_sweep_config(1, 0)
+    ctx.set_fp64_sweep(1)
+    try:
+        e_pt, _i, g_pt, q_pt = ctx.pb_solve_batch(small_batch, P, forces=True)
+        e32_pt, _i, _g, _q = ctx.pb_solve_batch(
+            small_batch, m.Params(tol=1e-8, precision=m.PB_FP32_IR, precond_leaf=16))
+    finally:
+        ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 0)
+        ctx.set_fp64_sweep(m.PB_SWEEP_PAIRWISE)
+    e32_pw, _i, _g, _q = ctx.pb_solve_batch(
+        small_batch, m.Params(tol=1e-8, precision=m.PB_FP32_IR, precond_leaf=16))
+    assert np.max(np.abs(e_pw - e_pt) / np.abs(e_pt)) <= 1e-10
+    assert np.abs(g_pw - g_pt).max() <= 1e-8 * np.abs(g_pt).max()
+    assert np.abs(q_pw - q_pt).max() <= 1e-8 * np.abs(q_pt).max()
+    assert np.max(np.abs(e32_pw - e_pt) / np.abs(e_pt)) <= 1e-6
+    assert np.max(np.abs(e32_pt - e_pt) / np.abs(e_pt)) <= 1e-6
