@@ -256,7 +256,7 @@ def main():
                          "reference kernel that calibrates FETCH_SIZE/WRITE_SIZE); batch: 64 "
                          "uneven systems in one call; tree: treecode matvec vs the direct sums")
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--precond-leaf", type=int, default=16,
+    ap.add_argument("--precond-leaf", type=int, default=24,
                     help="leaf size of the block-diagonal preconditioner (0 = none)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the FP32 sweep configurations first and use the fastest")
