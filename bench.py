@@ -181,29 +181,15 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def run_tree(args):
-    """Treecode matvec (theta 0.8, p 3, N0 100 unless given) against the
-    direct sums on the same surface: kernel time per matvec (cluster moments
-    plus tree walk; the host-side tree build is reported separately as part
-    of the call's wall time) and the error against the FP64 direct matvec."""
+def _tree_record(ctx, w, args, pbs, Params, PB_FP64, PB_FP32_IR, PB_SWEEP_PAIRWISE):
     import numpy as np
     import torch
-
-    import synth
-    from paper_2312_10044_amd import Context, Params, PB_FP64, PB_FP32_IR, PB_SWEEP_PAIRWISE
-    from paper_2312_10044_amd import pbsolve as pbs
-
-    w = synth.star_protein() if args.workload == "star81920" else synth.large_star_protein()
     N = w.n_tri
-    ctx = Context(0)
     base = Params(eps_in=w.eps_in, eps_out=w.eps_out, kappa=w.kappa)
     x = np.random.default_rng(0).normal(size=2 * N)
-    out = {"mode": "tree", "n_tri": N, "theta": args.theta, "order": args.order,
-           "leaf_size": args.leaf}
+    out = {"n_tri": N}
     y64 = ctx.pb_matvec(w.verts, w.tris, x, base, precision=PB_FP64)
-    ctx.set_sweep_config(PB_SWEEP_PAIRWISE, 0)
     ctx.pb_matvec(w.verts, w.tris, x, base, precision=PB_FP32_IR)
-    rows = []
     for kid, prec, label in ((pbs.PB_KERNEL_PAIRS_FP64, PB_FP64, "direct_fp64"),
                              (pbs.PB_KERNEL_PAIRS_FP32, PB_FP32_IR, "direct_fp32_pairwise")):
         ctx.profile_reset()
@@ -233,7 +219,68 @@ def run_tree(args):
     out["speedup_tree_vs_fp64_direct"] = out["direct_fp64"]["ms"] / out["treecode"]["ms"]
     out["speedup_tree_vs_fp32_pairwise"] = (out["direct_fp32_pairwise"]["ms"]
                                             / out["treecode"]["ms"])
+    return out
+
+
+def run_tree(args):
+    """Treecode matvec (theta 0.8, p 3, N0 100 unless given) against the
+    direct sums: kernel time per matvec (cluster moments plus tree walk; the
+    host-side tree build is in the call's wall time) and the error against the
+    FP64 direct matvec.  --tree-freqs lists star surfaces of 20 f^2 triangles
+    (the break-even sweep); otherwise --workload is used."""
+    import synth
+    from paper_2312_10044_amd import Context, Params, PB_FP64, PB_FP32_IR, PB_SWEEP_PAIRWISE
+    from paper_2312_10044_amd import pbsolve as pbs
+
+    if args.tree_freqs:
+        works = [synth.star_protein(freq=int(f), r0=20.0 * int(f) / 64.0, n_charges=1, seed=2)
+                 for f in args.tree_freqs.split(",")]
+    else:
+        works = [synth.star_protein() if args.workload == "star81920"
+                 else synth.large_star_protein()]
+    ctx = Context(0)
+    ctx.set_sweep_config(PB_SWEEP_PAIRWISE, 0)
+    recs = []
+    for w in works:
+        _log(f"bench tree: {w.n_tri} triangles")
+        recs.append(_tree_record(ctx, w, args, pbs, Params, PB_FP64, PB_FP32_IR,
+                                 PB_SWEEP_PAIRWISE))
+    solve_cmp = None
+    if len(works) == 1:
+        # whole solves: treecode GMRES against the direct solves, same preconditioner
+        w = works[0]
+        base = dict(eps_in=w.eps_in, eps_out=w.eps_out, kappa=w.kappa, restart=10,
+                    max_iter=2000)
+        args_s = (w.verts, w.tris, w.pos, w.q)
+        ref, _p, _d = ctx.pb_solve(*args_s, Params(tol=1e-12, **base))
+        solve_cmp = {}
+        for label, fn, prm in (
+                ("treecode_fp64", "tree", Params(tol=1e-6, precond_leaf=args.precond_leaf,
+                                                 **base)),
+                ("direct_fp64", "direct", Params(tol=1e-6, precond_leaf=args.precond_leaf,
+                                                 **base)),
+                ("direct_fp32_ir", "direct", Params(tol=1e-6, precision=PB_FP32_IR,
+                                                    inner_tol=1e-7,
+                                                    precond_leaf=args.precond_leaf, **base))):
+            def run():
+                if fn == "tree":
+                    return ctx.pb_solve_tree(*args_s, prm, theta=args.theta, order=args.order,
+                                             leaf_size=args.leaf)[0]
+                return ctx.pb_solve(*args_s, prm)[0]
+            run()
+            t0 = time.perf_counter()
+            info = run()
+            dt = time.perf_counter() - t0
+            solve_cmp[label] = {"seconds": dt, "iters": info.iters, "status": info.status,
+                                "e_rel_err": abs(info.e_solv - ref.e_solv) / abs(ref.e_solv)}
+        _log(f"bench tree: solves {solve_cmp}")
     ctx.close()
+    out = {"mode": "tree", "theta": args.theta, "order": args.order, "leaf_size": args.leaf}
+    if len(recs) == 1:
+        out.update(recs[0])
+        out["solve_tol_1e-6_host_arrays"] = solve_cmp
+    else:
+        out["sizes"] = recs
     print(json.dumps(out), flush=True)
 
 
@@ -249,6 +296,9 @@ def main():
     ap.add_argument("--theta", type=float, default=0.8, help="treecode MAC parameter (mode tree)")
     ap.add_argument("--order", type=int, default=3, help="treecode Taylor order (mode tree)")
     ap.add_argument("--leaf", type=int, default=100, help="treecode leaf size N0 (mode tree)")
+    ap.add_argument("--tree-freqs", default="",
+                    help="mode tree: comma-separated star frequencies f (20 f^2 triangles, "
+                         "radius scaled with f) for a break-even sweep")
     ap.add_argument("--mode", choices=["solve", "matvec", "copy", "batch", "tree"],
                     default="solve",
                     help="solve: the benchmark; matvec: only --steps matvecs of --precision "

@@ -239,6 +239,15 @@ int pb_precond_apply(pb_ctx *ctx, const pb_surface *s, const pb_params *p, const
  * N0 = 100. */
 int pb_matvec_tree(pb_ctx *ctx, const pb_surface *s, const pb_params *p, double theta,
                    int order, int leaf_size, const double *x, double *y, int64_t *counts);
+/* pb_solve with every GMRES matvec (Arnoldi steps and true-residual checks)
+ * replaced by the treecode matvec above, as the paper's treecode solver does
+ * (Sec. 2.2.3); the tree is built once per call.  p->precision must be
+ * PB_FP64; p->precond_leaf selects the block-diagonal preconditioner as in
+ * pb_solve.  Outputs, units and status codes as pb_solve; E_sol carries the
+ * treecode's approximation error. */
+int pb_solve_tree(pb_ctx *ctx, const pb_surface *s, const pb_charges *q, const pb_params *p,
+                  double theta, int order, int leaf_size, double *phi, double *dphi,
+                  pb_info *info);
 
 /* ---- launch configuration and autotuning ------------------------------- */
 /* The FP32 forward pair sweep (the hot loop of PB_FP32_IR solves) comes in

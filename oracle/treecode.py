@@ -274,45 +274,76 @@ def far_rows(T0, Tk, alg: SeriesAlgebra, M, D, nrm_t, eps: float, p: int):
     return r1, r2
 
 
+class TreeOperator:
+    """The treecode matvec for one geometry: the tree, every target's
+    interaction lists and the Taylor coefficients of each accepted
+    (target, cluster) pair are formed once; apply() then needs only the
+    moments of the current vector.  With `rows`, only those rows are formed
+    and apply() returns (y1, y2) for them."""
+
+    def __init__(self, g: Geometry, eps: float, kappa: float, theta: float, p: int, n0: int,
+                 rows=None):
+        self.g, self.eps, self.kappa, self.p = g, eps, kappa, p
+        self.rows = None if rows is None else np.asarray(rows)
+        self.tree = build_tree(g.cen, n0)
+        far, near = interaction_lists(self.tree, g.cen, theta, rows)
+        targets = range(g.n) if rows is None else rows
+        self.near = [(i, np.concatenate([c.idx for c in near[i]])) for i in targets if near[i]]
+        users = {}
+        for i in targets:
+            for c in far[i]:
+                users.setdefault(id(c), (c, []))[1].append(i)
+        self.far = []
+        for c, tl in users.values():
+            tl = np.asarray(tl, dtype=np.int64)
+            alg, T0, Tk = taylor_coefficients(g.cen[tl] - c.center, kappa, p + 2)
+            self.far.append((c, tl, alg, T0, Tk))
+
+    def apply(self, xi: np.ndarray):
+        g, eps, kappa, p = self.g, self.eps, self.kappa, self.p
+        n = g.n
+        xi = f64(xi)
+        phi, psi = xi[:n], xi[n:]
+        s1 = np.zeros(n)
+        s2 = np.zeros(n)
+        for i, j in self.near:
+            a1, a2 = _direct_rows(g, eps, kappa, phi, psi, i, j)
+            s1[i] += a1
+            s2[i] += a2
+        for c, tl, alg, T0, Tk in self.far:
+            M, D = moments(g, phi, psi, c, p)
+            r1, r2 = far_rows(T0, Tk, alg, M, D, g.nrm[tl], eps, p)
+            np.add.at(s1, tl, r1)
+            np.add.at(s2, tl, r2)
+        inv4pi = 1.0 / (4.0 * np.pi)
+        if self.rows is not None:
+            r = self.rows
+            return (0.5 * (1.0 + eps) * phi[r] - inv4pi * s1[r],
+                    0.5 * (1.0 + 1.0 / eps) * psi[r] - inv4pi * s2[r])
+        y = np.empty(2 * n)
+        y[:n] = 0.5 * (1.0 + eps) * phi - inv4pi * s1
+        y[n:] = 0.5 * (1.0 + 1.0 / eps) * psi - inv4pi * s2
+        return y
+
+
 def matvec(g: Geometry, eps: float, kappa: float, xi: np.ndarray, theta: float, p: int,
            n0: int, rows=None):
     """y = A xi with the pair sums replaced by the treecode approximation.
     With `rows`, only those rows of both blocks are formed and (y1, y2) for
     them is returned."""
-    n = g.n
-    xi = f64(xi)
-    phi, psi = xi[:n], xi[n:]
-    tree = build_tree(g.cen, n0)
-    far, near = interaction_lists(tree, g.cen, theta, rows)
-    s1 = np.zeros(n)
-    s2 = np.zeros(n)
-    for i in (range(n) if rows is None else rows):
-        if near[i]:
-            j = np.concatenate([c.idx for c in near[i]])
-            a1, a2 = _direct_rows(g, eps, kappa, phi, psi, i, j)
-            s1[i] += a1
-            s2[i] += a2
-    # far field cluster by cluster, vectorised over the targets that accept it
-    users = {}
-    for i in range(n):
-        for c in far[i]:
-            users.setdefault(id(c), (c, []))[1].append(i)
-    for c, tl in users.values():
-        tl = np.asarray(tl, dtype=np.int64)
-        alg, T0, Tk = taylor_coefficients(g.cen[tl] - c.center, kappa, p + 2)
-        M, D = moments(g, phi, psi, c, p)
-        r1, r2 = far_rows(T0, Tk, alg, M, D, g.nrm[tl], eps, p)
-        np.add.at(s1, tl, r1)
-        np.add.at(s2, tl, r2)
-    inv4pi = 1.0 / (4.0 * np.pi)
-    if rows is not None:
-        rows = np.asarray(rows)
-        return (0.5 * (1.0 + eps) * phi[rows] - inv4pi * s1[rows],
-                0.5 * (1.0 + 1.0 / eps) * psi[rows] - inv4pi * s2[rows])
-    y = np.empty(2 * n)
-    y[:n] = 0.5 * (1.0 + eps) * phi - inv4pi * s1
-    y[n:] = 0.5 * (1.0 + 1.0 / eps) * psi - inv4pi * s2
-    return y
+    return TreeOperator(g, eps, kappa, theta, p, n0, rows).apply(xi)
+
+
+def solve(verts, tris, pos, q, theta: float, p: int, n0: int, eps_in=1.0, eps_out=80.0,
+          kappa=0.1257, tol=1e-6, restart=10, max_iter=1000):
+    """The FP64 DSBI solve of the oracle with the treecode matvec in GMRES."""
+    from .dsbi import _ratios, energy, geometry, gmres, source
+    g = geometry(f64(verts), np.asarray(tris))
+    eps = _ratios(eps_in, eps_out)
+    b = source(g, pos, q, eps_in)
+    op = TreeOperator(g, eps, kappa, theta, p, n0)
+    xi, info = gmres(op.apply, b, restart=restart, tol=tol, max_iter=max_iter)
+    return energy(g, eps, kappa, xi, pos, q), xi, info
 
 
 def counts(g: Geometry, theta: float, n0: int):

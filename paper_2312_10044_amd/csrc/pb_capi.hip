@@ -56,7 +56,8 @@ int check_params(pb_ctx *c, const pb_params *p, bool solving)
 int setup_geometry(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
                    const int32_t *d_tri)
 {
-    c->pc_leaves = 0;   // a preconditioner belongs to one geometry
+    c->pc_leaves = 0;   // a preconditioner and a tree belong to one geometry
+    c->t_ready = false;
     if (n_tri <= 0 || n_vert < 3)
         return fail(c, PB_ERR_ARG, "need n_tri > 0 and n_vert >= 3");
     if (n_tri > (int64_t)1 << 30)
@@ -192,6 +193,10 @@ int apply_pairwise64(pb_ctx *c, const pb_params *p, int transpose, const double 
 int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const double *x, double *y)
 {
     const Geo &g = c->g;
+    if (c->t_solve && precision == PB_FP64 && !transpose) {   // pb_solve_tree
+        TRY(tree_prepare(c, c->t_solve_n0));
+        return tree_apply(c, p, c->t_theta, c->t_order, x, y, nullptr);
+    }
     if (precision == PB_FP32_IR && !transpose && c->f32_tpt == PB_SWEEP_PAIRWISE)
         return apply_pairwise(c, p, x, y);
     if (precision == PB_FP64 && c->f64_kind == PB_SWEEP_PAIRWISE)
@@ -1161,6 +1166,31 @@ static int pb_solve_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q, co
     return st;
 }
 
+static int pb_solve_tree_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q,
+                              const pb_params *p, double theta, int order, int leaf_size,
+                              double *phi, double *dphi, pb_info *info)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    if (!(theta >= 0.0 && theta < 1.0))
+        return fail(c, PB_ERR_ARG, "theta must lie in [0, 1)");
+    if (order < 0 || order > 5)
+        return fail(c, PB_ERR_ARG, "treecode order must be 0..5");
+    if (leaf_size < 1)
+        return fail(c, PB_ERR_ARG, "leaf_size must be >= 1");
+    if (p && p->precision != PB_FP64)
+        return fail(c, PB_ERR_ARG, "treecode solves run in FP64 (precision PB_FP64)");
+    struct Off {
+        pb_ctx *c;
+        ~Off() { c->t_solve = false; }
+    } off{c};
+    c->t_solve = true;
+    c->t_theta = theta;
+    c->t_order = order;
+    c->t_solve_n0 = leaf_size;
+    return pb_solve_impl(c, s, q, p, phi, dphi, info);
+}
+
 static int pb_forces_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q,
                           const pb_params *p, double *dE_dpos, double *dE_dq, pb_info *info)
 {
@@ -1228,6 +1258,13 @@ int pb_matvec(pb_ctx *c, const pb_surface *s, const pb_params *p, const double *
               int transpose, int precision)
 {
     return leave(c, pb_matvec_impl(c, s, p, x, y, transpose, precision));
+}
+
+int pb_solve_tree(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
+                  double theta, int order, int leaf_size, double *phi, double *dphi,
+                  pb_info *info)
+{
+    return leave(c, pb_solve_tree_impl(c, s, q, p, theta, order, leaf_size, phi, dphi, info));
 }
 
 int pb_matvec_tree(pb_ctx *c, const pb_surface *s, const pb_params *p, double theta, int order,

@@ -61,6 +61,12 @@ struct pb_ctx {
     int sym_waves = 0;
     // treecode: tree, permuted geometry and weights, moments, results
     pbk::DevBuf t_nodes, t_ctr, t_perm, t_geo, t_wv, t_out, t_mom, t_cnt;
+    bool t_ready = false;     // tree of the current geometry built (reset by setup_geometry)
+    int t_n0 = 0, t_n_nodes = 0;
+    // treecode matvec inside solves (pb_solve_tree): FP64 forward matvecs use it
+    bool t_solve = false;
+    double t_theta = 0.0;
+    int t_order = 0, t_solve_n0 = 0;
     // current geometry
     pbk::Geo g{};
     double center[3] = {0.0, 0.0, 0.0};
@@ -200,6 +206,9 @@ void build_leaves(const double *x, const double *y, const double *z, int64_t n, 
 // Batched solve of independent systems (pb_batch.hip).
 int tree_matvec(pb_ctx *c, const pb_params *p, double theta, int order, int n0, const double *x,
                 double *y, int64_t *counts);
+int tree_prepare(pb_ctx *c, int n0);
+int tree_apply(pb_ctx *c, const pb_params *p, double theta, int order, const double *x,
+               double *y, int64_t *counts);
 int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
                 const pb_params *p, int want_forces, double *e_solv, double *dE_dpos,
                 double *dE_dq, pb_info *info);

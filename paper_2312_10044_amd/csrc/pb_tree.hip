@@ -396,11 +396,14 @@ void build_tree(const double *x, const double *y, const double *z, int64_t n, in
     Rec::go(x, y, z, n0, all, c0, h0, 0, perm, node_i, node_d);
 }
 
-// ---- host: one treecode matvec on the context's geometry ---------------------------
+// ---- host: the tree of the context's geometry, then treecode matvecs -------------
 
-int tree_matvec(pb_ctx *c, const pb_params *p, double theta, int order, int n0, const double *x,
-                double *y, int64_t *counts)
+// Builds (or keeps) the tree of the current geometry with leaves of at most
+// n0 points, and the permuted geometry.
+int tree_prepare(pb_ctx *c, int n0)
 {
+    if (c->t_ready && c->t_n0 == n0)
+        return PB_OK;
     const Geo &g = c->g;
     const int64_t n = g.n;
     std::vector<double> h(3 * g.npad);
@@ -411,30 +414,44 @@ int tree_matvec(pb_ctx *c, const pb_params *p, double theta, int order, int n0, 
     std::vector<double> node_d;
     build_tree(h.data(), h.data() + g.npad, h.data() + 2 * g.npad, n, n0, perm, node_i, node_d);
     const int n_nodes = (int)(node_i.size() / 4);
-    const int NT = nterms(order);
     TRY(ensure(c, c->t_nodes, sizeof(int32_t) * node_i.size()));
     TRY(ensure(c, c->t_ctr, sizeof(double) * node_d.size()));
     TRY(ensure(c, c->t_perm, sizeof(int32_t) * n));
     TRY(ensure(c, c->t_geo, sizeof(double) * 6 * n));
     TRY(ensure(c, c->t_wv, sizeof(double) * 2 * n));
     TRY(ensure(c, c->t_out, sizeof(double) * 2 * n));
-    TRY(ensure(c, c->t_mom, sizeof(double) * 4 * NT * (size_t)n_nodes));
-    if (counts)
-        TRY(ensure(c, c->t_cnt, sizeof(int64_t) * 2 * n));
     HIPCHK(hipMemcpyAsync(c->t_nodes.p, node_i.data(), sizeof(int32_t) * node_i.size(),
                           hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->t_ctr.p, node_d.data(), sizeof(double) * node_d.size(),
                           hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->t_perm.p, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
                           c->stream));
+    hipLaunchKernelGGL(kt_permute, dim3(nblk(n)), dim3(TPB), 0, c->stream,
+                       as<int32_t>(c->t_perm), n, g.g, g.npad, as<double>(c->t_geo));
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(c->stream));   // host vectors go out of scope
+    c->t_n_nodes = n_nodes;
+    c->t_n0 = n0;
+    c->t_ready = true;
+    return PB_OK;
+}
+
+// y = A x with the treecode (needs tree_prepare for the current geometry).
+int tree_apply(pb_ctx *c, const pb_params *p, double theta, int order, const double *x,
+               double *y, int64_t *counts)
+{
+    const Geo &g = c->g;
+    const int64_t n = g.n;
+    const int n_nodes = c->t_n_nodes;
+    const int NT = nterms(order);
+    TRY(ensure(c, c->t_mom, sizeof(double) * 4 * NT * (size_t)n_nodes));
+    if (counts)
+        TRY(ensure(c, c->t_cnt, sizeof(int64_t) * 2 * n));
     const auto *nodes = as<TreeNode>(c->t_nodes);
     const auto *ctr = as<double4>(c->t_ctr);
     const int32_t *dperm = as<int32_t>(c->t_perm);
     double *tg = as<double>(c->t_geo), *wv = as<double>(c->t_wv), *out = as<double>(c->t_out);
     double *mom = as<double>(c->t_mom);
-    hipLaunchKernelGGL(kt_permute, dim3(nblk(n)), dim3(TPB), 0, c->stream, dperm, n, g.g, g.npad,
-                       tg);
-    LAUNCHCHK();
     hipLaunchKernelGGL(kt_gather, dim3(nblk(n)), dim3(TPB), 0, c->stream, dperm, n,
                        g.g + 6 * g.npad, x, wv);
     LAUNCHCHK();
@@ -478,6 +495,13 @@ int tree_matvec(pb_ctx *c, const pb_params *p, double theta, int order, int n0, 
         counts[2] = n_nodes;
     }
     return PB_OK;
+}
+
+int tree_matvec(pb_ctx *c, const pb_params *p, double theta, int order, int n0, const double *x,
+                double *y, int64_t *counts)
+{
+    TRY(tree_prepare(c, n0));
+    return tree_apply(c, p, theta, order, x, y, counts);
 }
 
 }  // namespace pbk

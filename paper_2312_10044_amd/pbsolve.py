@@ -76,6 +76,9 @@ _PROTOS = {
                          _int, _int]),
     "pb_matvec_tree": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params), _dbl,
                               _int, _int, _vp, _vp, _vp]),
+    "pb_solve_tree": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
+                             ctypes.POINTER(_Params), _dbl, _int, _int, _vp, _vp,
+                             ctypes.POINTER(_Info)]),
     "pb_energy": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
                          ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_dbl)]),
     "pb_solve": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
@@ -305,6 +308,21 @@ class Context:
         self._check(self._L.pb_solve(self._h, ctypes.byref(s), ctypes.byref(c), ctypes.byref(p),
                                      _vp(phi.ctypes.data), _vp(dphi.ctypes.data),
                                      ctypes.byref(info)))
+        return Info.of(info), phi, dphi
+
+    def pb_solve_tree(self, verts, tris, pos, q, params: Params, theta=0.8, order=3,
+                      leaf_size=100):
+        """pb_solve with the treecode matvec; returns (info, phi, dphi)."""
+        s, k1 = self._surface(verts, tris)
+        c, k2 = self._charges(pos, q)
+        phi = np.empty(s.n_tri)
+        dphi = np.empty(s.n_tri)
+        info = _Info()
+        p = params.c()
+        self._check(self._L.pb_solve_tree(self._h, ctypes.byref(s), ctypes.byref(c),
+                                          ctypes.byref(p), float(theta), int(order),
+                                          int(leaf_size), _vp(phi.ctypes.data),
+                                          _vp(dphi.ctypes.data), ctypes.byref(info)))
         return Info.of(info), phi, dphi
 
     def pb_forces(self, verts, tris, pos, q, params: Params):

@@ -107,3 +107,45 @@ def test_tree_rejects_bad_parameters(pb, star8):
         with pytest.raises(m.PbError) as e:
             ctx.pb_matvec_tree(w.verts, w.tris, x, m.Params(), **args)
         assert e.value.status == m.PB_ERR_ARG
+
+
+def test_tree_solve_theta_zero_is_the_direct_solve(pb, star8):
+    m, ctx = pb
+    w = synth.star_protein(freq=8, r0=8.0, n_charges=20, seed=7)
+    P = m.Params(tol=1e-10)
+    i_d, _p, _d = ctx.pb_solve(w.verts, w.tris, w.pos, w.q, P)
+    i_t, _p, _d = ctx.pb_solve_tree(w.verts, w.tris, w.pos, w.q, P, theta=0.0, order=2,
+                                    leaf_size=20)
+    assert i_t.status == m.PB_OK
+    assert abs(i_t.e_solv - i_d.e_solv) <= 1e-9 * abs(i_d.e_solv)
+
+
+def test_tree_solve_matches_oracle_treecode_solve(pb):
+    """Both sides solve the same treecode operator (theta 0.5, p 3, N0 20) to
+    tol 1e-10: the energies agree far below the treecode's own error."""
+    m, ctx = pb
+    w = synth.star_protein(freq=8, r0=8.0, n_charges=20, seed=7)
+    info, _p, _d = ctx.pb_solve_tree(w.verts, w.tris, w.pos, w.q, m.Params(tol=1e-10),
+                                     theta=0.5, order=3, leaf_size=20)
+    e_ref, _xi, _inf = tc.solve(w.verts, w.tris, w.pos, w.q, theta=0.5, p=3, n0=20, tol=1e-10)
+    _say(f"tree solve E = {info.e_solv:.12f}, oracle {e_ref:.12f}")
+    assert info.status == m.PB_OK
+    assert abs(info.e_solv - e_ref) <= 1e-8 * abs(e_ref)
+
+
+def test_tree_solve_with_preconditioner_and_bad_precision(pb, star12):
+    m, ctx = pb
+    w = star12
+    i_d, _p, _d = ctx.pb_solve(w.verts, w.tris, w.pos, w.q, m.Params(tol=1e-8, precond_leaf=16))
+    i_t, _p, _d = ctx.pb_solve_tree(w.verts, w.tris, w.pos, w.q,
+                                    m.Params(tol=1e-8, precond_leaf=16), theta=0.5, order=4,
+                                    leaf_size=50)
+    _say(f"tree solve (theta 0.5, p 4) vs direct: {abs(i_t.e_solv - i_d.e_solv) / abs(i_d.e_solv):.2e}")
+    assert i_t.status == m.PB_OK
+    assert abs(i_t.e_solv - i_d.e_solv) <= 1e-2 * abs(i_d.e_solv)
+    with pytest.raises(m.PbError) as e:
+        ctx.pb_solve_tree(w.verts, w.tris, w.pos, w.q, m.Params(precision=m.PB_FP32_IR))
+    assert e.value.status == m.PB_ERR_ARG
+    # the context's ordinary solves are unaffected afterwards
+    i_d2, _p, _d = ctx.pb_solve(w.verts, w.tris, w.pos, w.q, m.Params(tol=1e-8, precond_leaf=16))
+    assert i_d2.e_solv == i_d.e_solv
