@@ -50,6 +50,14 @@ def fp32_kernel_name(kind: int) -> str:
     return "k_pairs_f32_sym" if kind == PAIRWISE else "k_pairs_f32_fwd"
 
 
+def fp64_kernel_name(kind: int) -> str:
+    return "k_pairs_f64_sym" if kind == PAIRWISE else "k_pairs<double>"
+
+
+def sweep_label(kind: int) -> str:
+    return "pairwise" if kind == PAIRWISE else f"per-target, {kind} targets per thread"
+
+
 def kernel_digest(kind: int) -> str:
     """SHA-256 of the FP32 forward sweep's source: the shared device header
     plus the text of the sweep kernel that `kind` selects."""
@@ -72,7 +80,7 @@ def measured_traffic(n_tri, sweep):
     except (KeyError, OSError, ValueError):
         return None
     if (rec.get("kernel_digest") != kernel_digest(sweep[0]) or rec.get("n_tri") != n_tri
-            or [rec.get("targets_per_thread"), rec.get("target_waves")] != list(sweep)):
+            or [rec.get("sweep_kind"), rec.get("target_waves")] != list(sweep)):
         return None
     return float(rec["bytes_per_launch"])
 
@@ -379,8 +387,10 @@ def main():
         kid = pbs.PB_KERNEL_PAIRS_FP32 if prec == PB_FP32_IR else pbs.PB_KERNEL_PAIRS_FP64
         n_l, ms_l, pr_l = ctx.profile_read(kid)
         print(json.dumps({"mode": "matvec", "precision": args.precision, "n_tri": N,
-                          "kernel": fp32_kernel_name(tuned[0]),
-                          "kernel_digest": kernel_digest(tuned[0]),
+                          "kernel": (fp32_kernel_name(tuned[0]) if prec == PB_FP32_IR
+                                     else fp64_kernel_name(ctx.get_fp64_sweep())),
+                          "kernel_digest": (kernel_digest(tuned[0]) if prec == PB_FP32_IR
+                                            else None),
                           "launches": n_l, "avg_ms": ms_l / n_l,
                           "pairs_per_launch": pr_l / n_l,
                           "tflops_algorithmic": FLOP_PER_PAIR * pr_l / (ms_l * 1e-3) / 1e12,
@@ -490,7 +500,7 @@ def main():
             "tol": params.tol,
             "inner_tol": params.inner_tol if prec == PB_FP32_IR else None,
             "gmres_restart": 10,
-            "fp32_sweep": {"targets_per_thread": tuned[0], "target_waves": tuned[1]},
+            "fp32_sweep": {"kind": sweep_label(tuned[0]), "target_waves": tuned[1]},
         },
         "time_to_solution_s": ms_step / 1e3,
         "e_solv": infos[-1].e_solv,
@@ -504,7 +514,7 @@ def main():
         "roofline": {
             "bound": "alu",
             "kernel": (fp32_kernel_name(tuned[0]) if prec == PB_FP32_IR
-                       else "k_pairs<double,false>"),
+                       else fp64_kernel_name(ctx.get_fp64_sweep())),
             "achieved": achieved / 1e12,
             "peak": peak / 1e12,
             "unit": "TFLOP/s",

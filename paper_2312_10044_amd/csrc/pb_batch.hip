@@ -237,26 +237,24 @@ __global__ __launch_bounds__(TPB) void kb_pack_sym(const double *__restrict__ g,
     if (j < d.n) {
         const double a = g[6 * gtot + gi];
         const double ap = a * xv[d.npad + j] / sigma;
-        const double f = -3.0 * a * xv[j];
+        const double nu = 3.0 * a * xv[j];
         const double nx = g[3 * gtot + gi], ny = g[4 * gtot + gi], nz = g[5 * gtot + gi];
         s.x = float((g[gi] - d.cx) * sigma);
         s.y = float((g[gtot + gi] - d.cy) * sigma);
         s.z = float((g[2 * gtot + gi] - d.cz) * sigma);
-        s.w = float((1.0 - 1.0 / eps) * ap);
-        s.mx = float(f * nx);
-        s.my = float(f * ny);
-        s.mz = float(f * nz);
-        s.pad = float(-ap / eps);
+        s.w1 = float((1.0 - 1.0 / eps) * ap);
+        s.w2n = float(-ap / eps);
         s.nx = float(-nx);
         s.ny = float(-ny);
         s.nz = float(-nz);
+        s.nu = float(nu);
     } else {
         s.x = float((FAR_SRC + 8.0 * double(j - d.n) - d.cx) * sigma);
         s.y = s.z = 0.f;
-        s.w = s.mx = s.my = s.mz = s.pad = 0.f;
+        s.w1 = s.w2n = s.nu = 0.f;
         s.nx = s.ny = s.nz = 0.f;
     }
-    s.res = 0.f;
+    s.res0 = s.res1 = s.res2 = 0.f;
     src[gi] = s;
 }
 
@@ -265,13 +263,13 @@ __global__ __launch_bounds__(TPB) void kb_pack_sym64(const double *__restrict__ 
                                                      const SysDesc *__restrict__ sd,
                                                      const int32_t *__restrict__ blk2sys,
                                                      const double *__restrict__ x,
-                                                     Src10d *__restrict__ src, int mode)
+                                                     Src8d *__restrict__ src, int mode)
 {
     const int64_t gi = (int64_t)blockIdx.x * TPB + threadIdx.x;
     const SysDesc d = sd[blk2sys[blockIdx.x]];
     const int64_t j = gi - d.goff;
     const double *xv = x + 2 * d.goff;
-    Src10d s;
+    Src8d s;
     if (j < d.n) {
         const double a = g[6 * gtot + gi];
         const double w = mode ? xv[j] : a * xv[d.npad + j];
@@ -283,13 +281,11 @@ __global__ __launch_bounds__(TPB) void kb_pack_sym64(const double *__restrict__ 
         s.nx = g[3 * gtot + gi];
         s.ny = g[4 * gtot + gi];
         s.nz = g[5 * gtot + gi];
-        s.mx = f * s.nx;
-        s.my = f * s.ny;
-        s.mz = f * s.nz;
+        s.f = f;
     } else {
         s.x = FAR_SRC + 8.0 * double(j - d.n);
         s.y = s.z = 0.0;
-        s.w = s.mx = s.my = s.mz = s.nx = s.ny = s.nz = 0.0;
+        s.w = s.f = s.nx = s.ny = s.nz = 0.0;
     }
     src[gi] = s;
 }
@@ -319,7 +315,7 @@ __global__ __launch_bounds__(TPB) void kb_pairs_f32_sym(const Src12 *__restrict_
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(TPB) void kb_pairs_f64_sym(const Src10d *__restrict__ src,
+__global__ __launch_bounds__(TPB) void kb_pairs_f64_sym(const Src8d *__restrict__ src,
                                                         const SysDesc *__restrict__ sd,
                                                         const SItem *__restrict__ items,
                                                         int64_t n_items,
@@ -328,7 +324,7 @@ __global__ __launch_bounds__(TPB) void kb_pairs_f64_sym(const Src10d *__restrict
                                                         double *__restrict__ rowpart,
                                                         double *__restrict__ colpart)
 {
-    __shared__ Src10d sh[TILE];
+    __shared__ Src8d sh[TILE];
     __shared__ double colw[TPB / 64][2 * TILE + 64];
     PairParams pp;
     pp.eps = eps;
@@ -970,14 +966,14 @@ void enqueue_matvec(pb_ctx *c, const BatchPlan &P, BatchDev &D, bool f32, int tr
     }
     if (!f32 && c->f64_kind == PB_SWEEP_PAIRWISE) {
         hipLaunchKernelGGL(kb_pack_sym64, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
-                           D.blk2sys, x, reinterpret_cast<Src10d *>(D.src), trans ? 1 : 0);
+                           D.blk2sys, x, reinterpret_cast<Src8d *>(D.src), trans ? 1 : 0);
         if (trans)
             hipLaunchKernelGGL(kb_pairs_f64_sym<true>, dim3(sgrid), dim3(TPB), 0, s,
-                               reinterpret_cast<const Src10d *>(D.src), D.sd, D.sitems, nsi, mask,
+                               reinterpret_cast<const Src8d *>(D.src), D.sd, D.sitems, nsi, mask,
                                eps, kap, D.srow, static_cast<double *>(D.scol));
         else
             hipLaunchKernelGGL(kb_pairs_f64_sym<false>, dim3(sgrid), dim3(TPB), 0, s,
-                               reinterpret_cast<const Src10d *>(D.src), D.sd, D.sitems, nsi, mask,
+                               reinterpret_cast<const Src8d *>(D.src), D.sd, D.sitems, nsi, mask,
                                eps, kap, D.srow, static_cast<double *>(D.scol));
         hipLaunchKernelGGL(kb_sym_finish<double>, dim3(gb), dim3(TPB), 0, s, D.srow,
                            static_cast<const double *>(D.scol), D.rs, D.g, P.gtot, D.sd,

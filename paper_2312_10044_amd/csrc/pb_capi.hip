@@ -167,7 +167,7 @@ int apply_pairwise64(pb_ctx *c, const pb_params *p, int transpose, const double 
     TRY(ensure_sym_plan(c));
     const SymPlan &pl = c->sym_plan;
     const int64_t T = pl.n_tiles;
-    TRY(ensure(c, c->sym_src64, sizeof(double) * 10 * g.npad));
+    TRY(ensure(c, c->sym_src64, sizeof(double) * 8 * g.npad));
     TRY(ensure(c, c->sym_rowpart, sizeof(double) * 2 * TILE * (size_t)pl.n_items));
     TRY(ensure(c, c->sym_colpart,
                sizeof(double) * 2 * TILE * (size_t)std::max<int64_t>(T * (T - 1) / 2, 1)));

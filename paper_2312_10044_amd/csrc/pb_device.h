@@ -184,19 +184,24 @@ __device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&t
 // so one evaluation yields both the contribution of source j to row i and of
 // source i to row j.  Every collocation point is a target and a source; the
 // packed entry carries both roles (reduced form, lengths in units of 1/kappa
-// when kappa > 0): position, w1 = (1 - 1/eps) a psi / sigma, m = -3 a phi n,
-// w2n = -a psi / (eps sigma) and sn = -n.
+// when kappa > 0): position, w1 = (1 - 1/eps) a psi / sigma, w2n = -a psi /
+// (eps sigma), sn = -n and nu = 3 a phi.  The moment m = -3 a phi n of the
+// reduced form is parallel to the normal, so every product with m is a
+// product with the normal times nu: m_j.d = nu_j (sn_j.d), n_i.m_j =
+// nu_j (n_i.sn_j), and the three dot products of a pair (n_i.d, sn_j.d,
+// n_i.sn_j) serve both directions.
 struct alignas(16) Src12 {
-    float x, y, z, w, mx, my, mz, pad, nx, ny, nz, res;
+    float x, y, z, w1;
+    float w2n, nx, ny, nz;
+    float nu, res0, res1, res2;
 };
 
-// The thread's own point: target data (position, n_i) and its source weights
-// (w1, w2n and m = -3 a phi n of point i, as in the stream).
+// The thread's own point: position, n_i (the stream holds -n) and its
+// source weights w1, w2n and nu.
 struct OwnF32 {
     float x, y, z;
     float nx, ny, nz;
-    float w1, w2n;
-    float mx, my, mz;
+    float w1, w2n, nu;
 };
 
 __device__ __forceinline__ OwnF32 own_point(const Src12 &e)
@@ -208,11 +213,9 @@ __device__ __forceinline__ OwnF32 own_point(const Src12 &e)
     o.nx = -e.nx;
     o.ny = -e.ny;
     o.nz = -e.nz;
-    o.w1 = e.w;
-    o.w2n = e.pad;
-    o.mx = e.mx;
-    o.my = e.my;
-    o.mz = e.mz;
+    o.w1 = e.w1;
+    o.w2n = e.w2n;
+    o.nu = e.nu;
     return o;
 }
 
@@ -266,7 +269,11 @@ __device__ __forceinline__ T rs_finish(const T (&a)[4], int lane)
 }
 
 // One pair, forward direction only (source s on the own point o); with DIAG the
-// pair is dropped when `skip` (ir = 0 zeroes every term).
+// pair is dropped when `skip` (ir = 0 zeroes every term).  With d = x_j - x_i,
+// A = n_i.d, B = sn_j.d, C = n_i.sn_j, t3n = -tm1/3 and
+// b = (tm1 + 1 - 1/eps)/3 = c13 - t3n:
+//   row 1 / eps += (e-1) w2n_j / r + b nu_j B u
+//   row 2       += u [A (nu_j B h3 + tm1 w2n_j + w1_j) + t3n C nu_j]
 template <bool SCALED, bool DIAG>
 __device__ __forceinline__ void pair_fwd(const Src12 &s, const OwnF32 &o, const CoefF32 &cf,
                                          bool skip, float &P, float &Q)
@@ -282,24 +289,26 @@ __device__ __forceinline__ void pair_fwd(const Src12 &s, const OwnF32 &o, const 
     const float kr = SCALED ? r : cf.kappa * r;
     const float e = __builtin_amdgcn_exp2f(cf.kexp * r);
     const float em1 = e - 1.f;
-    P = fmaf(em1, ir * s.pad, P);
+    P = fmaf(em1 * ir, s.w2n, P);
     const float tm1 = fmaf(kr, e, em1);
-    const float t3 = tm1 * 0.333333343f;
-    const float cxd = o.nx * dx + o.ny * dy + o.nz * dz;
-    const float md3 = s.mx * dx + s.my * dy + s.mz * dz;
-    const float nsm = o.nx * s.mx + o.ny * s.my + o.nz * s.mz;   // -3 (-n_i/3).m
-    const float b = t3 + cf.c13;
-    P = fmaf(b * md3, u, P);
+    const float t3n = tm1 * -0.333333343f;
+    const float b = cf.c13 - t3n;
+    const float A = o.nx * dx + o.ny * dy + o.nz * dz;
+    const float B = s.nx * dx + s.ny * dy + s.nz * dz;
+    const float C = o.nx * s.nx + o.ny * s.ny + o.nz * s.nz;
+    const float md = s.nu * B;
+    P = fmaf(b * u, md, P);
     const float h3 = fmaf(tm1, ir2, cf.k23 * e);
-    const float cqw = fmaf(tm1, s.pad, s.w);
-    const float inner = fmaf(md3, h3, cqw);
-    Q = fmaf(u, fmaf(cxd, inner, -(t3 * nsm)), Q);
+    const float inner = fmaf(md, h3, fmaf(tm1, s.w2n, s.w1));
+    Q = fmaf(u, fmaf(A, inner, (t3n * C) * s.nu), Q);
 }
 
 // One pair, both directions: P, Q accumulate row i; cp, cq receive the
 // contribution of point i to row j.  The reverse direction is the forward
-// formula with i and j exchanged and d negated: its md3 is -m_i.d, its
-// c_x is sn_j.d, and its n.m term n_j.m_i equals -sn_j.m_i.
+// formula with i and j exchanged and d negated; in the notation of pair_fwd:
+//   row j, 1 / eps: (e-1) w2n_i / r + b nu_i A u
+//   row j, 2:       u [B (nu_i A h3 + tm1 w2n_i + w1_i) + t3n C nu_i]
+// so the pair costs 44 VALU operations and two transcendentals.
 template <bool SCALED>
 __device__ __forceinline__ void pair_both(const Src12 &s, const OwnF32 &o, const CoefF32 &cf,
                                           float &P, float &Q, float &cp, float &cq)
@@ -313,29 +322,27 @@ __device__ __forceinline__ void pair_both(const Src12 &s, const OwnF32 &o, const
     const float kr = SCALED ? r : cf.kappa * r;
     const float e = __builtin_amdgcn_exp2f(cf.kexp * r);
     const float em1 = e - 1.f;
-    P = fmaf(em1, ir * s.pad, P);
-    float p2 = em1 * (ir * o.w2n);
+    const float em1ir = em1 * ir;
+    P = fmaf(em1ir, s.w2n, P);
+    const float p2 = em1ir * o.w2n;
     const float tm1 = fmaf(kr, e, em1);
-    const float t3 = tm1 * 0.333333343f;
-    const float b = t3 + cf.c13;
+    const float t3n = tm1 * -0.333333343f;
+    const float bu = (cf.c13 - t3n) * u;
     const float h3 = fmaf(tm1, ir2, cf.k23 * e);
+    const float A = o.nx * dx + o.ny * dy + o.nz * dz;
+    const float B = s.nx * dx + s.ny * dy + s.nz * dz;
+    const float C = o.nx * s.nx + o.ny * s.ny + o.nz * s.nz;
+    const float tc = t3n * C;
     // source j on row i
-    const float cxd = o.nx * dx + o.ny * dy + o.nz * dz;
-    const float md3 = s.mx * dx + s.my * dy + s.mz * dz;
-    const float nsm = o.nx * s.mx + o.ny * s.my + o.nz * s.mz;
-    P = fmaf(b * md3, u, P);
-    const float cqw = fmaf(tm1, s.pad, s.w);
-    const float inner = fmaf(md3, h3, cqw);
-    Q = fmaf(u, fmaf(cxd, inner, -(t3 * nsm)), Q);
+    const float md = s.nu * B;
+    P = fmaf(bu, md, P);
+    const float inner = fmaf(md, h3, fmaf(tm1, s.w2n, s.w1));
+    Q = fmaf(u, fmaf(A, inner, tc * s.nu), Q);
     // source i on row j
-    const float pm = o.mx * dx + o.my * dy + o.mz * dz;      // -md3 of the reverse pair
-    const float cxdr = s.nx * dx + s.ny * dy + s.nz * dz;
-    const float spm = s.nx * o.mx + s.ny * o.my + s.nz * o.mz;
-    p2 = fmaf(-(b * pm), u, p2);
-    const float cqwr = fmaf(tm1, o.w2n, o.w1);
-    const float innerr = fmaf(-pm, h3, cqwr);
-    cp = p2;
-    cq = u * fmaf(cxdr, innerr, t3 * spm);
+    const float pm = o.nu * A;
+    cp = fmaf(bu, pm, p2);
+    const float innerr = fmaf(pm, h3, fmaf(tm1, o.w2n, o.w1));
+    cq = u * fmaf(B, innerr, tc * o.nu);
 }
 
 // Diagonal tile (sources = the block's own targets): forward direction, j = i
@@ -385,30 +392,33 @@ __device__ __forceinline__ void sweep_pairwise(const Src12 *sh, const OwnF32 &o,
 // ---- pairwise FP64 sweep ------------------------------------------------------
 //
 // The generic (FP64) pair algebra, with d = x_i - x_j, evaluated once per
-// unordered pair.  Forward stream: w = a psi, m = a phi n; transpose stream:
-// w = l1, m = l2 n; both also carry the point's normal n.  For source j on
-// row i (cP = g2, cQ = -g3 forward; cP = -g3, cQ = g2 transposed):
-//   P_i += -(e-1) w_j / r + cP (m_j.d) / r^3
-//   Q_i += [-(n_i.d) ((m_j.d) h + cQ w_j) + tm1 (n_i.m_j)] / r^3
+// unordered pair.  Forward stream: w = a psi, f = a phi; transpose stream:
+// w = l1, f = l2; the moment is m = f n.  With A = n_i.d, B = n_j.d and
+// C = n_i.n_j, every product with a moment is a product with a normal times
+// f (m_j.d = f_j B, n_i.m_j = f_j C, m_i.d = f_i A, n_j.m_i = f_i C), so the
+// three dot products serve both directions.  For source j on row i (cP = g2,
+// cQ = -g3 forward; cP = -g3, cQ = g2 transposed):
+//   P_i += -(e-1) w_j / r + cP f_j B / r^3
+//   Q_i += [-A (f_j B h + cQ w_j) + tm1 f_j C] / r^3
 // and for source i on row j the same with i and j exchanged, d -> -d:
-//   P_j += -(e-1) w_i / r - cP (m_i.d) / r^3
-//   Q_j += [(n_j.d) (-(m_i.d) h + cQ w_i) + tm1 (n_j.m_i)] / r^3.
+//   P_j += -(e-1) w_i / r - cP f_i A / r^3
+//   Q_j += [B (-f_i A h + cQ w_i) + tm1 f_i C] / r^3.
 // Transposed, P and Q are rows 2 and 1 of the output (swapped by the caller).
-struct alignas(16) Src10d {
-    double x, y, z, w, mx, my, mz, nx, ny, nz;
+struct alignas(64) Src8d {
+    double x, y, z, w, nx, ny, nz, f;
 };
 
 struct OwnF64 {
-    double x, y, z, nx, ny, nz, w, mx, my, mz;
+    double x, y, z, nx, ny, nz, w, f;
 };
 
-__device__ __forceinline__ OwnF64 own_point64(const Src10d &e)
+__device__ __forceinline__ OwnF64 own_point64(const Src8d &e)
 {
-    return OwnF64{e.x, e.y, e.z, e.nx, e.ny, e.nz, e.w, e.mx, e.my, e.mz};
+    return OwnF64{e.x, e.y, e.z, e.nx, e.ny, e.nz, e.w, e.f};
 }
 
 template <bool TRANS, bool BOTH, bool DIAG>
-__device__ __forceinline__ void pair64(const Src10d &s, const OwnF64 &o, const Coef<double> &cf,
+__device__ __forceinline__ void pair64(const Src8d &s, const OwnF64 &o, const Coef<double> &cf,
                                        bool skip, double &P, double &Q, double &cp, double &cq)
 {
     const double dx = o.x - s.x, dy = o.y - s.y, dz = o.z - s.z;
@@ -425,26 +435,26 @@ __device__ __forceinline__ void pair64(const Src10d &s, const OwnF64 &o, const C
     const double g2 = fma(cf.eps, tm1, cf.epsm1);
     const double g3 = fma(cf.ieps, tm1, cf.iepsm1);
     const double h = fma(tm1, 3.0 * ir2, cf.k2 * e);
-    const double cP = TRANS ? -g3 : g2;
+    const double cPu = (TRANS ? -g3 : g2) * u;
     const double cQ = TRANS ? g2 : -g3;
     const double a = -em1 * ir;
-    const double md = s.mx * dx + s.my * dy + s.mz * dz;
-    const double cxd = o.nx * dx + o.ny * dy + o.nz * dz;
-    const double nm = o.nx * s.mx + o.ny * s.my + o.nz * s.mz;
+    const double A = o.nx * dx + o.ny * dy + o.nz * dz;
+    const double B = s.nx * dx + s.ny * dy + s.nz * dz;
+    const double C = o.nx * s.nx + o.ny * s.ny + o.nz * s.nz;
+    const double tc = tm1 * C;
+    const double md = s.f * B;
     P = fma(a, s.w, P);
-    P = fma(cP * md, u, P);
-    Q = fma(u, fma(-cxd, fma(md, h, cQ * s.w), tm1 * nm), Q);
+    P = fma(cPu, md, P);
+    Q = fma(u, fma(-A, fma(md, h, cQ * s.w), tc * s.f), Q);
     if (BOTH) {
-        const double pm = o.mx * dx + o.my * dy + o.mz * dz;
-        const double cyd = s.nx * dx + s.ny * dy + s.nz * dz;
-        const double nmr = s.nx * o.mx + s.ny * o.my + s.nz * o.mz;
-        cp = fma(-cP * pm, u, a * o.w);
-        cq = u * fma(cyd, fma(-pm, h, cQ * o.w), tm1 * nmr);
+        const double pm = o.f * A;
+        cp = fma(-cPu, pm, a * o.w);
+        cq = u * fma(B, fma(-pm, h, cQ * o.w), tc * o.f);
     }
 }
 
 template <bool TRANS>
-__device__ __forceinline__ void sweep_diag64(const Src10d *sh, const OwnF64 &o,
+__device__ __forceinline__ void sweep_diag64(const Src8d *sh, const OwnF64 &o,
                                              const Coef<double> &cf, double &P, double &Q)
 {
     double dummy0 = 0.0, dummy1 = 0.0;
@@ -456,7 +466,7 @@ __device__ __forceinline__ void sweep_diag64(const Src10d *sh, const OwnF64 &o,
 // Off-diagonal tile, both directions; column sums as in sweep_pairwise,
 // stored in colw[comp * TILE + j] (2 * TILE + 64 doubles).
 template <bool TRANS>
-__device__ __forceinline__ void sweep_pairwise64(const Src10d *sh, const OwnF64 &o,
+__device__ __forceinline__ void sweep_pairwise64(const Src8d *sh, const OwnF64 &o,
                                                  const Coef<double> &cf, double &P, double &Q,
                                                  double *colw, int lane)
 {
@@ -522,10 +532,10 @@ __device__ __forceinline__ void sym_item_f32(const Src12 *__restrict__ src, int 
 }
 
 template <bool TRANS>
-__device__ __forceinline__ void sym_item_f64(const Src10d *__restrict__ src, int I, int J0,
+__device__ __forceinline__ void sym_item_f64(const Src8d *__restrict__ src, int I, int J0,
                                              int J1, int T, const Coef<double> &cf,
                                              double *__restrict__ rp,
-                                             double *__restrict__ cp_base, Src10d *sh,
+                                             double *__restrict__ cp_base, Src8d *sh,
                                              double (*colw)[2 * TILE + 64])
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;

@@ -267,27 +267,25 @@ __global__ __launch_bounds__(TPB) void k_pack_sym(const double *__restrict__ g, 
     if (j < n) {
         const double a = g[6 * npad + j];
         const double ap = a * x[n + j] / sigma;
-        const double f = -3.0 * a * x[j];
+        const double nu = 3.0 * a * x[j];
         const double nx = g[3 * npad + j], ny = g[4 * npad + j], nz = g[5 * npad + j];
         s.x = float((g[j] - cx) * sigma);
         s.y = float((g[npad + j] - cy) * sigma);
         s.z = float((g[2 * npad + j] - cz) * sigma);
-        s.w = float((1.0 - 1.0 / eps) * ap);
-        s.mx = float(f * nx);
-        s.my = float(f * ny);
-        s.mz = float(f * nz);
-        s.pad = float(-ap / eps);
+        s.w1 = float((1.0 - 1.0 / eps) * ap);
+        s.w2n = float(-ap / eps);
         s.nx = float(-nx);
         s.ny = float(-ny);
         s.nz = float(-nz);
+        s.nu = float(nu);
     } else {
         // padding: weightless points far away, 8 apart so no two coincide
         s.x = float((FAR_SRC + 8.0 * double(j - n) - cx) * sigma);
         s.y = s.z = 0.f;
-        s.w = s.mx = s.my = s.mz = s.pad = 0.f;
+        s.w1 = s.w2n = s.nu = 0.f;
         s.nx = s.ny = s.nz = 0.f;
     }
-    s.res = 0.f;
+    s.res0 = s.res1 = s.res2 = 0.f;
     src[j] = s;
 }
 
@@ -344,15 +342,15 @@ __global__ __launch_bounds__(TPB) void k_sym_finish(const double *__restrict__ r
 
 // ---- pairwise FP64 sweep ----------------------------------------------------
 
-// mode 0: w = a psi, m = a phi n; mode 1 (transpose): w = l1, m = l2 n.
+// mode 0: w = a psi, f = a phi; mode 1 (transpose): w = l1, f = l2.
 __global__ __launch_bounds__(TPB) void k_pack_sym64(const double *__restrict__ g, int64_t n,
                                                     int64_t npad, const double *__restrict__ x,
-                                                    Src10d *__restrict__ src, int mode)
+                                                    Src8d *__restrict__ src, int mode)
 {
     const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (j >= npad)
         return;
-    Src10d s;
+    Src8d s;
     if (j < n) {
         const double a = g[6 * npad + j];
         const double w = mode ? x[j] : a * x[n + j];
@@ -364,26 +362,24 @@ __global__ __launch_bounds__(TPB) void k_pack_sym64(const double *__restrict__ g
         s.nx = g[3 * npad + j];
         s.ny = g[4 * npad + j];
         s.nz = g[5 * npad + j];
-        s.mx = f * s.nx;
-        s.my = f * s.ny;
-        s.mz = f * s.nz;
+        s.f = f;
     } else {
         // padding: weightless points far away, 8 apart
         s.x = FAR_SRC + 8.0 * double(j - n);
         s.y = s.z = 0.0;
-        s.w = s.mx = s.my = s.mz = s.nx = s.ny = s.nz = 0.0;
+        s.w = s.f = s.nx = s.ny = s.nz = 0.0;
     }
     src[j] = s;
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(TPB) void k_pairs_f64_sym(const Src10d *__restrict__ src,
+__global__ __launch_bounds__(TPB) void k_pairs_f64_sym(const Src8d *__restrict__ src,
                                                        const int4 *__restrict__ items, int T,
                                                        PairParams pp,
                                                        double *__restrict__ rowpart,
                                                        double *__restrict__ colpart)
 {
-    __shared__ Src10d sh[TILE];
+    __shared__ Src8d sh[TILE];
     __shared__ double colw[TPB / 64][2 * TILE + 64];
     const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
     sym_item_f64<TRANS>(src, it.x, it.y, it.z, T, Coef<double>(pp),
@@ -1097,14 +1093,14 @@ void launch_sym_finish(hipStream_t s, const Geo &geo, const double *rowpart,
 void launch_pack_sym64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode)
 {
     hipLaunchKernelGGL(k_pack_sym64, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
-                       geo.npad, x, reinterpret_cast<Src10d *>(src), mode);
+                       geo.npad, x, reinterpret_cast<Src8d *>(src), mode);
 }
 
 void launch_pairs_f64_sym(hipStream_t s, const double *src, const int32_t *items, int n_items,
                           int n_tiles, const PairParams &pp, int transpose, double *rowpart,
                           double *colpart)
 {
-    const auto *p = reinterpret_cast<const Src10d *>(src);
+    const auto *p = reinterpret_cast<const Src8d *>(src);
     const auto *it = reinterpret_cast<const int4 *>(items);
     if (transpose)
         hipLaunchKernelGGL(k_pairs_f64_sym<true>, dim3(n_items), dim3(TPB), 0, s, p, it, n_tiles,
