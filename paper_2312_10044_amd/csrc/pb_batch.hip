@@ -300,8 +300,8 @@ __global__ __launch_bounds__(TPB) void kb_pairs_f32_sym(const Src12 *__restrict_
                                                         double *__restrict__ rowpart,
                                                         float *__restrict__ colpart)
 {
-    __shared__ Src12 sh[TILE];
-    __shared__ float colw[TPB / 64][2 * TILE + 64];
+    __shared__ SrcTileF32 sh;
+    __shared__ float colw[TPB / 64][2 * TILE];
     const CoefF32 cf = coef_f32(eps, kappa, SCALED);
     for (int64_t k = blockIdx.x; k < n_items; k += gridDim.x) {
         const SItem w = items[k];
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(TPB) void kb_pairs_f32_sym(const Src12 *__restrict_
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(TPB) void kb_pairs_f64_sym(const Src8d *__restrict__ src,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(5))) void kb_pairs_f64_sym(const Src8d *__restrict__ src,
                                                         const SysDesc *__restrict__ sd,
                                                         const SItem *__restrict__ items,
                                                         int64_t n_items,
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(TPB) void kb_pairs_f64_sym(const Src8d *__restrict_
                                                         double *__restrict__ colpart)
 {
     __shared__ Src8d sh[TILE];
-    __shared__ double colw[TPB / 64][2 * TILE + 64];
+    __shared__ double colw[TPB / 64][2 * TILE];
     PairParams pp;
     pp.eps = eps;
     pp.kappa = kappa;

@@ -219,6 +219,36 @@ __device__ __forceinline__ OwnF32 own_point(const Src12 &e)
     return o;
 }
 
+// A source tile in LDS, 36 bytes per entry in three aligned arrays (the
+// entry's 9 used values), read back as two 16-byte and one 4-byte broadcast.
+struct SrcTileF32 {
+    float4 a[TILE];   // x, y, z, w1
+    float4 b[TILE];   // w2n, sn
+    float c[TILE];    // nu
+    __device__ __forceinline__ void put(int t, const Src12 &e)
+    {
+        a[t] = make_float4(e.x, e.y, e.z, e.w1);
+        b[t] = make_float4(e.w2n, e.nx, e.ny, e.nz);
+        c[t] = e.nu;
+    }
+    __device__ __forceinline__ Src12 get(int j) const
+    {
+        const float4 u = a[j], v = b[j];
+        Src12 e;
+        e.x = u.x;
+        e.y = u.y;
+        e.z = u.z;
+        e.w1 = u.w;
+        e.w2n = v.x;
+        e.nx = v.y;
+        e.ny = v.z;
+        e.nz = v.w;
+        e.nu = c[j];
+        e.res0 = e.res1 = e.res2 = 0.f;
+        return e;
+    }
+};
+
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v)
 {
@@ -348,21 +378,21 @@ __device__ __forceinline__ void pair_both(const Src12 &s, const OwnF32 &o, const
 // Diagonal tile (sources = the block's own targets): forward direction, j = i
 // dropped.
 template <bool SCALED>
-__device__ __forceinline__ void sweep_diag(const Src12 *sh, const OwnF32 &o, const CoefF32 &cf,
-                                           float &P, float &Q)
+__device__ __forceinline__ void sweep_diag(const SrcTileF32 &sh, const OwnF32 &o,
+                                           const CoefF32 &cf, float &P, float &Q)
 {
 #pragma unroll 2
     for (int jj = 0; jj < TILE; ++jj)
-        pair_fwd<SCALED, true>(sh[jj], o, cf, jj == (int)threadIdx.x, P, Q);
+        pair_fwd<SCALED, true>(sh.get(jj), o, cf, jj == (int)threadIdx.x, P, Q);
 }
 
 // Off-diagonal tile: both directions.  The contributions to the tile's source
 // rows are summed over the wave's 64 targets in groups of 4 sources (8 values
-// per lane: reduce-scatter within rows, then across the 4 rows) and stored by
-// the even lanes 0-14 in colw[comp * TILE + j] (comp 0: row 1, 1: row 2);
-// colw holds 2 * TILE + 64 floats.
+// per lane: reduce-scatter within rows, then across the 4 rows) and stored
+// in colw[comp * TILE + j] (comp 0: row 1, 1: row 2); colw holds 2 * TILE
+// floats.
 template <bool SCALED>
-__device__ __forceinline__ void sweep_pairwise(const Src12 *sh, const OwnF32 &o,
+__device__ __forceinline__ void sweep_pairwise(const SrcTileF32 &sh, const OwnF32 &o,
                                                const CoefF32 &cf, float &P, float &Q,
                                                float *colw, int lane)
 {
@@ -371,23 +401,64 @@ __device__ __forceinline__ void sweep_pairwise(const Src12 *sh, const OwnF32 &o,
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             float p0, q0, p2, q2;
-            pair_both<SCALED>(sh[g + k], o, cf, P, Q, p0, q0);
+            pair_both<SCALED>(sh.get(g + k), o, cf, P, Q, p0, q0);
             __builtin_amdgcn_sched_barrier(0);
-            pair_both<SCALED>(sh[g + k + 2], o, cf, P, Q, p2, q2);
+            pair_both<SCALED>(sh.get(g + k + 2), o, cf, P, Q, p2, q2);
             rs_stage1(p0, q0, p2, q2, lane, a[2 * k], a[2 * k + 1]);
             __builtin_amdgcn_sched_barrier(0);
         }
         float t = rs_finish(a, lane);
         t += __shfl_xor(t, 16, 64);
         t += __shfl_xor(t, 32, 64);
-        // value index q: source g + q/2, row q%2.  Lanes that hold no new
-        // value write to a spare slot, which keeps the loop free of branches.
+        // value index q: source g + q/2, row q%2.  Every lane with the same q
+        // holds the same sum, bit for bit (each addition above adds the same
+        // two operands in both lanes of a pair), so all 64 lanes store it:
+        // eight lanes write one word with one value, and the loop stays free
+        // of branches.
         const int q = (lane >> 1) & 7;
-        const bool mine = lane < 16 && !(lane & 1);
-        colw[mine ? (q & 1) * TILE + g + (q >> 1) : 2 * TILE + lane] = t;
+        colw[(q & 1) * TILE + g + (q >> 1)] = t;
     }
 }
 
+
+// exp(-x) for 0 <= x <= 700, the range of kappa r on a pair: no overflow,
+// underflow or special value can occur, so the general function's range
+// checks are left out.  Cody-Waite reduction: e^-x = 2^-n e^g with
+// n = rint(x / ln 2) and g = n ln 2 - x, |g| <= ln 2 / 2, where ln 2 is split
+// into a 32-bit head (n times it is exact) and the rounded remainder.  e^g is
+// its Taylor series to degree 12, whose truncation error on that interval is
+// below 2.4e-16 relative.
+__device__ __forceinline__ double exp_neg_pair(double x)
+{
+    const double n = __builtin_rint(x * 1.4426950408889634);
+    const double g = fma(n, 1.9082149292705877e-10, fma(n, 0.6931471803691238, -x));
+    double p = 2.08767569878681e-09;          // 1/12!
+    p = fma(p, g, 2.505210838544172e-08);     // 1/11!
+    p = fma(p, g, 2.755731922398589e-07);
+    p = fma(p, g, 2.7557319223985893e-06);
+    p = fma(p, g, 2.48015873015873e-05);
+    p = fma(p, g, 0.0001984126984126984);
+    p = fma(p, g, 0.001388888888888889);
+    p = fma(p, g, 0.008333333333333333);
+    p = fma(p, g, 0.041666666666666664);
+    p = fma(p, g, 0.16666666666666666);
+    p = fma(p, g, 0.5);
+    p = fma(p, g, 1.0);
+    p = fma(p, g, 1.0);
+    return ldexp(p, -(int)n);
+}
+
+// 1/sqrt(x) for finite x > 0: the hardware estimate y refined by one
+// third-order Householder step, y (1 + e/2 + 3 e^2/8) with e = 1 - x y^2 (the
+// series of (1 - e)^(-1/2)), which takes the estimate's relative error eps to
+// about (5/16) eps^3.  x = 0 gives NaN; callers that can meet it replace the
+// result.
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
 
 // ---- pairwise FP64 sweep ------------------------------------------------------
 //
@@ -423,13 +494,13 @@ __device__ __forceinline__ void pair64(const Src8d &s, const OwnF64 &o, const Co
 {
     const double dx = o.x - s.x, dy = o.y - s.y, dz = o.z - s.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    double ir = rsqrt(r2);
+    double ir = rsqrt_pos(r2);
     if (DIAG)
         ir = skip ? 0.0 : ir;
     const double ir2 = ir * ir;
     const double u = ir2 * ir;
     const double kr = cf.kappa * (r2 * ir);
-    const double e = exp(-kr);
+    const double e = exp_neg_pair(kr);
     const double em1 = e - 1.0;
     const double tm1 = fma(kr, e, em1);
     const double g2 = fma(cf.eps, tm1, cf.epsm1);
@@ -464,7 +535,7 @@ __device__ __forceinline__ void sweep_diag64(const Src8d *sh, const OwnF64 &o,
 }
 
 // Off-diagonal tile, both directions; column sums as in sweep_pairwise,
-// stored in colw[comp * TILE + j] (2 * TILE + 64 doubles).
+// stored in colw[comp * TILE + j] (2 * TILE doubles).
 template <bool TRANS>
 __device__ __forceinline__ void sweep_pairwise64(const Src8d *sh, const OwnF64 &o,
                                                  const Coef<double> &cf, double &P, double &Q,
@@ -484,9 +555,8 @@ __device__ __forceinline__ void sweep_pairwise64(const Src8d *sh, const OwnF64 &
         double t = rs_finish(a, lane);
         t += __shfl_xor(t, 16, 64);
         t += __shfl_xor(t, 32, 64);
-        const int q = (lane >> 1) & 7;
-        const bool mine = lane < 16 && !(lane & 1);
-        colw[mine ? (q & 1) * TILE + g + (q >> 1) : 2 * TILE + lane] = t;
+        const int q = (lane >> 1) & 7;   // as in sweep_pairwise
+        colw[(q & 1) * TILE + g + (q >> 1)] = t;
     }
 }
 
@@ -502,15 +572,15 @@ __device__ __forceinline__ void sweep_pairwise64(const Src8d *sh, const OwnF64 &
 template <bool SCALED>
 __device__ __forceinline__ void sym_item_f32(const Src12 *__restrict__ src, int I, int J0, int J1,
                                              int T, const CoefF32 &cf, double *__restrict__ rp,
-                                             float *__restrict__ cp_base, Src12 *sh,
-                                             float (*colw)[2 * TILE + 64])
+                                             float *__restrict__ cp_base, SrcTileF32 &sh,
+                                             float (*colw)[2 * TILE])
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const OwnF32 o = own_point(src[(int64_t)I * TILE + threadIdx.x]);
     Acc<float> aP, aQ;
     for (int J = J0; J < J1; ++J) {
         __syncthreads();
-        sh[threadIdx.x] = src[(int64_t)J * TILE + threadIdx.x];
+        sh.put(threadIdx.x, src[(int64_t)J * TILE + threadIdx.x]);
         __syncthreads();
         float P = 0.f, Q = 0.f;
         if (J == I) {
@@ -536,7 +606,7 @@ __device__ __forceinline__ void sym_item_f64(const Src8d *__restrict__ src, int 
                                              int J1, int T, const Coef<double> &cf,
                                              double *__restrict__ rp,
                                              double *__restrict__ cp_base, Src8d *sh,
-                                             double (*colw)[2 * TILE + 64])
+                                             double (*colw)[2 * TILE])
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const OwnF64 o = own_point64(src[(int64_t)I * TILE + threadIdx.x]);

@@ -296,8 +296,8 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_sym(const Src12 *__restrict__
                                                        double *__restrict__ rowpart,
                                                        float *__restrict__ colpart)
 {
-    __shared__ Src12 sh[TILE];
-    __shared__ float colw[TPB / 64][2 * TILE + 64];
+    __shared__ SrcTileF32 sh;
+    __shared__ float colw[TPB / 64][2 * TILE];
     const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
     sym_item_f32<SCALED>(src, it.x, it.y, it.z, T, coef_f32(pp.eps, pp.kappa, SCALED),
                          rowpart + (int64_t)it.w * (2 * TILE), colpart, sh, colw);
@@ -373,14 +373,14 @@ __global__ __launch_bounds__(TPB) void k_pack_sym64(const double *__restrict__ g
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(TPB) void k_pairs_f64_sym(const Src8d *__restrict__ src,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs_f64_sym(const Src8d *__restrict__ src,
                                                        const int4 *__restrict__ items, int T,
                                                        PairParams pp,
                                                        double *__restrict__ rowpart,
                                                        double *__restrict__ colpart)
 {
     __shared__ Src8d sh[TILE];
-    __shared__ double colw[TPB / 64][2 * TILE + 64];
+    __shared__ double colw[TPB / 64][2 * TILE];
     const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
     sym_item_f64<TRANS>(src, it.x, it.y, it.z, T, Coef<double>(pp),
                         rowpart + (int64_t)it.w * (2 * TILE), colpart, sh, colw);
