@@ -604,6 +604,15 @@ int gmres(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
         LAUNCHCHK();
         // the host staging row is reused by the next fetch: drain first
         HIPCHK(hipStreamSynchronize(c->stream));
+        // Inside iterative refinement the FP64 residual of the updated
+        // iterate is taken next by the caller, which is the stronger test:
+        // a converged Arnoldi estimate ends the FP32 solve without an FP32
+        // confirmation matvec.
+        if (precision == PB_FP32_IR && k > 0 && std::fabs(gv[k]) / bnorm <= tol) {
+            st.rel = std::fabs(gv[k]) / bnorm;
+            st.converged = true;
+            return PB_OK;
+        }
     }
 }
 

@@ -304,31 +304,47 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_sym(const Src12 *__restrict__
 }
 
 // Row k = K*TILE + l: item rows of tile K, then the contributions of every tile
-// I < K, in that fixed order.  Transposed (FP64 only) the two partial rows are
-// output rows 2 and 1 and every row is scaled by its own area.
+// I < K.  Blocks of 64 rows (one tile's worth of lanes, all in tile K); wave w
+// of the 4 sums every 4th record of both lists, from record w on, and the four
+// partial sums are added in wave order, so the result does not depend on
+// scheduling.  Transposed (FP64 only) the two partial rows are output rows 2
+// and 1 and every row is scaled by its own area.
+constexpr int FIN_ROWS = 64, FIN_WAVES = 4;
+
 template <typename CT>
-__global__ __launch_bounds__(TPB) void k_sym_finish(const double *__restrict__ rowpart,
-                                                    const CT *__restrict__ colpart,
-                                                    const int32_t *__restrict__ row_start, int T,
-                                                    int64_t n, int64_t npad,
-                                                    const double *__restrict__ area,
-                                                    const double *__restrict__ x, double alpha,
-                                                    double beta, int trans, double scale1,
-                                                    double scale2, double *__restrict__ y)
+__global__ __launch_bounds__(FIN_ROWS * FIN_WAVES) void k_sym_finish(
+    const double *__restrict__ rowpart, const CT *__restrict__ colpart,
+    const int32_t *__restrict__ row_start, int T, int64_t n, int64_t npad,
+    const double *__restrict__ area, const double *__restrict__ x, double alpha, double beta,
+    int trans, double scale1, double scale2, double *__restrict__ y)
 {
-    const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (k >= n)
-        return;
-    const int K = (int)(k / TILE), l = (int)(k % TILE);
+    __shared__ double red[2][FIN_WAVES][FIN_ROWS];
+    const int lane = threadIdx.x % FIN_ROWS, w = threadIdx.x / FIN_ROWS;
+    const int64_t k = (int64_t)blockIdx.x * FIN_ROWS + lane;
     double s1 = 0.0, s2 = 0.0;
-    for (int q = row_start[K]; q < row_start[K + 1]; ++q) {
-        s1 += rowpart[(int64_t)q * (2 * TILE) + l];
-        s2 += rowpart[(int64_t)q * (2 * TILE) + TILE + l];
+    if (k < n) {
+        const int K = (int)(k / TILE), l = (int)(k % TILE);
+        for (int q = row_start[K] + w; q < row_start[K + 1]; q += FIN_WAVES) {
+            s1 += rowpart[(int64_t)q * (2 * TILE) + l];
+            s2 += rowpart[(int64_t)q * (2 * TILE) + TILE + l];
+        }
+        for (int I = w; I < K; I += FIN_WAVES) {
+            const CT *cp = colpart + sym_pair_index(I, K, T) * (2 * TILE);
+            s1 += (double)cp[l];
+            s2 += (double)cp[TILE + l];
+        }
     }
-    for (int I = 0; I < K; ++I) {
-        const CT *cp = colpart + sym_pair_index(I, K, T) * (2 * TILE);
-        s1 += (double)cp[l];
-        s2 += (double)cp[TILE + l];
+    red[0][w][lane] = s1;
+    red[1][w][lane] = s2;
+    __syncthreads();
+    if (w != 0 || k >= n)
+        return;
+    s1 = red[0][0][lane];
+    s2 = red[1][0][lane];
+#pragma unroll
+    for (int v = 1; v < FIN_WAVES; ++v) {
+        s1 += red[0][v][lane];
+        s2 += red[1][v][lane];
     }
     if (trans) {
         const double sc = area[k] * INV_4PI;
@@ -1085,7 +1101,8 @@ void launch_sym_finish(hipStream_t s, const Geo &geo, const double *rowpart,
                        const double *x, double alpha, double beta, double scale1, double scale2,
                        double *y)
 {
-    hipLaunchKernelGGL(k_sym_finish<float>, dim3(blocks_for(geo.n)), dim3(TPB), 0, s, rowpart,
+    hipLaunchKernelGGL(k_sym_finish<float>, dim3((geo.n + FIN_ROWS - 1) / FIN_ROWS),
+                       dim3(FIN_ROWS * FIN_WAVES), 0, s, rowpart,
                        colpart, row_start, n_tiles, geo.n, geo.npad, geo.g + 6 * geo.npad, x,
                        alpha, beta, 0, scale1, scale2, y);
 }
@@ -1114,7 +1131,8 @@ void launch_sym_finish64(hipStream_t s, const Geo &geo, const double *rowpart,
                          const double *colpart, const int32_t *row_start, int n_tiles,
                          const double *x, double alpha, double beta, int transpose, double *y)
 {
-    hipLaunchKernelGGL(k_sym_finish<double>, dim3(blocks_for(geo.n)), dim3(TPB), 0, s, rowpart,
+    hipLaunchKernelGGL(k_sym_finish<double>, dim3((geo.n + FIN_ROWS - 1) / FIN_ROWS),
+                       dim3(FIN_ROWS * FIN_WAVES), 0, s, rowpart,
                        colpart, row_start, n_tiles, geo.n, geo.npad, geo.g + 6 * geo.npad, x,
                        alpha, beta, transpose, 1.0, 1.0, y);
 }
