@@ -291,7 +291,7 @@ __global__ __launch_bounds__(TPB) void kb_pack_sym64(const double *__restrict__ 
 }
 
 template <bool SCALED>
-__global__ __launch_bounds__(TPB) void kb_pairs_f32_sym(const Src12 *__restrict__ src,
+__global__ __launch_bounds__(SYM_NT) void kb_pairs_f32_sym(const Src12 *__restrict__ src,
                                                         const SysDesc *__restrict__ sd,
                                                         const SItem *__restrict__ items,
                                                         int64_t n_items,
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(TPB) void kb_pairs_f32_sym(const Src12 *__restrict_
                                                         float *__restrict__ colpart)
 {
     __shared__ SrcTileF32 sh;
-    __shared__ float colw[TPB / 64][2 * TILE];
+    __shared__ float colw[SYM_NT / 64][2 * TILE];
     const CoefF32 cf = coef_f32(eps, kappa, SCALED);
     for (int64_t k = blockIdx.x; k < n_items; k += gridDim.x) {
         const SItem w = items[k];
@@ -951,11 +951,11 @@ void enqueue_matvec(pb_ctx *c, const BatchPlan &P, BatchDev &D, bool f32, int tr
         hipLaunchKernelGGL(kb_pack_sym, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd, D.blk2sys,
                            x, reinterpret_cast<Src12 *>(D.src), eps, sig);
         if (kap > 0.0)
-            hipLaunchKernelGGL(kb_pairs_f32_sym<true>, dim3(sgrid), dim3(TPB), 0, s,
+            hipLaunchKernelGGL(kb_pairs_f32_sym<true>, dim3(sgrid), dim3(SYM_NT), 0, s,
                                reinterpret_cast<const Src12 *>(D.src), D.sd, D.sitems, nsi, mask,
                                eps, kap, D.srow, static_cast<float *>(D.scol));
         else
-            hipLaunchKernelGGL(kb_pairs_f32_sym<false>, dim3(sgrid), dim3(TPB), 0, s,
+            hipLaunchKernelGGL(kb_pairs_f32_sym<false>, dim3(sgrid), dim3(SYM_NT), 0, s,
                                reinterpret_cast<const Src12 *>(D.src), D.sd, D.sitems, nsi, mask,
                                eps, kap, D.srow, static_cast<float *>(D.scol));
         hipLaunchKernelGGL(kb_sym_finish<float>, dim3(gb), dim3(TPB), 0, s, D.srow,

@@ -142,6 +142,10 @@ struct CoefF32 {
     float kappa, kexp, c13, k23;
 };
 
+// Targets per thread of the pairwise FP32 sweep (blocks of TILE / SYM_TT).
+constexpr int SYM_TT = 2;
+constexpr int SYM_NT = TILE / SYM_TT;
+
 template <int TPT, int DSLOT, bool SCALED>
 __device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&tg)[TPT][9],
                                           const CoefF32 &cf, float (&P)[TPT], float (&Q)[TPT])
@@ -339,7 +343,9 @@ __device__ __forceinline__ void pair_fwd(const Src12 &s, const OwnF32 &o, const 
 //   row j, 1 / eps: (e-1) w2n_i / r + b nu_i A u
 //   row j, 2:       u [B (nu_i A h3 + tm1 w2n_i + w1_i) + t3n C nu_i]
 // so the pair costs 44 VALU operations and two transcendentals.
-template <bool SCALED>
+// FIRST starts cp, cq; otherwise the pair's contributions are added to them
+// (the thread's further targets on the same source).
+template <bool SCALED, bool FIRST>
 __device__ __forceinline__ void pair_both(const Src12 &s, const OwnF32 &o, const CoefF32 &cf,
                                           float &P, float &Q, float &cp, float &cq)
 {
@@ -354,7 +360,7 @@ __device__ __forceinline__ void pair_both(const Src12 &s, const OwnF32 &o, const
     const float em1 = e - 1.f;
     const float em1ir = em1 * ir;
     P = fmaf(em1ir, s.w2n, P);
-    const float p2 = em1ir * o.w2n;
+    const float p2 = FIRST ? em1ir * o.w2n : fmaf(em1ir, o.w2n, cp);
     const float tm1 = fmaf(kr, e, em1);
     const float t3n = tm1 * -0.333333343f;
     const float bu = (cf.c13 - t3n) * u;
@@ -372,38 +378,59 @@ __device__ __forceinline__ void pair_both(const Src12 &s, const OwnF32 &o, const
     const float pm = o.nu * A;
     cp = fmaf(bu, pm, p2);
     const float innerr = fmaf(pm, h3, fmaf(tm1, o.w2n, o.w1));
-    cq = u * fmaf(B, innerr, tc * o.nu);
+    const float yr = fmaf(B, innerr, tc * o.nu);
+    cq = FIRST ? u * yr : fmaf(u, yr, cq);
 }
 
 // Diagonal tile (sources = the block's own targets): forward direction, j = i
-// dropped.
-template <bool SCALED>
-__device__ __forceinline__ void sweep_diag(const SrcTileF32 &sh, const OwnF32 &o,
-                                           const CoefF32 &cf, float &P, float &Q)
+// dropped.  Each thread owns TT targets, k * (TILE / TT) + threadIdx.x.
+template <bool SCALED, int TT>
+__device__ __forceinline__ void sweep_diag(const SrcTileF32 &sh, const OwnF32 (&o)[TT],
+                                           const CoefF32 &cf, float (&P)[TT], float (&Q)[TT])
 {
 #pragma unroll 2
-    for (int jj = 0; jj < TILE; ++jj)
-        pair_fwd<SCALED, true>(sh.get(jj), o, cf, jj == (int)threadIdx.x, P, Q);
+    for (int jj = 0; jj < TILE; ++jj) {
+        const Src12 s = sh.get(jj);
+#pragma unroll
+        for (int k = 0; k < TT; ++k)
+            pair_fwd<SCALED, true>(s, o[k], cf, jj == k * (TILE / TT) + (int)threadIdx.x, P[k],
+                                   Q[k]);
+    }
+}
+
+// One source against the thread's TT targets; (cp, cq) is its contribution to
+// the source's rows summed over those targets.
+template <bool SCALED, int TT>
+__device__ __forceinline__ void pair_both_tt(const Src12 &s, const OwnF32 (&o)[TT],
+                                             const CoefF32 &cf, float (&P)[TT], float (&Q)[TT],
+                                             float &cp, float &cq)
+{
+    pair_both<SCALED, true>(s, o[0], cf, P[0], Q[0], cp, cq);
+#pragma unroll
+    for (int k = 1; k < TT; ++k) {
+        __builtin_amdgcn_sched_barrier(0);
+        pair_both<SCALED, false>(s, o[k], cf, P[k], Q[k], cp, cq);
+    }
 }
 
 // Off-diagonal tile: both directions.  The contributions to the tile's source
-// rows are summed over the wave's 64 targets in groups of 4 sources (8 values
+// rows are summed over the wave's targets in groups of 4 sources (8 values
 // per lane: reduce-scatter within rows, then across the 4 rows) and stored
 // in colw[comp * TILE + j] (comp 0: row 1, 1: row 2); colw holds 2 * TILE
 // floats.
-template <bool SCALED>
-__device__ __forceinline__ void sweep_pairwise(const SrcTileF32 &sh, const OwnF32 &o,
-                                               const CoefF32 &cf, float &P, float &Q,
-                                               float *colw, int lane)
+template <bool SCALED, int TT>
+__device__ __forceinline__ void sweep_pairwise(const SrcTileF32 &sh, const OwnF32 (&o)[TT],
+                                               const CoefF32 &cf, float (&P)[TT],
+                                               float (&Q)[TT], float *colw, int lane)
 {
     for (int g = 0; g < TILE; g += 4) {
         float a[4];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             float p0, q0, p2, q2;
-            pair_both<SCALED>(sh.get(g + k), o, cf, P, Q, p0, q0);
+            pair_both_tt<SCALED, TT>(sh.get(g + k), o, cf, P, Q, p0, q0);
             __builtin_amdgcn_sched_barrier(0);
-            pair_both<SCALED>(sh.get(g + k + 2), o, cf, P, Q, p2, q2);
+            pair_both_tt<SCALED, TT>(sh.get(g + k + 2), o, cf, P, Q, p2, q2);
             rs_stage1(p0, q0, p2, q2, lane, a[2 * k], a[2 * k + 1]);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -569,36 +596,57 @@ __device__ __forceinline__ void sweep_pairwise64(const Src8d *sh, const OwnF64 &
 // (I, J) to the rows of tile J to cp_base + pair_index(I, J) * 2 TILE.  Block
 // of TPB threads; sh and colw are the block's LDS.
 
+// FP32: blocks of TILE / SYM_TT threads, each thread owning SYM_TT targets
+// (k * TILE / SYM_TT + threadIdx.x), so that every column reduction serves
+// SYM_TT pairs per lane.
 template <bool SCALED>
 __device__ __forceinline__ void sym_item_f32(const Src12 *__restrict__ src, int I, int J0, int J1,
                                              int T, const CoefF32 &cf, double *__restrict__ rp,
                                              float *__restrict__ cp_base, SrcTileF32 &sh,
                                              float (*colw)[2 * TILE])
 {
+    constexpr int TT = SYM_TT, NT = TILE / SYM_TT, NW = NT / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const OwnF32 o = own_point(src[(int64_t)I * TILE + threadIdx.x]);
-    Acc<float> aP, aQ;
+    OwnF32 o[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k)
+        o[k] = own_point(src[(int64_t)I * TILE + k * NT + threadIdx.x]);
+    Acc<float> aP[TT], aQ[TT];
     for (int J = J0; J < J1; ++J) {
         __syncthreads();
-        sh.put(threadIdx.x, src[(int64_t)J * TILE + threadIdx.x]);
+#pragma unroll
+        for (int k = 0; k < TT; ++k)
+            sh.put(k * NT + threadIdx.x, src[(int64_t)J * TILE + k * NT + threadIdx.x]);
         __syncthreads();
-        float P = 0.f, Q = 0.f;
+        float P[TT], Q[TT];
+#pragma unroll
+        for (int k = 0; k < TT; ++k)
+            P[k] = Q[k] = 0.f;
         if (J == I) {
-            sweep_diag<SCALED>(sh, o, cf, P, Q);
+            sweep_diag<SCALED, TT>(sh, o, cf, P, Q);
         } else {
-            sweep_pairwise<SCALED>(sh, o, cf, P, Q, colw[wid], lane);
+            sweep_pairwise<SCALED, TT>(sh, o, cf, P, Q, colw[wid], lane);
             __syncthreads();
             float *cp = cp_base + sym_pair_index(I, J, T) * (2 * TILE);
-            const int t = threadIdx.x;
-            cp[t] = ((colw[0][t] + colw[1][t]) + colw[2][t]) + colw[3][t];
-            cp[TILE + t] = ((colw[0][TILE + t] + colw[1][TILE + t]) + colw[2][TILE + t]) +
-                           colw[3][TILE + t];
+            for (int t = threadIdx.x; t < 2 * TILE; t += NT) {
+                float v = colw[0][t];
+#pragma unroll
+                for (int w = 1; w < NW; ++w)
+                    v += colw[w][t];
+                cp[t] = v;
+            }
         }
-        aP.add(P);
-        aQ.add(Q);
+#pragma unroll
+        for (int k = 0; k < TT; ++k) {
+            aP[k].add(P[k]);
+            aQ[k].add(Q[k]);
+        }
     }
-    rp[threadIdx.x] = aP.value();
-    rp[TILE + threadIdx.x] = aQ.value();
+#pragma unroll
+    for (int k = 0; k < TT; ++k) {
+        rp[k * NT + threadIdx.x] = aP[k].value();
+        rp[TILE + k * NT + threadIdx.x] = aQ[k].value();
+    }
 }
 
 template <bool TRANS>

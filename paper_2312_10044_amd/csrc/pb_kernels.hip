@@ -290,14 +290,14 @@ __global__ __launch_bounds__(TPB) void k_pack_sym(const double *__restrict__ g, 
 }
 
 template <bool SCALED>
-__global__ __launch_bounds__(TPB) void k_pairs_f32_sym(const Src12 *__restrict__ src,
+__global__ __launch_bounds__(SYM_NT) void k_pairs_f32_sym(const Src12 *__restrict__ src,
                                                        const int4 *__restrict__ items, int T,
                                                        PairParams pp,
                                                        double *__restrict__ rowpart,
                                                        float *__restrict__ colpart)
 {
     __shared__ SrcTileF32 sh;
-    __shared__ float colw[TPB / 64][2 * TILE];
+    __shared__ float colw[SYM_NT / 64][2 * TILE];
     const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
     sym_item_f32<SCALED>(src, it.x, it.y, it.z, T, coef_f32(pp.eps, pp.kappa, SCALED),
                          rowpart + (int64_t)it.w * (2 * TILE), colpart, sh, colw);
@@ -1089,10 +1089,10 @@ void launch_pairs_f32_sym(hipStream_t s, const float *src, const int32_t *items,
     const auto *p = reinterpret_cast<const Src12 *>(src);
     const auto *it = reinterpret_cast<const int4 *>(items);
     if (pp.kappa > 0.0)
-        hipLaunchKernelGGL(k_pairs_f32_sym<true>, dim3(n_items), dim3(TPB), 0, s, p, it,
+        hipLaunchKernelGGL(k_pairs_f32_sym<true>, dim3(n_items), dim3(SYM_NT), 0, s, p, it,
                            n_tiles, pp, rowpart, colpart);
     else
-        hipLaunchKernelGGL(k_pairs_f32_sym<false>, dim3(n_items), dim3(TPB), 0, s, p, it,
+        hipLaunchKernelGGL(k_pairs_f32_sym<false>, dim3(n_items), dim3(SYM_NT), 0, s, p, it,
                            n_tiles, pp, rowpart, colpart);
 }
 
