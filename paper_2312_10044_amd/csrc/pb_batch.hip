@@ -227,7 +227,7 @@ __global__ __launch_bounds__(TPB) void kb_pack_sym(const double *__restrict__ g,
                                                    const int32_t *__restrict__ blk2sys,
                                                    const double *__restrict__ x,
                                                    Src12 *__restrict__ src, double eps,
-                                                   double sigma)
+                                                   double sigma, int mode)
 {
     const int64_t gi = (int64_t)blockIdx.x * TPB + threadIdx.x;
     const SysDesc d = sd[blk2sys[blockIdx.x]];
@@ -236,14 +236,24 @@ __global__ __launch_bounds__(TPB) void kb_pack_sym(const double *__restrict__ g,
     Src12 s;
     if (j < d.n) {
         const double a = g[6 * gtot + gi];
-        const double ap = a * xv[d.npad + j] / sigma;
-        const double nu = 3.0 * a * xv[j];
+        double w1, w2n, nu;
+        if (mode) {
+            const double w = xv[j] / sigma;
+            w1 = (eps - 1.0) * w;
+            w2n = eps * w;
+            nu = 3.0 * xv[d.npad + j];
+        } else {
+            const double w = a * xv[d.npad + j] / sigma;
+            w1 = (1.0 - 1.0 / eps) * w;
+            w2n = -w / eps;
+            nu = 3.0 * a * xv[j];
+        }
         const double nx = g[3 * gtot + gi], ny = g[4 * gtot + gi], nz = g[5 * gtot + gi];
         s.x = float((g[gi] - d.cx) * sigma);
         s.y = float((g[gtot + gi] - d.cy) * sigma);
         s.z = float((g[2 * gtot + gi] - d.cz) * sigma);
-        s.w1 = float((1.0 - 1.0 / eps) * ap);
-        s.w2n = float(-ap / eps);
+        s.w1 = float(w1);
+        s.w2n = float(w2n);
         s.nx = float(-nx);
         s.ny = float(-ny);
         s.nz = float(-nz);
@@ -382,8 +392,8 @@ __global__ __launch_bounds__(TPB) void kb_sym_finish(const double *__restrict__ 
     }
     if (trans) {
         const double sc = g[6 * gtot + gi] * INV_4PI;
-        yv[j] = alpha * xv[j] - sc * s2;
-        yv[d.npad + j] = beta * xv[d.npad + j] - sc * s1;
+        yv[j] = alpha * xv[j] - sc * scale2 * s2;
+        yv[d.npad + j] = beta * xv[d.npad + j] - sc * scale1 * s1;
     } else {
         yv[j] = alpha * xv[j] - INV_4PI * scale1 * s1;
         yv[d.npad + j] = beta * xv[d.npad + j] - INV_4PI * scale2 * s2;
@@ -926,7 +936,23 @@ struct BatchDev {
     GState *st = nullptr;
     double *red = nullptr, *dpart = nullptr, *per = nullptr, *e = nullptr;
     int64_t vtot = 0, nvb = 0, ld = 0;
+    // persistent grids of the pairwise sweeps: the blocks the device holds
+    unsigned grid_s32 = BATCH_GRID, grid_s64 = BATCH_GRID;
 };
+
+// Blocks of `kernel` (with `threads` per block) resident on the whole device
+// at once; BATCH_GRID if the runtime cannot tell.
+template <typename F>
+unsigned resident_blocks(F *kernel, int threads)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
+        cus < 1 || per < 1)
+        return BATCH_GRID;
+    return (unsigned)(cus * per);
+}
 
 void pc_apply_batch(hipStream_t s, const BatchDev &D, int trans, const double *x, double *y)
 {
@@ -945,26 +971,32 @@ void enqueue_matvec(pb_ctx *c, const BatchPlan &P, BatchDev &D, bool f32, int tr
     const unsigned gb = nblk(P.gtot);
     const double alpha = 0.5 * (1.0 + eps), beta = 0.5 * (1.0 + 1.0 / eps);
     const int64_t nsi = (int64_t)P.sitems.size();
-    const unsigned sgrid = (unsigned)std::min<int64_t>(nsi, BATCH_GRID);
-    if (f32 && !trans && c->f32_tpt == PB_SWEEP_PAIRWISE) {
+    if (f32 && c->f32_tpt == PB_SWEEP_PAIRWISE) {
+        // transposed: stream mode 1, eps -> 1/eps in the pair constant, rows
+        // swapped and scaled by -sigma^2/eps and sigma^3 (as in the single-
+        // system sweep)
+        const unsigned sgrid = (unsigned)std::min<int64_t>(nsi, D.grid_s32);
         const double sig = f32_sigma(kap);
+        const double keps = trans ? 1.0 / eps : eps;
         hipLaunchKernelGGL(kb_pack_sym, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd, D.blk2sys,
-                           x, reinterpret_cast<Src12 *>(D.src), eps, sig);
+                           x, reinterpret_cast<Src12 *>(D.src), eps, sig, trans ? 1 : 0);
         if (kap > 0.0)
             hipLaunchKernelGGL(kb_pairs_f32_sym<true>, dim3(sgrid), dim3(SYM_NT), 0, s,
                                reinterpret_cast<const Src12 *>(D.src), D.sd, D.sitems, nsi, mask,
-                               eps, kap, D.srow, static_cast<float *>(D.scol));
+                               keps, kap, D.srow, static_cast<float *>(D.scol));
         else
             hipLaunchKernelGGL(kb_pairs_f32_sym<false>, dim3(sgrid), dim3(SYM_NT), 0, s,
                                reinterpret_cast<const Src12 *>(D.src), D.sd, D.sitems, nsi, mask,
-                               eps, kap, D.srow, static_cast<float *>(D.scol));
+                               keps, kap, D.srow, static_cast<float *>(D.scol));
+        const double s1 = trans ? -sig * sig / eps : eps * sig * sig;
         hipLaunchKernelGGL(kb_sym_finish<float>, dim3(gb), dim3(TPB), 0, s, D.srow,
                            static_cast<const float *>(D.scol), D.rs, D.g, P.gtot, D.sd,
-                           D.blk2sys, mask, x, alpha, beta, 0, eps * sig * sig, sig * sig * sig,
+                           D.blk2sys, mask, x, alpha, beta, trans ? 1 : 0, s1, sig * sig * sig,
                            y);
         return;
     }
     if (!f32 && c->f64_kind == PB_SWEEP_PAIRWISE) {
+        const unsigned sgrid = (unsigned)std::min<int64_t>(nsi, D.grid_s64);
         hipLaunchKernelGGL(kb_pack_sym64, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
                            D.blk2sys, x, reinterpret_cast<Src8d *>(D.src), trans ? 1 : 0);
         if (trans)
@@ -1156,6 +1188,8 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     BatchPlan P;
     plan_batch(P, n_sys, surf, chg);
     BatchDev D;
+    D.grid_s32 = resident_blocks(kb_pairs_f32_sym<true>, SYM_NT);
+    D.grid_s64 = resident_blocks(kb_pairs_f64_sym<false>, TPB);
     const int m = p->restart;
     D.vtot = 2 * P.gtot;
     D.nvb = D.vtot / TPB;

@@ -132,7 +132,7 @@ int ensure_sym_plan(pb_ctx *c)
 }
 
 // Pairwise FP32 sweep: every unordered pair once, both directions.
-int apply_pairwise(pb_ctx *c, const pb_params *p, const double *x, double *y)
+int apply_pairwise(pb_ctx *c, const pb_params *p, int transpose, const double *x, double *y)
 {
     const Geo &g = c->g;
     TRY(ensure_sym_plan(c));
@@ -144,18 +144,23 @@ int apply_pairwise(pb_ctx *c, const pb_params *p, const double *x, double *y)
                sizeof(float) * 2 * TILE * (size_t)std::max<int64_t>(T * (T - 1) / 2, 1)));
     const PairParams pp = pair_params(c, p);
     const double eps = pp.eps, sig = f32_sigma(pp.kappa);
-    launch_pack_sym(c->stream, g, x, as<float>(c->sym_src), pp.cx, pp.cy, pp.cz, eps, sig);
+    launch_pack_sym(c->stream, g, x, as<float>(c->sym_src), pp.cx, pp.cy, pp.cz, eps, sig,
+                    transpose ? 1 : 0);
     LAUNCHCHK();
     {
-        ProfScope ps(c, PB_KERNEL_PAIRS_FP32, (double)g.n * (double)(g.n - 1));
+        ProfScope ps(c, transpose ? PB_KERNEL_PAIRS_FP32_T : PB_KERNEL_PAIRS_FP32,
+                     (double)g.n * (double)(g.n - 1));
         launch_pairs_f32_sym(c->stream, as<float>(c->sym_src), as<int32_t>(c->sym_items),
-                             pl.n_items, pl.n_tiles, pp, as<double>(c->sym_rowpart),
-                             as<float>(c->sym_colpart));
+                             pl.n_items, pl.n_tiles, pp, transpose ? 1 : 0,
+                             as<double>(c->sym_rowpart), as<float>(c->sym_colpart));
     }
     LAUNCHCHK();
+    // lengths in units of 1/kappa: row 1 sums P / (eps sigma^2) forward and
+    // -eps P^T / sigma^2 transposed, row 2 sums Q / sigma^3
+    const double s1 = transpose ? -sig * sig / eps : eps * sig * sig;
     launch_sym_finish(c->stream, g, as<double>(c->sym_rowpart), as<float>(c->sym_colpart),
                       as<int32_t>(c->sym_rowstart), pl.n_tiles, x, 0.5 * (1.0 + eps),
-                      0.5 * (1.0 + 1.0 / eps), eps * sig * sig, sig * sig * sig, y);
+                      0.5 * (1.0 + 1.0 / eps), transpose ? 1 : 0, s1, sig * sig * sig, y);
     LAUNCHCHK();
     return PB_OK;
 }
@@ -197,8 +202,8 @@ int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
         TRY(tree_prepare(c, c->t_solve_n0));
         return tree_apply(c, p, c->t_theta, c->t_order, x, y, nullptr);
     }
-    if (precision == PB_FP32_IR && !transpose && c->f32_tpt == PB_SWEEP_PAIRWISE)
-        return apply_pairwise(c, p, x, y);
+    if (precision == PB_FP32_IR && c->f32_tpt == PB_SWEEP_PAIRWISE)
+        return apply_pairwise(c, p, transpose, x, y);
     if (precision == PB_FP64 && c->f64_kind == PB_SWEEP_PAIRWISE)
         return apply_pairwise64(c, p, transpose, x, y);
     const bool fast32 = precision == PB_FP32_IR && !transpose;

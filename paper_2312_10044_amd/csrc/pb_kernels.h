@@ -89,14 +89,16 @@ __host__ __device__ inline int64_t sym_pair_index(int64_t I, int64_t J, int64_t 
 {
     return I * T - I * (I + 1) / 2 + (J - I - 1);
 }
+// mode / transpose: 0 forward, 1 transposed (x = [l1; l2]).
 void launch_pack_sym(hipStream_t s, const Geo &geo, const double *x, float *src, double cx,
-                     double cy, double cz, double eps, double sigma);
+                     double cy, double cz, double eps, double sigma, int mode);
 void launch_pairs_f32_sym(hipStream_t s, const float *src, const int32_t *items, int n_items,
-                          int n_tiles, const PairParams &pp, double *rowpart, float *colpart);
+                          int n_tiles, const PairParams &pp, int transpose, double *rowpart,
+                          float *colpart);
 void launch_sym_finish(hipStream_t s, const Geo &geo, const double *rowpart,
                        const float *colpart, const int32_t *row_start, int n_tiles,
-                       const double *x, double alpha, double beta, double scale1, double scale2,
-                       double *y);
+                       const double *x, double alpha, double beta, int transpose, double scale1,
+                       double scale2, double *y);
 
 // Pairwise FP64 sweep on the same work items (forward and transposed).
 void launch_pack_sym64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode);

@@ -253,12 +253,18 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_fwd(const Src8<float> *__rest
     }
 }
 
-// ---- pairwise FP32 forward sweep ------------------------------------------
-
+// ---- pairwise FP32 sweep -----------------------------------------------------
+//
+// Forward (mode 0): w1 = (1 - 1/eps) a psi / sigma, w2n = -a psi / (eps sigma),
+// nu = 3 a phi.  Transposed (mode 1), x = [l1; l2]: w1 = (eps - 1) l1 / sigma,
+// w2n = eps l1 / sigma, nu = 3 l2.  The generic transposed pair algebra
+// (P with the coefficient -g3, Q with g2) then takes the forward reduced form
+// with eps replaced by 1/eps in the constant c13 = (1 - 1/eps)/3: its first
+// row sums -eps P^T and its second row Q^T, in units of 1/kappa.
 __global__ __launch_bounds__(TPB) void k_pack_sym(const double *__restrict__ g, int64_t n,
                                                   int64_t npad, const double *__restrict__ x,
                                                   Src12 *__restrict__ src, double cx, double cy,
-                                                  double cz, double eps, double sigma)
+                                                  double cz, double eps, double sigma, int mode)
 {
     const int64_t j = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (j >= npad)
@@ -266,14 +272,24 @@ __global__ __launch_bounds__(TPB) void k_pack_sym(const double *__restrict__ g, 
     Src12 s;
     if (j < n) {
         const double a = g[6 * npad + j];
-        const double ap = a * x[n + j] / sigma;
-        const double nu = 3.0 * a * x[j];
+        double w1, w2n, nu;
+        if (mode) {
+            const double w = x[j] / sigma;
+            w1 = (eps - 1.0) * w;
+            w2n = eps * w;
+            nu = 3.0 * x[n + j];
+        } else {
+            const double w = a * x[n + j] / sigma;
+            w1 = (1.0 - 1.0 / eps) * w;
+            w2n = -w / eps;
+            nu = 3.0 * a * x[j];
+        }
         const double nx = g[3 * npad + j], ny = g[4 * npad + j], nz = g[5 * npad + j];
         s.x = float((g[j] - cx) * sigma);
         s.y = float((g[npad + j] - cy) * sigma);
         s.z = float((g[2 * npad + j] - cz) * sigma);
-        s.w1 = float((1.0 - 1.0 / eps) * ap);
-        s.w2n = float(-ap / eps);
+        s.w1 = float(w1);
+        s.w2n = float(w2n);
         s.nx = float(-nx);
         s.ny = float(-ny);
         s.nz = float(-nz);
@@ -307,8 +323,8 @@ __global__ __launch_bounds__(SYM_NT) void k_pairs_f32_sym(const Src12 *__restric
 // I < K.  Blocks of 64 rows (one tile's worth of lanes, all in tile K); wave w
 // of the 4 sums every 4th record of both lists, from record w on, and the four
 // partial sums are added in wave order, so the result does not depend on
-// scheduling.  Transposed (FP64 only) the two partial rows are output rows 2
-// and 1 and every row is scaled by its own area.
+// scheduling.  Transposed, the two partial rows are output rows 2 and 1 and
+// every row is scaled by its own area (and by scale1, scale2 as forward).
 constexpr int FIN_ROWS = 64, FIN_WAVES = 4;
 
 template <typename CT>
@@ -348,8 +364,8 @@ __global__ __launch_bounds__(FIN_ROWS * FIN_WAVES) void k_sym_finish(
     }
     if (trans) {
         const double sc = area[k] * INV_4PI;
-        y[k] = alpha * x[k] - sc * s2;
-        y[n + k] = beta * x[n + k] - sc * s1;
+        y[k] = alpha * x[k] - sc * scale2 * s2;
+        y[n + k] = beta * x[n + k] - sc * scale1 * s1;
     } else {
         y[k] = alpha * x[k] - INV_4PI * scale1 * s1;
         y[n + k] = beta * x[n + k] - INV_4PI * scale2 * s2;
@@ -1077,34 +1093,38 @@ void launch_pairs_f32_fwd(hipStream_t s, const Geo &geo, const float *src, const
 }
 
 void launch_pack_sym(hipStream_t s, const Geo &geo, const double *x, float *src, double cx,
-                     double cy, double cz, double eps, double sigma)
+                     double cy, double cz, double eps, double sigma, int mode)
 {
     hipLaunchKernelGGL(k_pack_sym, dim3(blocks_for(geo.npad)), dim3(TPB), 0, s, geo.g, geo.n,
-                       geo.npad, x, reinterpret_cast<Src12 *>(src), cx, cy, cz, eps, sigma);
+                       geo.npad, x, reinterpret_cast<Src12 *>(src), cx, cy, cz, eps, sigma, mode);
 }
 
 void launch_pairs_f32_sym(hipStream_t s, const float *src, const int32_t *items, int n_items,
-                          int n_tiles, const PairParams &pp, double *rowpart, float *colpart)
+                          int n_tiles, const PairParams &pp, int transpose, double *rowpart,
+                          float *colpart)
 {
     const auto *p = reinterpret_cast<const Src12 *>(src);
     const auto *it = reinterpret_cast<const int4 *>(items);
-    if (pp.kappa > 0.0)
+    PairParams q = pp;
+    if (transpose)
+        q.eps = 1.0 / pp.eps;   // the pair constant of the transposed reduced form
+    if (q.kappa > 0.0)
         hipLaunchKernelGGL(k_pairs_f32_sym<true>, dim3(n_items), dim3(SYM_NT), 0, s, p, it,
-                           n_tiles, pp, rowpart, colpart);
+                           n_tiles, q, rowpart, colpart);
     else
         hipLaunchKernelGGL(k_pairs_f32_sym<false>, dim3(n_items), dim3(SYM_NT), 0, s, p, it,
-                           n_tiles, pp, rowpart, colpart);
+                           n_tiles, q, rowpart, colpart);
 }
 
 void launch_sym_finish(hipStream_t s, const Geo &geo, const double *rowpart,
                        const float *colpart, const int32_t *row_start, int n_tiles,
-                       const double *x, double alpha, double beta, double scale1, double scale2,
-                       double *y)
+                       const double *x, double alpha, double beta, int transpose, double scale1,
+                       double scale2, double *y)
 {
     hipLaunchKernelGGL(k_sym_finish<float>, dim3((geo.n + FIN_ROWS - 1) / FIN_ROWS),
                        dim3(FIN_ROWS * FIN_WAVES), 0, s, rowpart,
                        colpart, row_start, n_tiles, geo.n, geo.npad, geo.g + 6 * geo.npad, x,
-                       alpha, beta, 0, scale1, scale2, y);
+                       alpha, beta, transpose, scale1, scale2, y);
 }
 
 void launch_pack_sym64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode)

@@ -1,5 +1,6 @@
-"""The FP32 forward sweep in both kinds (pairwise: each unordered pair once;
-per-target: 1 or 2 targets per thread) against the oracle's matvec."""
+"""The FP32 sweeps in both kinds (pairwise: each unordered pair once, forward
+and transposed; per-target: 1 or 2 targets per thread) and the pairwise FP64
+sweep against the oracle's matvec."""
 import numpy as np
 import pytest
 
@@ -31,13 +32,15 @@ def star12():
     return synth.star_protein(freq=12, r0=10.0, n_charges=300, seed=41)
 
 
-def _err(m, ctx, w, kappa=KAPPA, rows=None, seed=0):
+def _err(m, ctx, w, kappa=KAPPA, rows=None, seed=0, transpose=False):
     g = dsbi.geometry(w.verts, w.tris)
     x = np.random.default_rng(seed).normal(size=2 * g.n)
-    y = ctx.pb_matvec(w.verts, w.tris, x, m.Params(kappa=kappa), precision=m.PB_FP32_IR)
+    y = ctx.pb_matvec(w.verts, w.tris, x, m.Params(kappa=kappa), transpose=transpose,
+                      precision=m.PB_FP32_IR)
     if rows is None:
         rows = np.arange(g.n)
-    y1, y2, s1, s2 = dsbi.matvec(g, 80.0, kappa, x, rows=rows, with_abs=True)
+    y1, y2, s1, s2 = dsbi.matvec(g, 80.0, kappa, x, rows=rows, transpose=transpose,
+                                 with_abs=True)
     return max((np.abs(y[rows] - y1) / s1).max(), (np.abs(y[g.n + rows] - y2) / s2).max()), y
 
 
@@ -54,6 +57,21 @@ def test_fp32_sweep_kinds_all_rows(pb, star12, kind, kappa):
     assert err <= 5e-5
 
 
+@pytest.mark.parametrize("kappa", [KAPPA, 0.0])
+def test_fp32_pairwise_transposed_all_rows(pb, star12, kappa):
+    """The transposed operator through the pairwise sweep (stream of l1, l2,
+    the pair constant with eps -> 1/eps, rows swapped and area-scaled)."""
+    m, ctx = pb
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 32768)
+    _say(f"fp32 pairwise transposed kappa={kappa}: {star12.n_tri} triangles")
+    err, y = _err(m, ctx, star12, kappa=kappa, seed=8, transpose=True)
+    _e, y2 = _err(m, ctx, star12, kappa=kappa, seed=8, transpose=True)
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
+    _say(f"  max |dy|/S = {err:.3e}")
+    assert err <= 5e-5
+    assert np.array_equal(y, y2)
+
+
 @pytest.mark.parametrize("freq,r0", [(2, 3.0), (8, 2.0)])
 def test_pairwise_small_meshes(pb, freq, r0):
     """80 triangles (one real tile, one tile of padding only) and 1,280."""
@@ -63,8 +81,9 @@ def test_pairwise_small_meshes(pb, freq, r0):
     ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 32768)
     _say(f"pairwise small mesh: {w.n_tri} triangles")
     err, _y = _err(m, ctx, w)
+    err_t, _y = _err(m, ctx, w, transpose=True)
     ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
-    assert err <= 5e-5
+    assert err <= 5e-5 and err_t <= 5e-5
 
 
 @pytest.mark.parametrize("waves", [256, 8192, 131072])
