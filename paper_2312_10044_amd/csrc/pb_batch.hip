@@ -325,7 +325,7 @@ __global__ __launch_bounds__(SYM_NT) void kb_pairs_f32_sym(const Src12 *__restri
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(5))) void kb_pairs_f64_sym(const Src8d *__restrict__ src,
+__global__ __launch_bounds__(SYM64_NT) void kb_pairs_f64_sym(const Src8d *__restrict__ src,
                                                         const SysDesc *__restrict__ sd,
                                                         const SItem *__restrict__ items,
                                                         int64_t n_items,
@@ -334,8 +334,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(5))) void k
                                                         double *__restrict__ rowpart,
                                                         double *__restrict__ colpart)
 {
-    __shared__ Src8d sh[TILE];
-    __shared__ double colw[TPB / 64][2 * TILE];
+    __shared__ Src8d sh[SYM64_NS];
+    __shared__ double colw[SYM64_NT / 64][2 * SYM64_NS];
     PairParams pp;
     pp.eps = eps;
     pp.kappa = kappa;
@@ -1000,11 +1000,11 @@ void enqueue_matvec(pb_ctx *c, const BatchPlan &P, BatchDev &D, bool f32, int tr
         hipLaunchKernelGGL(kb_pack_sym64, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
                            D.blk2sys, x, reinterpret_cast<Src8d *>(D.src), trans ? 1 : 0);
         if (trans)
-            hipLaunchKernelGGL(kb_pairs_f64_sym<true>, dim3(sgrid), dim3(TPB), 0, s,
+            hipLaunchKernelGGL(kb_pairs_f64_sym<true>, dim3(sgrid), dim3(SYM64_NT), 0, s,
                                reinterpret_cast<const Src8d *>(D.src), D.sd, D.sitems, nsi, mask,
                                eps, kap, D.srow, static_cast<double *>(D.scol));
         else
-            hipLaunchKernelGGL(kb_pairs_f64_sym<false>, dim3(sgrid), dim3(TPB), 0, s,
+            hipLaunchKernelGGL(kb_pairs_f64_sym<false>, dim3(sgrid), dim3(SYM64_NT), 0, s,
                                reinterpret_cast<const Src8d *>(D.src), D.sd, D.sitems, nsi, mask,
                                eps, kap, D.srow, static_cast<double *>(D.scol));
         hipLaunchKernelGGL(kb_sym_finish<double>, dim3(gb), dim3(TPB), 0, s, D.srow,
@@ -1189,7 +1189,7 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     plan_batch(P, n_sys, surf, chg);
     BatchDev D;
     D.grid_s32 = resident_blocks(kb_pairs_f32_sym<true>, SYM_NT);
-    D.grid_s64 = resident_blocks(kb_pairs_f64_sym<false>, TPB);
+    D.grid_s64 = resident_blocks(kb_pairs_f64_sym<false>, SYM64_NT);
     const int m = p->restart;
     D.vtot = 2 * P.gtot;
     D.nvb = D.vtot / TPB;

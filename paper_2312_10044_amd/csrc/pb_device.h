@@ -515,7 +515,9 @@ __device__ __forceinline__ OwnF64 own_point64(const Src8d &e)
     return OwnF64{e.x, e.y, e.z, e.nx, e.ny, e.nz, e.w, e.f};
 }
 
-template <bool TRANS, bool BOTH, bool DIAG>
+// With BOTH, FIRST starts cp, cq; otherwise the pair's contributions to the
+// source's rows are added to them (the thread's further targets).
+template <bool TRANS, bool BOTH, bool DIAG, bool FIRST = true>
 __device__ __forceinline__ void pair64(const Src8d &s, const OwnF64 &o, const Coef<double> &cf,
                                        bool skip, double &P, double &Q, double &cp, double &cq)
 {
@@ -546,36 +548,73 @@ __device__ __forceinline__ void pair64(const Src8d &s, const OwnF64 &o, const Co
     Q = fma(u, fma(-A, fma(md, h, cQ * s.w), tc * s.f), Q);
     if (BOTH) {
         const double pm = o.f * A;
-        cp = fma(-cPu, pm, a * o.w);
-        cq = u * fma(B, fma(-pm, h, cQ * o.w), tc * o.f);
+        const double yq = fma(B, fma(-pm, h, cQ * o.w), tc * o.f);
+        if (FIRST) {
+            cp = fma(-cPu, pm, a * o.w);
+            cq = u * yq;
+        } else {
+            cp = fma(-cPu, pm, fma(a, o.w, cp));
+            cq = fma(u, yq, cq);
+        }
+    }
+}
+
+// Sources per LDS stage and targets per thread of the pairwise FP64 sweep:
+// blocks of TILE / SYM64_TT threads, each owning SYM64_TT targets; the
+// source tile is staged in halves so that a block holds 12 KB of LDS.
+constexpr int SYM64_TT = 2;
+constexpr int SYM64_NT = TILE / SYM64_TT;
+constexpr int SYM64_NS = SYM64_NT;
+
+// Diagonal tile: forward direction, j = i dropped; sh holds sources
+// base .. base + SYM64_NS - 1 of the tile.
+template <bool TRANS>
+__device__ __forceinline__ void sweep_diag64(const Src8d *sh, int base, const OwnF64 (&o)[SYM64_TT],
+                                             const Coef<double> &cf, double (&P)[SYM64_TT],
+                                             double (&Q)[SYM64_TT])
+{
+    double dummy0 = 0.0, dummy1 = 0.0;
+#pragma unroll 2
+    for (int jj = 0; jj < SYM64_NS; ++jj) {
+        const Src8d s = sh[jj];
+#pragma unroll
+        for (int k = 0; k < SYM64_TT; ++k)
+            pair64<TRANS, false, true>(s, o[k], cf,
+                                       base + jj == k * SYM64_NT + (int)threadIdx.x, P[k], Q[k],
+                                       dummy0, dummy1);
     }
 }
 
 template <bool TRANS>
-__device__ __forceinline__ void sweep_diag64(const Src8d *sh, const OwnF64 &o,
-                                             const Coef<double> &cf, double &P, double &Q)
+__device__ __forceinline__ void pair64_tt(const Src8d &s, const OwnF64 (&o)[SYM64_TT],
+                                          const Coef<double> &cf, double (&P)[SYM64_TT],
+                                          double (&Q)[SYM64_TT], double &cp, double &cq)
 {
-    double dummy0 = 0.0, dummy1 = 0.0;
-#pragma unroll 2
-    for (int jj = 0; jj < TILE; ++jj)
-        pair64<TRANS, false, true>(sh[jj], o, cf, jj == (int)threadIdx.x, P, Q, dummy0, dummy1);
+    pair64<TRANS, true, false, true>(s, o[0], cf, false, P[0], Q[0], cp, cq);
+#pragma unroll
+    for (int k = 1; k < SYM64_TT; ++k) {
+        __builtin_amdgcn_sched_barrier(0);
+        pair64<TRANS, true, false, false>(s, o[k], cf, false, P[k], Q[k], cp, cq);
+    }
 }
 
-// Off-diagonal tile, both directions; column sums as in sweep_pairwise,
-// stored in colw[comp * TILE + j] (2 * TILE doubles).
+// Off-diagonal tile, both directions; column sums as in sweep_pairwise, over
+// the SYM64_NS staged sources, stored in colw[comp * SYM64_NS + j]
+// (2 * SYM64_NS doubles).
 template <bool TRANS>
-__device__ __forceinline__ void sweep_pairwise64(const Src8d *sh, const OwnF64 &o,
-                                                 const Coef<double> &cf, double &P, double &Q,
+__device__ __forceinline__ void sweep_pairwise64(const Src8d *sh, const OwnF64 (&o)[SYM64_TT],
+                                                 const Coef<double> &cf,
+                                                 double (&P)[SYM64_TT], double (&Q)[SYM64_TT],
                                                  double *colw, int lane)
 {
-    for (int g = 0; g < TILE; g += 4) {
+    for (int g = 0; g < SYM64_NS; g += 4) {
         double a[4];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             double p0, q0, p2, q2;
-            pair64<TRANS, true, false>(sh[g + k], o, cf, false, P, Q, p0, q0);
+            pair64_tt<TRANS>(sh[g + k], o, cf, P, Q, p0, q0);
             __builtin_amdgcn_sched_barrier(0);
-            pair64<TRANS, true, false>(sh[g + k + 2], o, cf, false, P, Q, p2, q2);
+            pair64_tt<TRANS>(sh[g + k + 2], o, cf, P, Q, p2, q2);
             rs_stage1(p0, q0, p2, q2, lane, a[2 * k], a[2 * k + 1]);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -583,7 +622,7 @@ __device__ __forceinline__ void sweep_pairwise64(const Src8d *sh, const OwnF64 &
         t += __shfl_xor(t, 16, 64);
         t += __shfl_xor(t, 32, 64);
         const int q = (lane >> 1) & 7;   // as in sweep_pairwise
-        colw[(q & 1) * TILE + g + (q >> 1)] = t;
+        colw[(q & 1) * SYM64_NS + g + (q >> 1)] = t;
     }
 }
 
@@ -649,37 +688,55 @@ __device__ __forceinline__ void sym_item_f32(const Src12 *__restrict__ src, int 
     }
 }
 
+// FP64: blocks of SYM64_NT threads (SYM64_TT targets each); every source tile
+// is staged and swept in halves of SYM64_NS sources.
 template <bool TRANS>
 __device__ __forceinline__ void sym_item_f64(const Src8d *__restrict__ src, int I, int J0,
                                              int J1, int T, const Coef<double> &cf,
                                              double *__restrict__ rp,
                                              double *__restrict__ cp_base, Src8d *sh,
-                                             double (*colw)[2 * TILE])
+                                             double (*colw)[2 * SYM64_NS])
 {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const OwnF64 o = own_point64(src[(int64_t)I * TILE + threadIdx.x]);
-    double aP = 0.0, aQ = 0.0;
+    constexpr int TT = SYM64_TT, NT = SYM64_NT, NS = SYM64_NS;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, t = threadIdx.x;
+    OwnF64 o[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k)
+        o[k] = own_point64(src[(int64_t)I * TILE + k * NT + t]);
+    double aP[TT], aQ[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k)
+        aP[k] = aQ[k] = 0.0;
     for (int J = J0; J < J1; ++J) {
-        __syncthreads();
-        sh[threadIdx.x] = src[(int64_t)J * TILE + threadIdx.x];
-        __syncthreads();
-        double P = 0.0, Q = 0.0;
-        if (J == I) {
-            sweep_diag64<TRANS>(sh, o, cf, P, Q);
-        } else {
-            sweep_pairwise64<TRANS>(sh, o, cf, P, Q, colw[wid], lane);
+        double P[TT], Q[TT];
+#pragma unroll
+        for (int k = 0; k < TT; ++k)
+            P[k] = Q[k] = 0.0;
+        for (int base = 0; base < TILE; base += NS) {
             __syncthreads();
-            double *cp = cp_base + sym_pair_index(I, J, T) * (2 * TILE);
-            const int t = threadIdx.x;
-            cp[t] = ((colw[0][t] + colw[1][t]) + colw[2][t]) + colw[3][t];
-            cp[TILE + t] = ((colw[0][TILE + t] + colw[1][TILE + t]) + colw[2][TILE + t]) +
-                           colw[3][TILE + t];
+            sh[t] = src[(int64_t)J * TILE + base + t];
+            __syncthreads();
+            if (J == I) {
+                sweep_diag64<TRANS>(sh, base, o, cf, P, Q);
+            } else {
+                sweep_pairwise64<TRANS>(sh, o, cf, P, Q, colw[wid], lane);
+                __syncthreads();
+                double *cp = cp_base + sym_pair_index(I, J, T) * (2 * TILE);
+                cp[base + t] = colw[0][t] + colw[1][t];
+                cp[TILE + base + t] = colw[0][NS + t] + colw[1][NS + t];
+            }
         }
-        aP += P;
-        aQ += Q;
+#pragma unroll
+        for (int k = 0; k < TT; ++k) {
+            aP[k] += P[k];
+            aQ[k] += Q[k];
+        }
     }
-    rp[threadIdx.x] = aP;
-    rp[TILE + threadIdx.x] = aQ;
+#pragma unroll
+    for (int k = 0; k < TT; ++k) {
+        rp[k * NT + t] = aP[k];
+        rp[TILE + k * NT + t] = aQ[k];
+    }
 }
 
 inline __device__ CoefF32 coef_f32(double eps, double kappa, bool scaled)

@@ -405,14 +405,14 @@ __global__ __launch_bounds__(TPB) void k_pack_sym64(const double *__restrict__ g
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(5))) void k_pairs_f64_sym(const Src8d *__restrict__ src,
+__global__ __launch_bounds__(SYM64_NT) void k_pairs_f64_sym(const Src8d *__restrict__ src,
                                                        const int4 *__restrict__ items, int T,
                                                        PairParams pp,
                                                        double *__restrict__ rowpart,
                                                        double *__restrict__ colpart)
 {
-    __shared__ Src8d sh[TILE];
-    __shared__ double colw[TPB / 64][2 * TILE];
+    __shared__ Src8d sh[SYM64_NS];
+    __shared__ double colw[SYM64_NT / 64][2 * SYM64_NS];
     const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
     sym_item_f64<TRANS>(src, it.x, it.y, it.z, T, Coef<double>(pp),
                         rowpart + (int64_t)it.w * (2 * TILE), colpart, sh, colw);
@@ -1140,10 +1140,10 @@ void launch_pairs_f64_sym(hipStream_t s, const double *src, const int32_t *items
     const auto *p = reinterpret_cast<const Src8d *>(src);
     const auto *it = reinterpret_cast<const int4 *>(items);
     if (transpose)
-        hipLaunchKernelGGL(k_pairs_f64_sym<true>, dim3(n_items), dim3(TPB), 0, s, p, it, n_tiles,
+        hipLaunchKernelGGL(k_pairs_f64_sym<true>, dim3(n_items), dim3(SYM64_NT), 0, s, p, it, n_tiles,
                            pp, rowpart, colpart);
     else
-        hipLaunchKernelGGL(k_pairs_f64_sym<false>, dim3(n_items), dim3(TPB), 0, s, p, it, n_tiles,
+        hipLaunchKernelGGL(k_pairs_f64_sym<false>, dim3(n_items), dim3(SYM64_NT), 0, s, p, it, n_tiles,
                            pp, rowpart, colpart);
 }
 
