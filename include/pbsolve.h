@@ -250,14 +250,16 @@ int pb_solve_tree(pb_ctx *ctx, const pb_surface *s, const pb_charges *q, const p
                   pb_info *info);
 
 /* ---- launch configuration and autotuning ------------------------------- */
-/* The FP32 forward pair sweep (the hot loop of PB_FP32_IR solves) comes in
- * two kinds, selected by `targets_per_thread`:
+/* The FP32 pair sweep (the hot loop of PB_FP32_IR solves and of their
+ * adjoints) comes in two kinds, selected by `targets_per_thread`:
  *   1 or 2             per-target sweep: that many collocation points per
- *                      thread, the source range split into chunks;
- *   PB_SWEEP_PAIRWISE  pairwise sweep: each unordered pair (i, j) is
- *                      evaluated once and feeds both row i and row j (the
- *                      distance, exp(-kappa r) and the kernel factors they
- *                      share are computed once).
+ *                      thread, the source range split into chunks (forward;
+ *                      the transposed sweep of this kind has one target per
+ *                      thread);
+ *   PB_SWEEP_PAIRWISE  pairwise sweep, forward and transposed: each
+ *                      unordered pair (i, j) is evaluated once and feeds both
+ *                      row i and row j (the distance, exp(-kappa r) and the
+ *                      kernel factors they share are computed once).
  * Either kind sizes one launch to about `target_waves` wavefronts.  0 leaves a
  * value unchanged.  Defaults: PB_SWEEP_PAIRWISE, 131072.  Both kinds give the
  * same matvec up to FP32 rounding; only the summation order differs. */

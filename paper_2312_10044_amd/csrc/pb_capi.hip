@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace pbk;
@@ -262,6 +263,82 @@ namespace pbk {
 // stable counting sort into its octants, so the ranges of the children follow
 // each other in octant order and the final `perm` lists the leaves depth
 // first.
+namespace {
+
+struct LeafFrame {
+    int64_t a, b;   // range of perm
+    double c[3], h;
+    int depth;
+};
+
+// Splits frame f of perm by octant (stable) and returns the child frames in
+// octant order; or, if f is a leaf, appends its leaf ends to `ends`.
+void split_frame(const double *x, const double *y, const double *z, int n0, const LeafFrame &f,
+                 int32_t *perm, int32_t *tmp, uint8_t *oct, std::vector<LeafFrame> &kids,
+                 std::vector<int32_t> &ends)
+{
+    kids.clear();
+    const int64_t m = f.b - f.a;
+    if (m <= n0 || f.depth >= 40) {
+        // at the depth limit (coincident points) the leaf is cut into
+        // consecutive runs of at most n0 points
+        for (int64_t a = f.a; a < f.b; a += n0)
+            ends.push_back((int32_t)std::min(f.b, a + (int64_t)n0));
+        return;
+    }
+    int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t k = f.a; k < f.b; ++k) {
+        const int32_t i = perm[k];
+        const int o =
+            (x[i] >= f.c[0] ? 1 : 0) + (y[i] >= f.c[1] ? 2 : 0) + (z[i] >= f.c[2] ? 4 : 0);
+        oct[k] = (uint8_t)o;
+        ++cnt[o];
+    }
+    int64_t off[9];
+    off[0] = f.a;
+    for (int o = 0; o < 8; ++o)
+        off[o + 1] = off[o] + cnt[o];
+    int64_t put[8];
+    for (int o = 0; o < 8; ++o)
+        put[o] = off[o];
+    for (int64_t k = f.a; k < f.b; ++k)
+        tmp[put[oct[k]]++] = perm[k];
+    std::copy(tmp + f.a, tmp + f.b, perm + f.a);
+    const double hh = 0.5 * f.h;
+    for (int o = 0; o < 8; ++o) {
+        if (cnt[o] == 0)
+            continue;
+        kids.push_back(LeafFrame{off[o], off[o + 1],
+                                 {f.c[0] + ((o & 1) ? hh : -hh), f.c[1] + ((o & 2) ? hh : -hh),
+                                  f.c[2] + ((o & 4) ? hh : -hh)},
+                                 hh, f.depth + 1});
+    }
+}
+
+// Depth-first build of the subtree of `root`; leaf ends in octant order.
+void build_subtree(const double *x, const double *y, const double *z, int n0,
+                   const LeafFrame &root, int32_t *perm, int32_t *tmp, uint8_t *oct,
+                   std::vector<int32_t> &ends)
+{
+    std::vector<LeafFrame> stack{root}, kids;
+    while (!stack.empty()) {
+        const LeafFrame f = stack.back();
+        stack.pop_back();
+        split_frame(x, y, z, n0, f, perm, tmp, oct, kids, ends);
+        // children pushed in reverse so they pop in octant order
+        for (auto it = kids.rbegin(); it != kids.rend(); ++it)
+            stack.push_back(*it);
+    }
+}
+
+}  // namespace
+
+// Octree over the collocation points: a cell with more than n0 points is split
+// at its centre into octants (stable), a cell with at most n0 points is a leaf;
+// perm lists the points leaf by leaf in depth-first octant order and
+// start[l] .. start[l + 1] delimits leaf l.  The subtrees of the root's
+// children are built on their own threads (disjoint ranges of perm); the
+// result does not depend on the thread count.
 void build_leaves(const double *x, const double *y, const double *z, int64_t n, int n0,
                   std::vector<int32_t> &perm, std::vector<int32_t> &start)
 {
@@ -273,64 +350,39 @@ void build_leaves(const double *x, const double *y, const double *z, int64_t n, 
             hi[k] = std::max(hi[k], p[k]);
         }
     }
-    struct Frame {
-        int64_t a, b;   // range of perm
-        double c[3], h;
-        int depth;
-    };
     perm.resize(n);
     for (int64_t i = 0; i < n; ++i)
         perm[i] = (int32_t)i;
     std::vector<int32_t> tmp(n);
     std::vector<uint8_t> oct(n);
-    start.assign(1, 0);
-    std::vector<Frame> stack;
-    Frame root{0, n, {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])}, 0.0,
-               0};
+    LeafFrame root{0, n, {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])},
+                   0.0, 0};
     for (int k = 0; k < 3; ++k)
         root.h = std::max(root.h, 0.5 * (hi[k] - lo[k]));
-    stack.push_back(root);
-    while (!stack.empty()) {
-        const Frame f = stack.back();
-        stack.pop_back();
-        const int64_t m = f.b - f.a;
-        if (m <= n0 || f.depth >= 40) {
-            // at the depth limit (coincident points) the leaf is cut into
-            // consecutive runs of at most n0 points
-            for (int64_t a = f.a; a < f.b; a += n0)
-                start.push_back((int32_t)std::min(f.b, a + (int64_t)n0));
-            continue;
-        }
-        int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int64_t k = f.a; k < f.b; ++k) {
-            const int32_t i = perm[k];
-            const int o = (x[i] >= f.c[0] ? 1 : 0) + (y[i] >= f.c[1] ? 2 : 0) +
-                          (z[i] >= f.c[2] ? 4 : 0);
-            oct[k] = (uint8_t)o;
-            ++cnt[o];
-        }
-        int64_t off[9];
-        off[0] = f.a;
-        for (int o = 0; o < 8; ++o)
-            off[o + 1] = off[o] + cnt[o];
-        int64_t put[8];
-        for (int o = 0; o < 8; ++o)
-            put[o] = off[o];
-        for (int64_t k = f.a; k < f.b; ++k)
-            tmp[put[oct[k]]++] = perm[k];
-        std::copy(tmp.begin() + f.a, tmp.begin() + f.b, perm.begin() + f.a);
-        // children pushed in reverse so they pop in octant order
-        const double hh = 0.5 * f.h;
-        for (int o = 7; o >= 0; --o) {
-            if (cnt[o] == 0)
-                continue;
-            Frame ch{off[o], off[o + 1],
-                     {f.c[0] + ((o & 1) ? hh : -hh), f.c[1] + ((o & 2) ? hh : -hh),
-                      f.c[2] + ((o & 4) ? hh : -hh)},
-                     hh, f.depth + 1};
-            stack.push_back(ch);
-        }
+    start.assign(1, 0);
+    std::vector<LeafFrame> kids;
+    std::vector<int32_t> ends;
+    split_frame(x, y, z, n0, root, perm.data(), tmp.data(), oct.data(), kids, ends);
+    if (kids.empty()) {
+        start.insert(start.end(), ends.begin(), ends.end());
+        return;
     }
+    std::vector<std::vector<int32_t>> sub(kids.size());
+    const bool threaded = n >= 16384;
+    std::vector<std::thread> pool;
+    for (size_t k = 0; k < kids.size(); ++k) {
+        auto job = [&, k] {
+            build_subtree(x, y, z, n0, kids[k], perm.data(), tmp.data(), oct.data(), sub[k]);
+        };
+        if (threaded)
+            pool.emplace_back(job);
+        else
+            job();
+    }
+    for (auto &t : pool)
+        t.join();
+    for (const auto &s : sub)
+        start.insert(start.end(), s.begin(), s.end());
 }
 
 }  // namespace pbk
@@ -344,23 +396,29 @@ int setup_precond(pb_ctx *c, const pb_params *p)
     if (p->precond_leaf <= 0)
         return PB_OK;
     const Geo &g = c->g;
-    std::vector<double> h(3 * g.n);
-    for (int k = 0; k < 3; ++k)
-        HIPCHK(hipMemcpyAsync(h.data() + k * g.n, g.g + k * g.npad, sizeof(double) * g.n,
-                              hipMemcpyDeviceToHost, c->stream));
+    // centroids x, y, z (3 npad doubles, one copy) into pinned staging
+    if (c->hgeo_n < (size_t)(3 * g.npad)) {
+        if (c->hgeo)
+            (void)hipHostFree(c->hgeo);
+        c->hgeo = nullptr;
+        c->hgeo_n = 0;
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->hgeo), sizeof(double) * 3 * g.npad,
+                          hipHostMallocDefault) != hipSuccess)
+            return fail(c, PB_ERR_OOM, "pinned host staging of %lld doubles",
+                        (long long)(3 * g.npad));
+        c->hgeo_n = (size_t)(3 * g.npad);
+    }
+    HIPCHK(hipMemcpyAsync(c->hgeo, g.g, sizeof(double) * 3 * g.npad, hipMemcpyDeviceToHost,
+                          c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     std::vector<int32_t> perm, start;
-    build_leaves(h.data(), h.data() + g.n, h.data() + 2 * g.n, g.n, p->precond_leaf, perm, start);
+    build_leaves(c->hgeo, c->hgeo + g.npad, c->hgeo + 2 * g.npad, g.n, p->precond_leaf, perm,
+                 start);
     const int64_t L = (int64_t)start.size() - 1;
     std::vector<int64_t> boff(L + 1, 0);
     for (int64_t l = 0; l < L; ++l) {
         const int64_t m2 = 2 * (int64_t)(start[l + 1] - start[l]);
         boff[l + 1] = boff[l] + m2 * m2;
-    }
-    std::vector<int64_t> pq(2 * g.n);
-    for (int64_t e = 0; e < g.n; ++e) {
-        pq[e] = perm[e];              // phi of the element
-        pq[g.n + e] = g.n + perm[e];  // psi of the element
     }
     const size_t off64 = round_up(sizeof(int32_t) * (g.n + L + 1), 8);
     TRY(ensure(c, c->pc_idx, off64 + sizeof(int64_t) * (L + 1 + 2 * g.n)));
@@ -375,8 +433,8 @@ int setup_precond(pb_ctx *c, const pb_params *p)
                           c->stream));
     HIPCHK(hipMemcpyAsync(dboff, boff.data(), sizeof(int64_t) * (L + 1), hipMemcpyHostToDevice,
                           c->stream));
-    HIPCHK(hipMemcpyAsync(dpq, pq.data(), sizeof(int64_t) * 2 * g.n, hipMemcpyHostToDevice,
-                          c->stream));
+    launch_pc_index(c->stream, dperm, g.n, dpq);   // phi and psi slots of each element
+    LAUNCHCHK();
     launch_pc_build(c->stream, g, dperm, dstart, dboff, L, p->eps_out / p->eps_in, p->kappa,
                     as<double>(c->pc_inv));
     LAUNCHCHK();
@@ -1004,6 +1062,8 @@ void pb_destroy(pb_ctx *c)
             (void)hipFree(b->p);
     if (c->hsmall)
         (void)hipHostFree(c->hsmall);
+    if (c->hgeo)
+        (void)hipHostFree(c->hgeo);
     for (hipEvent_t e : c->ev_pool)
         (void)hipEventDestroy(e);
     if (c->own_stream)

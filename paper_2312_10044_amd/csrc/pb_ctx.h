@@ -39,6 +39,8 @@ struct pb_ctx {
     pbk::DevBuf geo, geo_part, src64, src32, part, vec, V, small, dpart, chg_part, chg_per;
     pbk::DevBuf in_vert, in_tri, in_pos, in_q, io_x, io_y;
     double *hsmall = nullptr;   // pinned host staging, HSMALL doubles
+    double *hgeo = nullptr;     // pinned host staging of the centroids (leaf build)
+    size_t hgeo_n = 0;
     // kernel timing (pb_profile_*)
     struct Mark {
         hipEvent_t a, b;

@@ -148,6 +148,9 @@ void launch_force_finish(hipStream_t s, const double *part, int n_chunks, int64_
 // lstart[l]..lstart[l+1] the points of leaf l, boff[l] the offset of its
 // (2m)^2 inverse block in inv; pidx/qidx the vector positions of each
 // point's phi and psi unknowns.
+// pq[e] = perm[e], pq[n + e] = n + perm[e]: the phi and psi slots of the
+// elements in leaf order.
+void launch_pc_index(hipStream_t s, const int32_t *perm, int64_t n, int64_t *pq);
 void launch_pc_build(hipStream_t s, const Geo &geo, const int32_t *perm, const int32_t *lstart,
                      const int64_t *boff, int64_t n_leaves, double eps, double kappa, double *inv);
 void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, const int64_t *pidx,

@@ -692,7 +692,18 @@ __global__ __launch_bounds__(TPB) void k_force_finish(const double *__restrict__
 // on the leaf's indices (rows/columns [phi; psi] of the leaf) is assembled in
 // LDS and inverted in place by Gauss-Jordan elimination with partial (row)
 // pivoting; the inverse is stored row-major at inv + boff[leaf].  Applying
-// M^-1 is then one small dense matvec per leaf.
+// M^-1 is then one small dense matvec per leaf.  The index table pq holds the
+// phi and psi slots of the elements in leaf order.
+
+__global__ __launch_bounds__(TPB) void k_pc_index(const int32_t *__restrict__ perm, int64_t n,
+                                                  int64_t *__restrict__ pq)
+{
+    const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (e >= n)
+        return;
+    pq[e] = perm[e];
+    pq[n + e] = n + perm[e];
+}
 
 __global__ __launch_bounds__(TPB) void k_pc_build(const double *__restrict__ g, int64_t npad,
                                                   const int32_t *__restrict__ perm,
@@ -1248,6 +1259,11 @@ void launch_force_finish(hipStream_t s, const double *part, int n_chunks, int64_
     hipLaunchKernelGGL(k_force_finish, dim3(blocks_for(nc)), dim3(TPB), 0, s, part, n_chunks, nc,
                        ncpad, q, half_cu, inv4pi_eps_in, dpos, dq, per);
     hipLaunchKernelGGL(k_weighted_total, dim3(1), dim3(TPB), 0, s, per, q, nc, half_cu, out);
+}
+
+void launch_pc_index(hipStream_t s, const int32_t *perm, int64_t n, int64_t *pq)
+{
+    hipLaunchKernelGGL(k_pc_index, dim3(blocks_for(n)), dim3(TPB), 0, s, perm, n, pq);
 }
 
 void launch_pc_build(hipStream_t s, const Geo &geo, const int32_t *perm, const int32_t *lstart,
