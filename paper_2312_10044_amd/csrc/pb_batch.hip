@@ -1357,7 +1357,8 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
         gall.g = D.g;
         gall.n = P.gtot;
         gall.npad = P.gtot;   // array stride of the concatenated geometry
-        launch_pc_build(s, gall, D.pc_perm, D.pc_start, D.pc_boff, L, eps, kap, D.pc_inv);
+        launch_pc_build(s, gall, D.pc_perm, D.pc_start, D.pc_boff, L, p->precond_leaf, eps, kap,
+                        D.pc_inv);
         LAUNCHCHK();
         HIPCHK(hipStreamSynchronize(s));   // host index vectors go out of scope
         D.pc_leaves = L;

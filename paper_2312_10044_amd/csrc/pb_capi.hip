@@ -435,8 +435,8 @@ int setup_precond(pb_ctx *c, const pb_params *p)
                           c->stream));
     launch_pc_index(c->stream, dperm, g.n, dpq);   // phi and psi slots of each element
     LAUNCHCHK();
-    launch_pc_build(c->stream, g, dperm, dstart, dboff, L, p->eps_out / p->eps_in, p->kappa,
-                    as<double>(c->pc_inv));
+    launch_pc_build(c->stream, g, dperm, dstart, dboff, L, p->precond_leaf,
+                    p->eps_out / p->eps_in, p->kappa, as<double>(c->pc_inv));
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(c->stream));   // host vectors go out of scope
     c->pc_leaves = L;

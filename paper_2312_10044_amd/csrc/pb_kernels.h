@@ -152,7 +152,8 @@ void launch_force_finish(hipStream_t s, const double *part, int n_chunks, int64_
 // elements in leaf order.
 void launch_pc_index(hipStream_t s, const int32_t *perm, int64_t n, int64_t *pq);
 void launch_pc_build(hipStream_t s, const Geo &geo, const int32_t *perm, const int32_t *lstart,
-                     const int64_t *boff, int64_t n_leaves, double eps, double kappa, double *inv);
+                     const int64_t *boff, int64_t n_leaves, int max_leaf, double eps,
+                     double kappa, double *inv);
 void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, const int64_t *pidx,
                      const int64_t *qidx, const int32_t *lstart, int64_t n_leaves,
                      const double *x, int trans, double *y);

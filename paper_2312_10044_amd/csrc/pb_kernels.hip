@@ -705,33 +705,114 @@ __global__ __launch_bounds__(TPB) void k_pc_index(const int32_t *__restrict__ pe
     pq[n + e] = n + perm[e];
 }
 
-__global__ __launch_bounds__(TPB) void k_pc_build(const double *__restrict__ g, int64_t npad,
-                                                  const int32_t *__restrict__ perm,
-                                                  const int32_t *__restrict__ lstart,
-                                                  const int64_t *__restrict__ boff, double eps,
-                                                  double kappa, double *__restrict__ inv)
+// One wave per leaf: lane i holds row i of the 2m x 2m block in registers
+// (MM >= 2m columns, unrolled), the pivot of column k is the largest |A(i, k)|
+// over rows not yet used (wave argmax, ties to the lower row), and only the
+// scaled pivot row passes through LDS (a broadcast).  Rows are never moved:
+// lane piv[k] ends with row k of the in-place inverse of the row-permuted
+// block, so inverse(r, c) = A(piv[r], q[c]) with q the inverse permutation of
+// piv.
+constexpr int PC_LANES = 64;
+
+// Gauss-Jordan inversion of the 2m x 2m block held in LDS rows of stride LD
+// (lane i: row i in registers, W >= 2m columns unrolled); writes the inverse
+// row-major to out.
+template <int W, int LD>
+__device__ __forceinline__ void pc_invert(double *A, double *prow, int *piv, int *qinv, int m,
+                                          double eps, double *__restrict__ out)
 {
-    constexpr int MM = 2 * PC_MAX_LEAF;
+    const int lane = threadIdx.x, m2 = 2 * m;
+    const bool mine = lane < m2;
+    const double dg = lane < m ? 0.5 * (1.0 + eps) : 0.5 * (1.0 + 1.0 / eps);
+    double row[W];   // every index below is a compile-time constant
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+        row[c] = (mine && c < m2) ? A[lane * LD + c] + (c == lane ? dg : 0.0) : 0.0;
+    uint64_t used = 0;   // rows already chosen as pivots (the same in every lane)
+    for (int k = 0; k < m2; ++k) {
+        double ak = 0.0;
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+            ak = (c == k) ? row[c] : ak;
+        double v = (mine && !((used >> lane) & 1)) ? fabs(ak) : -1.0;
+        int idx = lane;
+#pragma unroll
+        for (int off = PC_LANES / 2; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(v, off, PC_LANES);
+            const int oi = __shfl_xor(idx, off, PC_LANES);
+            if (ov > v || (ov == v && oi < idx)) {
+                v = ov;
+                idx = oi;
+            }
+        }
+        const int p = idx;
+        used |= 1ull << p;
+        if (lane == p) {
+            const double pinv = 1.0 / ak;
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+                row[c] = (c == k) ? pinv : row[c] * pinv;
+                prow[c] = row[c];
+            }
+            piv[k] = p;
+        }
+        __syncthreads();
+        if (mine && lane != p) {
+            const double pinv = prow[k];
+#pragma unroll
+            for (int c = 0; c < W; ++c)
+                row[c] = (c == k) ? -ak * pinv : fma(-ak, prow[c], row[c]);
+        }
+        __syncthreads();
+    }
+    if (mine) {
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+            A[lane * LD + c] = row[c];
+        qinv[piv[lane]] = lane;
+    }
+    __syncthreads();
+    for (int e = lane; e < m2 * m2; e += PC_LANES) {
+        const int r = e / m2, c = e - r * m2;
+        out[e] = A[piv[r] * LD + qinv[c]];
+    }
+}
+
+template <int MM>
+__global__ __launch_bounds__(PC_LANES) void k_pc_build(const double *__restrict__ g,
+                                                       int64_t npad,
+                                                       const int32_t *__restrict__ perm,
+                                                       const int32_t *__restrict__ lstart,
+                                                       const int64_t *__restrict__ boff,
+                                                       double eps, double kappa,
+                                                       double *__restrict__ inv)
+{
     __shared__ double A[MM][MM + 1];
-    __shared__ double fcol[MM];
-    __shared__ int ipiv[MM];
-    __shared__ double pinv;
-    const int l = blockIdx.x;
+    __shared__ double prow[MM];
+    __shared__ double gp[7][MM / 2];   // the leaf's points: centroid, normal, area
+    __shared__ int piv[MM], qinv[MM];
+    const int l = blockIdx.x, lane = threadIdx.x;
     const int s0 = lstart[l];
     const int m = lstart[l + 1] - s0;
     const int m2 = 2 * m;
-    if (m < 1 || m > PC_MAX_LEAF)
+    if (m < 1 || m2 > MM)
         return;   // the host never builds such leaves; never overrun the LDS block
+    if (lane < m) {
+        const int64_t i = perm[s0 + lane];
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            gp[k][lane] = g[k * npad + i];
+    }
+    __syncthreads();
     const double epsm1 = eps - 1.0, ieps = 1.0 / eps, iepsm1 = 1.0 / eps - 1.0;
-    for (int e = threadIdx.x; e < m * m; e += TPB) {
-        const int r = e / m, q = e - r * m;
-        const int64_t i = perm[s0 + r], j = perm[s0 + q];
+    for (int e = lane; e < m * m; e += PC_LANES) {
+        const int r = e / m, q = e - r * m;   // rows and columns in leaf order
         double k1 = 0.0, k2 = 0.0, k3 = 0.0, k4 = 0.0;
-        if (i != j) {
-            const double dx = g[i] - g[j], dy = g[npad + i] - g[npad + j];
-            const double dz = g[2 * npad + i] - g[2 * npad + j];
-            const double nxi = g[3 * npad + i], nyi = g[4 * npad + i], nzi = g[5 * npad + i];
-            const double nxj = g[3 * npad + j], nyj = g[4 * npad + j], nzj = g[5 * npad + j];
+        if (r != q) {
+            const double dx = gp[0][r] - gp[0][q], dy = gp[1][r] - gp[1][q];
+            const double dz = gp[2][r] - gp[2][q];
+            const double nxi = gp[3][r], nyi = gp[4][r], nzi = gp[5][r];
+            const double nxj = gp[3][q], nyj = gp[4][q], nzj = gp[5][q];
             const double r2 = dx * dx + dy * dy + dz * dz;
             const double ir = rsqrt(r2);
             const double ir2 = ir * ir, u = ir2 * ir;
@@ -748,75 +829,26 @@ __global__ __launch_bounds__(TPB) void k_pc_build(const double *__restrict__ g, 
             k3 = fma(ieps, tm1, iepsm1) * cx * u;
             k4 = u * (tm1 * nn - cx * cy * h);
         }
-        const double aj = g[6 * npad + j] * INV_4PI;
+        const double aj = gp[6][q] * INV_4PI;
         A[r][q] = -k2 * aj;
         A[r][m + q] = -k1 * aj;
         A[m + r][q] = -k4 * aj;
         A[m + r][m + q] = -k3 * aj;
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < m; r += TPB) {
-        A[r][r] += 0.5 * (1.0 + eps);
-        A[m + r][m + r] += 0.5 * (1.0 + 1.0 / eps);
-    }
-    __syncthreads();
-    for (int k = 0; k < m2; ++k) {
-        if (threadIdx.x == 0) {
-            int p = k;
-            double best = fabs(A[k][k]);
-            for (int i = k + 1; i < m2; ++i) {
-                const double v = fabs(A[i][k]);
-                if (v > best) {
-                    best = v;
-                    p = i;
-                }
-            }
-            ipiv[k] = p;
-        }
-        __syncthreads();
-        const int p = ipiv[k];
-        if (p != k) {
-            for (int c = threadIdx.x; c < m2; c += TPB) {
-                const double t = A[k][c];
-                A[k][c] = A[p][c];
-                A[p][c] = t;
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            pinv = 1.0 / A[k][k];
-            A[k][k] = 1.0;
-        }
-        __syncthreads();
-        for (int c = threadIdx.x; c < m2; c += TPB)
-            A[k][c] *= pinv;
-        for (int i = threadIdx.x; i < m2; i += TPB)
-            fcol[i] = A[i][k];
-        __syncthreads();
-        for (int e = threadIdx.x; e < m2 * m2; e += TPB) {
-            const int i = e / m2, c = e - i * m2;
-            if (i == k)
-                continue;
-            const double base = (c == k) ? 0.0 : A[i][c];
-            A[i][c] = base - fcol[i] * A[k][c];
-        }
-        __syncthreads();
-    }
-    for (int k = m2 - 1; k >= 0; --k) {
-        const int p = ipiv[k];
-        if (p != k) {
-            for (int r = threadIdx.x; r < m2; r += TPB) {
-                const double t = A[r][k];
-                A[r][k] = A[r][p];
-                A[r][p] = t;
-            }
-        }
-        __syncthreads();
-    }
     double *out = inv + boff[l];
-    for (int e = threadIdx.x; e < m2 * m2; e += TPB) {
-        const int r = e / m2, c = e - r * m2;
-        out[e] = A[r][c];
+    // the unrolled width follows the leaf, not the bound
+    if (m2 <= 16)
+        pc_invert<16, MM + 1>(&A[0][0], prow, piv, qinv, m, eps, out);
+    else if constexpr (MM >= 32) {
+        if (m2 <= 32)
+            pc_invert<32, MM + 1>(&A[0][0], prow, piv, qinv, m, eps, out);
+        else if constexpr (MM >= 48) {
+            if (m2 <= 48)
+                pc_invert<48, MM + 1>(&A[0][0], prow, piv, qinv, m, eps, out);
+            else if constexpr (MM >= 64)
+                pc_invert<64, MM + 1>(&A[0][0], prow, piv, qinv, m, eps, out);
+        }
     }
 }
 
@@ -1267,10 +1299,23 @@ void launch_pc_index(hipStream_t s, const int32_t *perm, int64_t n, int64_t *pq)
 }
 
 void launch_pc_build(hipStream_t s, const Geo &geo, const int32_t *perm, const int32_t *lstart,
-                     const int64_t *boff, int64_t n_leaves, double eps, double kappa, double *inv)
+                     const int64_t *boff, int64_t n_leaves, int max_leaf, double eps,
+                     double kappa, double *inv)
 {
-    hipLaunchKernelGGL(k_pc_build, dim3((unsigned)n_leaves), dim3(TPB), 0, s, geo.g, geo.npad, perm,
-                       lstart, boff, eps, kappa, inv);
+    const int mm = 2 * std::min(std::max(max_leaf, 1), PC_MAX_LEAF);
+    const dim3 grid((unsigned)n_leaves), block(PC_LANES);
+    if (mm <= 16)
+        hipLaunchKernelGGL(k_pc_build<16>, grid, block, 0, s, geo.g, geo.npad, perm, lstart,
+                           boff, eps, kappa, inv);
+    else if (mm <= 32)
+        hipLaunchKernelGGL(k_pc_build<32>, grid, block, 0, s, geo.g, geo.npad, perm, lstart,
+                           boff, eps, kappa, inv);
+    else if (mm <= 48)
+        hipLaunchKernelGGL(k_pc_build<48>, grid, block, 0, s, geo.g, geo.npad, perm, lstart,
+                           boff, eps, kappa, inv);
+    else
+        hipLaunchKernelGGL(k_pc_build<64>, grid, block, 0, s, geo.g, geo.npad, perm, lstart,
+                           boff, eps, kappa, inv);
 }
 
 void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, const int64_t *pidx,
