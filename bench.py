@@ -135,6 +135,9 @@ def run_batch(args):
     leaf = args.precond_leaf
     prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
     pb = Params(tol=tol, precision=prec, restart=10, max_iter=2000, precond_leaf=leaf)
+    # tile shapes of the batched sweeps picked on this batch, outside the timing
+    tuned_kind, tuned_tiles = ctx.pb_autotune_batch(sys_list, pb)
+    _log(f"bench batch: autotuned sweep kind={tuned_kind} tiles/item={tuned_tiles}")
     e_b, inf_b, g_b, q_b = ctx.pb_solve_batch(sys_list, pb, forces=True)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -170,6 +173,7 @@ def run_batch(args):
         "precision": "FP32 matvec + FP64 restart residuals" if prec == PB_FP32_IR else "FP64",
         "precond_leaf": leaf,
         "tol": tol,
+        "autotuned": {"sweep_kind": sweep_label(tuned_kind), "tiles_per_item": tuned_tiles},
         "batched_s": t_batch,
         "batched_solves_per_s": len(systems) / t_batch,
         "sequential_fp64_same_preconditioner_s": t_seq,

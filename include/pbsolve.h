@@ -278,6 +278,23 @@ int pb_get_fp64_sweep(pb_ctx *ctx, int *kind);
 int pb_autotune(pb_ctx *ctx, const pb_surface *s, const pb_params *p, int *best_tpt,
                 int *best_waves);
 
+/* Batched solves (pb_solve_batch): the pairwise work items of the batched
+ * sweeps take `tiles` source tiles (of 256 points) each; shorter items spread
+ * the uneven systems over more blocks, longer ones reuse each target tile's
+ * registers longer.  0 leaves the value unchanged; default 16. */
+int pb_set_batch_tiles(pb_ctx *ctx, int tiles);
+int pb_get_batch_tiles(pb_ctx *ctx, int *tiles);
+/* Autotuner of the batched sweeps: on this batch (validated and laid out as by
+ * pb_solve_batch, nothing solved), times the batched FP32 forward sweep over
+ * all systems with HIP events, one warm-up and three timed launches per
+ * candidate, for the pairwise kind with 4, 8, 16 and 32 source tiles per work
+ * item and for the per-target kind, and keeps the fastest in the context:
+ * the sweep kind as by pb_set_sweep_config, the tiles as by
+ * pb_set_batch_tiles.  best_* may be NULL.  Same errors as pb_solve_batch. */
+int pb_autotune_batch(pb_ctx *ctx, int32_t n_sys, const pb_surface *surfaces,
+                      const pb_charges *charges, const pb_params *p, int *best_kind,
+                      int *best_tiles);
+
 /* ---- kernel timing hook (benchmarks, profiling) ------------------------ */
 /* When enabled, every launch of the kernels below is bracketed by a pair of
  * HIP events recorded on the context's stream; elapsed times are collected

@@ -64,7 +64,7 @@ struct SItem {
     int32_t sys, I, J0, J1, slot, pad0, pad1, pad2;
 };
 
-constexpr int SYM_TILES = 16;                 // source tiles per pairwise work item
+constexpr int SYM_TILES = 16;                 // default source tiles per pairwise work item
 
 struct GState {
     double H[(BM_MAX + 1) * BM_MAX];
@@ -851,7 +851,35 @@ struct BatchPlan {
     int64_t n_slots = 0, cptot = 0;
 };
 
-void plan_batch(BatchPlan &P, int n_sys, const pb_surface *surf, const pb_charges *chg)
+// Pairwise work items: row tile I of every system against its tiles I.. in
+// runs of `tiles` source tiles, longest first; rebuilt when the autotuner
+// tries another run length (the tile-pair records do not depend on it).
+void plan_sym_items(BatchPlan &P, int tiles)
+{
+    P.sitems.clear();
+    P.rs.clear();
+    P.n_slots = 0;
+    for (int b = 0; b < P.n_sys; ++b) {
+        SysDesc &d = P.sd[b];
+        const int nt = d.T;
+        d.rs0 = (int32_t)P.rs.size();
+        for (int I = 0; I < nt; ++I) {
+            P.rs.push_back((int32_t)P.n_slots);
+            for (int J0 = I; J0 < nt; J0 += tiles) {
+                P.sitems.push_back({b, I, J0, std::min(nt, J0 + tiles), (int32_t)P.n_slots, 0,
+                                    0, 0});
+                ++P.n_slots;
+            }
+        }
+        P.rs.push_back((int32_t)P.n_slots);
+    }
+    std::stable_sort(P.sitems.begin(), P.sitems.end(), [](const SItem &a, const SItem &b) {
+        return a.J1 - a.J0 > b.J1 - b.J0;
+    });
+}
+
+void plan_batch(BatchPlan &P, int n_sys, const pb_surface *surf, const pb_charges *chg,
+                int sym_tiles)
 {
     P.n_sys = n_sys;
     P.sd.resize(n_sys);
@@ -892,24 +920,12 @@ void plan_batch(BatchPlan &P, int n_sys, const pb_surface *surf, const pb_charge
             P.vblk2sys.push_back(b);
         for (int64_t k = 0; k < d.ncpad / TPB; ++k)
             P.cblk2sys.push_back(b);
-        // pairwise items: row I against tiles I.. in runs of SYM_TILES
+        // pairwise sweeps: T tiles, row-slot table at rs0, tile pairs at cp0
         d.T = nt;
-        d.rs0 = (int32_t)P.rs.size();
         d.cp0 = P.cptot;
         P.cptot += (int64_t)nt * (nt - 1) / 2;
-        for (int I = 0; I < nt; ++I) {
-            P.rs.push_back((int32_t)P.n_slots);
-            for (int J0 = I; J0 < nt; J0 += SYM_TILES) {
-                P.sitems.push_back({b, I, J0, std::min(nt, J0 + SYM_TILES),
-                                    (int32_t)P.n_slots, 0, 0, 0});
-                ++P.n_slots;
-            }
-        }
-        P.rs.push_back((int32_t)P.n_slots);
     }
-    std::stable_sort(P.sitems.begin(), P.sitems.end(), [](const SItem &a, const SItem &b) {
-        return a.J1 - a.J0 > b.J1 - b.J0;
-    });
+    plan_sym_items(P, sym_tiles);
 }
 
 struct BatchDev {
@@ -1166,13 +1182,85 @@ int upload(pb_ctx *c, void *dst, const void *src, size_t bytes)
     return PB_OK;
 }
 
+// Batched FP32 forward sweep over all systems timed for each candidate
+// configuration (HIP events, one warm-up and three timed launches each); the
+// fastest is kept in the context.
+int batch_tune_run(pb_ctx *c, BatchPlan &P, BatchDev &D, const pb_params *p, BatchTune &tn)
+{
+    hipStream_t s = c->stream;
+    const int ns = P.n_sys;
+    const double eps = p->eps_out / p->eps_in, kap = p->kappa;
+    {
+        std::vector<int32_t> ones(ns, 1);
+        TRY(upload(c, D.mask_step, ones.data(), sizeof(int32_t) * ns));
+    }
+    hipLaunchKernelGGL(kb_fill, dim3((unsigned)D.nvb), dim3(TPB), 0, s, D.x, 1.0);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));
+    const int kind0 = c->f32_tpt, tiles0 = c->b_sym_tiles;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = -1;
+    int rc = PB_OK;
+    for (int k = 0; k < tn.n && rc == PB_OK; ++k) {
+        c->f32_tpt = tn.kind[k];
+        if (tn.kind[k] == PB_SWEEP_PAIRWISE) {
+            plan_sym_items(P, tn.tiles[k]);
+            rc = ensure(c, c->b_sitems, sizeof(SItem) * std::max<size_t>(P.sitems.size(), 1));
+            if (rc == PB_OK)
+                rc = ensure(c, c->b_srow,
+                            sizeof(double) * 2 * TILE * std::max<int64_t>(P.n_slots, 1));
+            if (rc != PB_OK)
+                break;
+            D.sitems = as<SItem>(c->b_sitems);
+            D.srow = as<double>(c->b_srow);
+            if (hipMemcpyAsync(D.sitems, P.sitems.data(), sizeof(SItem) * P.sitems.size(),
+                               hipMemcpyHostToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(D.rs, P.rs.data(), sizeof(int32_t) * P.rs.size(),
+                               hipMemcpyHostToDevice, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                rc = fail(c, PB_ERR_HIP, "autotune upload failed");
+                break;
+            }
+        }
+        enqueue_matvec(c, P, D, true, 0, D.mask_step, eps, kap, D.x, D.w);
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 3; ++r)
+            enqueue_matvec(c, P, D, true, 0, D.mask_step, eps, kap, D.x, D.w);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(c, PB_ERR_HIP, "autotune launch failed: %s",
+                      hipGetErrorString(hipGetLastError()));
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        tn.ms[k] = ms / 3.0;
+        if (best < 0 || tn.ms[k] < tn.ms[best])
+            best = k;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != PB_OK || best < 0) {
+        c->f32_tpt = kind0;
+        c->b_sym_tiles = tiles0;
+        return rc != PB_OK ? rc : fail(c, PB_ERR_ARG, "no autotune candidate");
+    }
+    c->f32_tpt = tn.kind[best];
+    if (tn.kind[best] == PB_SWEEP_PAIRWISE)
+        c->b_sym_tiles = tn.tiles[best];
+    tn.best = best;
+    return PB_OK;
+}
+
 }  // namespace
 
 int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
                 const pb_params *p, int want_forces, double *e_solv, double *dE_dpos,
-                double *dE_dq, pb_info *info)
+                double *dE_dq, pb_info *info, BatchTune *tune)
 {
-    if (n_sys < 1 || !surf || !chg || !e_solv)
+    if (n_sys < 1 || !surf || !chg || (!e_solv && !tune))
         return fail(c, PB_ERR_ARG, "batch needs n_sys >= 1, surfaces, charges and e_solv");
     if (p->restart > BM_MAX)
         return fail(c, PB_ERR_ARG, "batched solves support restart <= %d", BM_MAX);
@@ -1186,7 +1274,7 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     }
     hipStream_t s = c->stream;
     BatchPlan P;
-    plan_batch(P, n_sys, surf, chg);
+    plan_batch(P, n_sys, surf, chg, c->b_sym_tiles);
     BatchDev D;
     D.grid_s32 = resident_blocks(kb_pairs_f32_sym<true>, SYM_NT);
     D.grid_s64 = resident_blocks(kb_pairs_f64_sym<false>, SYM64_NT);
@@ -1307,6 +1395,8 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
         TRY(upload(c, D.rs, P.rs.data(), sizeof(int32_t) * P.rs.size()));
         HIPCHK(hipStreamSynchronize(s));   // host staging vectors go out of scope
     }
+    if (tune)
+        return batch_tune_run(c, P, D, p, *tune);
     const double eps = p->eps_out / p->eps_in, kap = p->kappa;
     const unsigned gb = nblk(P.gtot), vb = (unsigned)D.nvb, cbk = nblk(P.ctot);
     // preconditioned vectors: the apply writes real entries only, so the

@@ -1675,6 +1675,53 @@ int pb_solve_batch(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_ch
     return leave(c, pb_solve_batch_impl(c, n_sys, surf, chg, p, e_solv, dE_dpos, dE_dq, info));
 }
 
+static int pb_autotune_batch_impl(pb_ctx *c, int32_t n_sys, const pb_surface *surf,
+                                  const pb_charges *chg, const pb_params *p, int *best_kind,
+                                  int *best_tiles)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, true));
+    BatchTune tn;
+    const int tiles[] = {4, 8, 16, 32};
+    for (int t : tiles) {
+        tn.kind[tn.n] = PB_SWEEP_PAIRWISE;
+        tn.tiles[tn.n++] = t;
+    }
+    tn.kind[tn.n] = 1;   // per-target sweep
+    tn.tiles[tn.n++] = 0;
+    TRY(batch_solve(c, n_sys, surf, chg, p, 0, nullptr, nullptr, nullptr, nullptr, &tn));
+    if (best_kind)
+        *best_kind = c->f32_tpt;
+    if (best_tiles)
+        *best_tiles = c->b_sym_tiles;
+    return PB_OK;
+}
+
+int pb_autotune_batch(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
+                      const pb_params *p, int *best_kind, int *best_tiles)
+{
+    return leave(c, pb_autotune_batch_impl(c, n_sys, surf, chg, p, best_kind, best_tiles));
+}
+
+int pb_set_batch_tiles(pb_ctx *c, int tiles)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    if (tiles < 0 || tiles > 1024)
+        return fail(c, PB_ERR_ARG, "batch tiles per item must be in [1, 1024] (0: unchanged)");
+    if (tiles > 0)
+        c->b_sym_tiles = tiles;
+    return PB_OK;
+}
+
+int pb_get_batch_tiles(pb_ctx *c, int *tiles)
+{
+    if (!c || !tiles)
+        return PB_ERR_ARG;
+    *tiles = c->b_sym_tiles;
+    return PB_OK;
+}
+
 int pb_profile_enable(pb_ctx *c, int enable)
 {
     if (!c)

@@ -59,6 +59,7 @@ struct pb_ctx {
     // pairwise sweep: packed points, work items and partial sums (plan cached)
     pbk::DevBuf sym_src, sym_src64, sym_items, sym_rowstart, sym_rowpart, sym_colpart;
     int f64_kind = PB_SWEEP_PAIRWISE;   // FP64 sweep: 1 per-target, or pairwise
+    int b_sym_tiles = 16;                // batch: source tiles per pairwise work item
     pbk::SymPlan sym_plan;
     int sym_waves = 0;
     // treecode: tree, permuted geometry and weights, moments, results
@@ -211,8 +212,15 @@ int tree_matvec(pb_ctx *c, const pb_params *p, double theta, int order, int n0, 
 int tree_prepare(pb_ctx *c, int n0);
 int tree_apply(pb_ctx *c, const pb_params *p, double theta, int order, const double *x,
                double *y, int64_t *counts);
+// Candidate configurations of the batch autotuner and their timings.
+struct BatchTune {
+    int n = 0;
+    int kind[8] = {0}, tiles[8] = {0};
+    double ms[8] = {0.0};
+    int best = -1;
+};
 int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
                 const pb_params *p, int want_forces, double *e_solv, double *dE_dpos,
-                double *dE_dq, pb_info *info);
+                double *dE_dq, pb_info *info, BatchTune *tune = nullptr);
 
 }  // namespace pbk

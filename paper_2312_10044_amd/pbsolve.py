@@ -108,6 +108,11 @@ _PROTOS = {
     "pb_get_sweep_config": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
     "pb_autotune": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Params),
                            ctypes.POINTER(_int), ctypes.POINTER(_int)]),
+    "pb_autotune_batch": (_int, [_vp, ctypes.c_int32, ctypes.POINTER(_Surface),
+                                 ctypes.POINTER(_Charges), ctypes.POINTER(_Params),
+                                 ctypes.POINTER(_int), ctypes.POINTER(_int)]),
+    "pb_set_batch_tiles": (_int, [_vp, _int]),
+    "pb_get_batch_tiles": (_int, [_vp, ctypes.POINTER(_int)]),
     "pb_profile_enable": (_int, [_vp, _int]),
     "pb_profile_reset": (_int, [_vp]),
     "pb_profile_read": (_int, [_vp, _int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
@@ -338,9 +343,7 @@ class Context:
                                       ctypes.byref(info)))
         return Info.of(info), gpos, gq
 
-    def pb_solve_batch(self, systems, params: Params, forces: bool = False):
-        """systems: list of (verts, tris, pos, q).  Returns (e [n_sys], infos,
-        dE_dpos [sum n_b, 3] or None, dE_dq [sum n_b] or None)."""
+    def _batch_args(self, systems):
         n = len(systems)
         surfs = (_Surface * n)()
         chgs = (_Charges * n)()
@@ -353,6 +356,31 @@ class Context:
             chgs[b] = c
             keep += [k1, k2]
             nct += c.n
+        return n, surfs, chgs, keep, nct
+
+    def pb_autotune_batch(self, systems, params: Params):
+        """Time the batched FP32 sweep configurations on this batch and keep
+        the fastest; returns (sweep kind, source tiles per work item)."""
+        n, surfs, chgs, keep, _nct = self._batch_args(systems)
+        p = params.c()
+        kind, tiles = _int(0), _int(0)
+        self._check(self._L.pb_autotune_batch(self._h, n, surfs, chgs, ctypes.byref(p),
+                                              ctypes.byref(kind), ctypes.byref(tiles)))
+        return int(kind.value), int(tiles.value)
+
+    def set_batch_tiles(self, tiles: int = 0):
+        """Source tiles per pairwise work item of the batched sweeps; 0 keeps it."""
+        self._check(self._L.pb_set_batch_tiles(self._h, int(tiles)))
+
+    def get_batch_tiles(self) -> int:
+        t = _int(0)
+        self._check(self._L.pb_get_batch_tiles(self._h, ctypes.byref(t)))
+        return int(t.value)
+
+    def pb_solve_batch(self, systems, params: Params, forces: bool = False):
+        """systems: list of (verts, tris, pos, q).  Returns (e [n_sys], infos,
+        dE_dpos [sum n_b, 3] or None, dE_dq [sum n_b] or None)."""
+        n, surfs, chgs, keep, nct = self._batch_args(systems)
         e = np.empty(n)
         infos = (_Info * n)()
         gpos = np.empty((nct, 3)) if forces else None

@@ -150,3 +150,33 @@ def test_batch_sweep_kinds_agree(pb, small_batch):
     assert np.abs(q_pw - q_pt).max() <= 1e-8 * np.abs(q_pt).max()
     assert np.max(np.abs(e32_pw - e_pt) / np.abs(e_pt)) <= 1e-6
     assert np.max(np.abs(e32_pt - e_pt) / np.abs(e_pt)) <= 1e-6
+
+
+def test_batch_autotune_and_item_lengths(pb, small_batch):
+    """The batch autotuner keeps one of its candidates in the context; batched
+    solves agree across pairwise item lengths (FP64 to rounding) and after
+    tuning (refined FP32 within 1e-6 of FP64)."""
+    m, ctx = pb
+    P64 = m.Params(tol=1e-12, precond_leaf=16)
+    P32 = m.Params(tol=1e-8, precision=m.PB_FP32_IR, precond_leaf=16)
+    try:
+        e_ref = None
+        for tiles in (1, 4, 32):
+            ctx.set_batch_tiles(tiles)
+            assert ctx.get_batch_tiles() == tiles
+            e, _i, _g, _q = ctx.pb_solve_batch(small_batch, P64)
+            _say(f"batch tiles={tiles}: E[0]={e[0]:.12f}")
+            if e_ref is None:
+                e_ref = e
+            assert np.max(np.abs(e - e_ref) / np.abs(e_ref)) <= 1e-10
+        kind, tiles = ctx.pb_autotune_batch(small_batch, P32)
+        _say(f"batch autotune: kind={kind} tiles={tiles}")
+        assert (kind, tiles) in {(m.PB_SWEEP_PAIRWISE, t) for t in (4, 8, 16, 32)} or kind == 1
+        assert ctx.get_sweep_config()[0] == kind
+        if kind == m.PB_SWEEP_PAIRWISE:
+            assert ctx.get_batch_tiles() == tiles
+        e32, _i, _g, _q = ctx.pb_solve_batch(small_batch, P32)
+        assert np.max(np.abs(e32 - e_ref) / np.abs(e_ref)) <= 1e-6
+    finally:
+        ctx.set_batch_tiles(16)
+        ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 0)
