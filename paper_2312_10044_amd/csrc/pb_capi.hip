@@ -389,8 +389,11 @@ void build_leaves(const double *x, const double *y, const double *z, int64_t n, 
 
 namespace {
 
-// Leaves of the current geometry and the inverses of their blocks.
-int setup_precond(pb_ctx *c, const pb_params *p)
+// Leaves of the current geometry and the inverses of their blocks, in two
+// halves: precond_fetch enqueues the copy of the centroids to the host (the
+// caller may enqueue more GPU work behind it), precond_finish builds the
+// leaves on the host as soon as the copy has landed and inverts the blocks.
+int precond_fetch(pb_ctx *c, const pb_params *p)
 {
     c->pc_leaves = 0;
     if (p->precond_leaf <= 0)
@@ -410,7 +413,18 @@ int setup_precond(pb_ctx *c, const pb_params *p)
     }
     HIPCHK(hipMemcpyAsync(c->hgeo, g.g, sizeof(double) * 3 * g.npad, hipMemcpyDeviceToHost,
                           c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    if (!c->ev_fetch)
+        HIPCHK(hipEventCreateWithFlags(&c->ev_fetch, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(c->ev_fetch, c->stream));
+    return PB_OK;
+}
+
+int precond_finish(pb_ctx *c, const pb_params *p)
+{
+    if (p->precond_leaf <= 0)
+        return PB_OK;
+    const Geo &g = c->g;
+    HIPCHK(hipEventSynchronize(c->ev_fetch));
     std::vector<int32_t> perm, start;
     build_leaves(c->hgeo, c->hgeo + g.npad, c->hgeo + 2 * g.npad, g.n, p->precond_leaf, perm,
                  start);
@@ -446,6 +460,12 @@ int setup_precond(pb_ctx *c, const pb_params *p)
     c->pc_pidx = dpq;
     c->pc_qidx = dpq + g.n;
     return PB_OK;
+}
+
+int setup_precond(pb_ctx *c, const pb_params *p)
+{
+    TRY(precond_fetch(c, p));
+    return precond_finish(c, p);
 }
 
 int pc_apply(pb_ctx *c, int transpose, const double *x, double *y)
@@ -681,7 +701,10 @@ int gmres(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
 
 // ---- charges: inside check, sources (step 2), energy (step 5) -----------------
 
-int check_charges_inside(pb_ctx *c, const pb_params *p, int64_t nc, const double *d_pos,
+// Discrete solid angle of the surface at every charge (one N x Nc sweep with
+// unit potential and zero flux); the result is copied to pinned staging and
+// judged by charges_inside_verdict after the stream drains.
+int launch_charges_inside(pb_ctx *c, const pb_params *p, int64_t nc, const double *d_pos,
                          Vecs &v)
 {
     const Geo &g = c->g;
@@ -706,10 +729,25 @@ int check_charges_inside(pb_ctx *c, const pb_params *p, int64_t nc, const double
     launch_charge_finish(c->stream, as<double>(c->chg_part), sw.n_chunks, nc, ncpad, nullptr,
                          1.0, as<double>(c->chg_per), nullptr);
     LAUNCHCHK();
-    std::vector<double> omega(nc);
-    HIPCHK(hipMemcpyAsync(omega.data(), c->chg_per.p, sizeof(double) * nc, hipMemcpyDeviceToHost,
+    if (c->hchg_n < (size_t)nc) {
+        if (c->hchg)
+            (void)hipHostFree(c->hchg);
+        c->hchg = nullptr;
+        c->hchg_n = 0;
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->hchg), sizeof(double) * nc,
+                          hipHostMallocDefault) != hipSuccess)
+            return fail(c, PB_ERR_OOM, "pinned host staging of %lld doubles", (long long)nc);
+        c->hchg_n = (size_t)nc;
+    }
+    HIPCHK(hipMemcpyAsync(c->hchg, c->chg_per.p, sizeof(double) * nc, hipMemcpyDeviceToHost,
                           c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    return PB_OK;
+}
+
+// The verdict of launch_charges_inside, once the stream has drained.
+int charges_inside_verdict(pb_ctx *c, int64_t nc)
+{
+    const double *omega = c->hchg;
     for (int64_t k = 0; k < nc; ++k) {
         // discrete solid angle: ~4 pi inside, ~0 outside
         if (!(omega[k] >= TWO_PI))
@@ -841,13 +879,18 @@ int forward_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
     TRY(check_charges_args(c, nc, d_pos, d_q));
     TRY(setup_geometry(c, n_vert, n_tri, d_vert, d_tri));
     TRY(setup_vectors(c, p->restart, v));
-    TRY(check_charges_inside(c, p, nc, d_pos, v));
-    TRY(setup_precond(c, p));
+    // The centroid copy goes first; the charge check and the sources run on
+    // the device while the host builds the preconditioner's leaves.
+    TRY(precond_fetch(c, p));
+    TRY(launch_charges_inside(c, p, nc, d_pos, v));
     {
         ProfScope ps(c, PB_KERNEL_SOURCE, (double)c->g.n * (double)nc);
         launch_source(c->stream, c->g, nc, d_pos, d_q, p->eps_in, v.b);
     }
     LAUNCHCHK();
+    TRY(precond_finish(c, p));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    TRY(charges_inside_verdict(c, nc));
     TRY(solve_system(c, p, 0, v.b, v.x, v, ss));
     return PB_OK;
 }
@@ -1064,6 +1107,10 @@ void pb_destroy(pb_ctx *c)
         (void)hipHostFree(c->hsmall);
     if (c->hgeo)
         (void)hipHostFree(c->hgeo);
+    if (c->hchg)
+        (void)hipHostFree(c->hchg);
+    if (c->ev_fetch)
+        (void)hipEventDestroy(c->ev_fetch);
     for (hipEvent_t e : c->ev_pool)
         (void)hipEventDestroy(e);
     if (c->own_stream)

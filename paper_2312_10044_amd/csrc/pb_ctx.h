@@ -41,6 +41,9 @@ struct pb_ctx {
     double *hsmall = nullptr;   // pinned host staging, HSMALL doubles
     double *hgeo = nullptr;     // pinned host staging of the centroids (leaf build)
     size_t hgeo_n = 0;
+    double *hchg = nullptr;     // pinned host staging of the charges' solid angles
+    size_t hchg_n = 0;
+    hipEvent_t ev_fetch = nullptr;   // marks the centroid copy for the leaf build
     // kernel timing (pb_profile_*)
     struct Mark {
         hipEvent_t a, b;
