@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -58,9 +59,18 @@ def sweep_label(kind: int) -> str:
     return "pairwise" if kind == PAIRWISE else f"per-target, {kind} targets per thread"
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace runs collapsed, so
+    that the digest follows the code and not its commentary."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_digest(kind: int) -> str:
-    """SHA-256 of the FP32 forward sweep's source: the shared device header
-    plus the text of the sweep kernel that `kind` selects."""
+    """SHA-256 of the FP32 forward sweep's code (comments and layout
+    stripped): the shared device header plus the text of the sweep kernel
+    that `kind` selects."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2312_10044_amd", "csrc")
     dev = open(os.path.join(csrc, "pb_device.h")).read()
@@ -69,7 +79,7 @@ def kernel_digest(kind: int) -> str:
     b0 = ker.index(f" void {name}(")
     a = ker.rindex("template <", 0, b0)
     b = ker.index("\n}\n", b0) + 3
-    return hashlib.sha256((dev + ker[a:b]).encode()).hexdigest()
+    return hashlib.sha256(_code_only(dev + ker[a:b]).encode()).hexdigest()
 
 
 def measured_traffic(n_tri, sweep):

@@ -632,8 +632,8 @@ __device__ __forceinline__ void sweep_pairwise64(const Src8d *sh, const OwnF64 (
 // Target tile I of a system whose points start at `src` (T tiles), against its
 // source tiles J0..J1-1 (J0 >= I; the tile J = I runs forward only).  Row sums
 // go to rp[0..TILE) and rp[TILE..2 TILE), the contributions of tile pair
-// (I, J) to the rows of tile J to cp_base + pair_index(I, J) * 2 TILE.  Block
-// of TPB threads; sh and colw are the block's LDS.
+// (I, J) to the rows of tile J to cp_base + pair_index(I, J) * 2 TILE.  Blocks
+// of SYM_NT (FP32) or SYM64_NT (FP64) threads; sh and colw are the block's LDS.
 
 // FP32: blocks of TILE / SYM_TT threads, each thread owning SYM_TT targets
 // (k * TILE / SYM_TT + threadIdx.x), so that every column reduction serves
