@@ -15,6 +15,9 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <new>
+#include <stdexcept>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -374,9 +377,16 @@ void build_leaves(const double *x, const double *y, const double *z, int64_t n, 
         auto job = [&, k] {
             build_subtree(x, y, z, n0, kids[k], perm.data(), tmp.data(), oct.data(), sub[k]);
         };
-        if (threaded)
-            pool.emplace_back(job);
-        else
+        bool spawned = false;
+        if (threaded) {
+            try {
+                pool.emplace_back(job);
+                spawned = true;
+            } catch (const std::system_error &) {
+                // no thread available: build this subtree here
+            }
+        }
+        if (!spawned)
             job();
     }
     for (auto &t : pool)
@@ -1025,6 +1035,22 @@ int enter(pb_ctx *c)
 
 // Every entry point returns through here: drain the stream and fold the
 // recorded kernel timings in, whatever the status.
+// Runs an entry point's body; no exception crosses the C ABI (host
+// allocations, thread creation): they become status codes.
+template <typename F>
+int guarded(pb_ctx *c, F &&body)
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return c ? fail(c, PB_ERR_OOM, "host memory exhausted") : PB_ERR_OOM;
+    } catch (const std::exception &e) {
+        return c ? fail(c, PB_ERR_HIP, "host error: %s", e.what()) : PB_ERR_HIP;
+    } catch (...) {
+        return c ? fail(c, PB_ERR_HIP, "host error") : PB_ERR_HIP;
+    }
+}
+
 int leave(pb_ctx *c, int st)
 {
     if (c && !c->marks.empty()) {
@@ -1367,63 +1393,75 @@ static int pb_solve_dev_impl(pb_ctx *c, int64_t n_vert, int64_t n_tri, const dou
 
 int pb_geometry(pb_ctx *c, const pb_surface *s, double *cen, double *nrm, double *area)
 {
-    return leave(c, pb_geometry_impl(c, s, cen, nrm, area));
+    return leave(c, guarded(c, [&] { return pb_geometry_impl(c, s, cen, nrm, area); }));
 }
 
 int pb_source(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p, double *b)
 {
-    return leave(c, pb_source_impl(c, s, q, p, b));
+    return leave(c, guarded(c, [&] { return pb_source_impl(c, s, q, p, b); }));
 }
 
 int pb_matvec(pb_ctx *c, const pb_surface *s, const pb_params *p, const double *x, double *y,
               int transpose, int precision)
 {
-    return leave(c, pb_matvec_impl(c, s, p, x, y, transpose, precision));
+    return leave(c, guarded(c, [&] {
+        return pb_matvec_impl(c, s, p, x, y, transpose, precision);
+    }));
 }
 
 int pb_solve_tree(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
                   double theta, int order, int leaf_size, double *phi, double *dphi,
                   pb_info *info)
 {
-    return leave(c, pb_solve_tree_impl(c, s, q, p, theta, order, leaf_size, phi, dphi, info));
+    return leave(c, guarded(c, [&] {
+        return pb_solve_tree_impl(c, s, q, p, theta, order, leaf_size, phi, dphi, info);
+    }));
 }
 
 int pb_matvec_tree(pb_ctx *c, const pb_surface *s, const pb_params *p, double theta, int order,
                    int leaf_size, const double *x, double *y, int64_t *counts)
 {
-    return leave(c, pb_matvec_tree_impl(c, s, p, theta, order, leaf_size, x, y, counts));
+    return leave(c, guarded(c, [&] {
+        return pb_matvec_tree_impl(c, s, p, theta, order, leaf_size, x, y, counts);
+    }));
 }
 
 int pb_matvec_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
                   const int32_t *d_tri, const pb_params *p, const double *d_x, double *d_y,
                   int transpose, int precision)
 {
-    return leave(c, pb_matvec_dev_impl(c, n_vert, n_tri, d_vert, d_tri, p, d_x, d_y, transpose, precision));
+    return leave(c, guarded(c, [&] {
+        return pb_matvec_dev_impl(c, n_vert, n_tri, d_vert, d_tri, p, d_x, d_y, transpose,
+                                  precision);
+    }));
 }
 
 int pb_energy(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
               const double *phi, const double *dphi, double *e_solv)
 {
-    return leave(c, pb_energy_impl(c, s, q, p, phi, dphi, e_solv));
+    return leave(c, guarded(c, [&] { return pb_energy_impl(c, s, q, p, phi, dphi, e_solv); }));
 }
 
 int pb_solve(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
              double *phi, double *dphi, pb_info *info)
 {
-    return leave(c, pb_solve_impl(c, s, q, p, phi, dphi, info));
+    return leave(c, guarded(c, [&] { return pb_solve_impl(c, s, q, p, phi, dphi, info); }));
 }
 
 int pb_solve_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
                  const int32_t *d_tri, int64_t n_charges, const double *d_pos, const double *d_q,
                  const pb_params *p, double *d_phi, double *d_dphi, pb_info *info)
 {
-    return leave(c, pb_solve_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p, d_phi, d_dphi, info));
+    return leave(c, guarded(c, [&] {
+        return pb_solve_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p, d_phi,
+                                 d_dphi, info);
+    }));
 }
 
 int pb_forces(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
               double *dE_dpos, double *dE_dq, pb_info *info)
 {
-    return leave(c, pb_forces_impl(c, s, q, p, dE_dpos, dE_dq, info));
+    return leave(c, guarded(c, [&] { return pb_forces_impl(c, s, q, p, dE_dpos, dE_dq, info); }));
 }
 
 int pb_forces_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
@@ -1431,8 +1469,10 @@ int pb_forces_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert
                   const double *d_q, const pb_params *p, double *d_dE_dpos, double *d_dE_dq,
                   pb_info *info)
 {
-    return leave(c, pb_forces_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p,
-                                       d_dE_dpos, d_dE_dq, info));
+    return leave(c, guarded(c, [&] {
+        return pb_forces_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p,
+                                  d_dE_dpos, d_dE_dq, info);
+    }));
 }
 
 static int pb_potential_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q,
@@ -1518,12 +1558,14 @@ int pb_potential(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_p
                  const double *phi, const double *dphi, int64_t n_points, const double *points,
                  double *reaction, double *total)
 {
-    return leave(c, pb_potential_impl(c, s, q, p, phi, dphi, n_points, points, reaction, total));
+    return leave(c, guarded(c, [&] {
+        return pb_potential_impl(c, s, q, p, phi, dphi, n_points, points, reaction, total);
+    }));
 }
 
 int pb_coulomb_energy(pb_ctx *c, const pb_charges *q, const pb_params *p, double *e_coul)
 {
-    return leave(c, pb_coulomb_energy_impl(c, q, p, e_coul));
+    return leave(c, guarded(c, [&] { return pb_coulomb_energy_impl(c, q, p, e_coul); }));
 }
 
 static int pb_precond_leaves_impl(pb_ctx *c, const pb_surface *s, int leaf, int32_t *perm,
@@ -1580,13 +1622,15 @@ static int pb_precond_apply_impl(pb_ctx *c, const pb_surface *s, const pb_params
 int pb_precond_leaves(pb_ctx *c, const pb_surface *s, int leaf, int32_t *perm,
                       int32_t *leaf_start, int64_t *n_leaves)
 {
-    return leave(c, pb_precond_leaves_impl(c, s, leaf, perm, leaf_start, n_leaves));
+    return leave(c, guarded(c, [&] {
+        return pb_precond_leaves_impl(c, s, leaf, perm, leaf_start, n_leaves);
+    }));
 }
 
 int pb_precond_apply(pb_ctx *c, const pb_surface *s, const pb_params *p, const double *x,
                      double *y, int transpose)
 {
-    return leave(c, pb_precond_apply_impl(c, s, p, x, y, transpose));
+    return leave(c, guarded(c, [&] { return pb_precond_apply_impl(c, s, p, x, y, transpose); }));
 }
 
 int pb_set_sweep_config(pb_ctx *c, int targets_per_thread, int target_waves)
@@ -1695,7 +1739,7 @@ static int pb_autotune_impl(pb_ctx *c, const pb_surface *s, const pb_params *p, 
 int pb_autotune(pb_ctx *c, const pb_surface *s, const pb_params *p, int *best_tpt,
                 int *best_waves)
 {
-    return leave(c, pb_autotune_impl(c, s, p, best_tpt, best_waves));
+    return leave(c, guarded(c, [&] { return pb_autotune_impl(c, s, p, best_tpt, best_waves); }));
 }
 
 static int pb_solve_batch_impl(pb_ctx *c, int32_t n_sys, const pb_surface *surf,
@@ -1719,7 +1763,9 @@ int pb_solve_batch(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_ch
                    const pb_params *p, double *e_solv, double *dE_dpos, double *dE_dq,
                    pb_info *info)
 {
-    return leave(c, pb_solve_batch_impl(c, n_sys, surf, chg, p, e_solv, dE_dpos, dE_dq, info));
+    return leave(c, guarded(c, [&] {
+        return pb_solve_batch_impl(c, n_sys, surf, chg, p, e_solv, dE_dpos, dE_dq, info);
+    }));
 }
 
 static int pb_autotune_batch_impl(pb_ctx *c, int32_t n_sys, const pb_surface *surf,
@@ -1747,7 +1793,9 @@ static int pb_autotune_batch_impl(pb_ctx *c, int32_t n_sys, const pb_surface *su
 int pb_autotune_batch(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
                       const pb_params *p, int *best_kind, int *best_tiles)
 {
-    return leave(c, pb_autotune_batch_impl(c, n_sys, surf, chg, p, best_kind, best_tiles));
+    return leave(c, guarded(c, [&] {
+        return pb_autotune_batch_impl(c, n_sys, surf, chg, p, best_kind, best_tiles);
+    }));
 }
 
 int pb_set_batch_tiles(pb_ctx *c, int tiles)
