@@ -28,6 +28,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 namespace pbk {
@@ -216,6 +219,32 @@ __global__ __launch_bounds__(TPB) void kb_pairs(const Src8<T> *__restrict__ src,
         part[it * TPB + threadIdx.x] = TRANS ? Q : P;
         part[(n_items + it) * TPB + threadIdx.x] = TRANS ? P : Q;
     }
+}
+
+// Preconditioner index tables of the batch: element k of the leaf order is
+// point perm[k] = goff + e of system b (sbase[b] <= k < sbase[b + 1]); its
+// phi and psi slots in the batch vectors are 2 goff + e and 2 goff + npad + e.
+__global__ __launch_bounds__(TPB) void kb_pc_index(const int32_t *__restrict__ perm, int64_t ne,
+                                                   const int64_t *__restrict__ sbase,
+                                                   const SysDesc *__restrict__ sd, int n_sys,
+                                                   int64_t *__restrict__ pidx,
+                                                   int64_t *__restrict__ qidx)
+{
+    const int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (k >= ne)
+        return;
+    int lo = 0, hi = n_sys - 1;   // the system whose range holds k
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (sbase[mid] <= k)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const SysDesc d = sd[lo];
+    const int64_t p = (int64_t)perm[k] + d.goff;   // 2 goff + e
+    pidx[k] = p;
+    qidx[k] = p + d.npad;
 }
 
 // ---- pairwise sweeps over the batch ------------------------------------------
@@ -1405,29 +1434,65 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     hipLaunchKernelGGL(kb_fill, dim3(vb), dim3(TPB), 0, s, D.pb, 0.0);
     LAUNCHCHK();
     if (p->precond_leaf > 0) {
-        std::vector<double> hg(3 * P.gtot);
-        HIPCHK(hipMemcpyAsync(hg.data(), D.g, sizeof(double) * 3 * P.gtot, hipMemcpyDeviceToHost,
+        // centroids of every system (3 gtot doubles, one copy) into pinned staging
+        if (c->hgeo_n < (size_t)(3 * P.gtot)) {
+            if (c->hgeo)
+                (void)hipHostFree(c->hgeo);
+            c->hgeo = nullptr;
+            c->hgeo_n = 0;
+            if (hipHostMalloc(reinterpret_cast<void **>(&c->hgeo), sizeof(double) * 3 * P.gtot,
+                              hipHostMallocDefault) != hipSuccess)
+                return fail(c, PB_ERR_OOM, "pinned host staging of %lld doubles",
+                            (long long)(3 * P.gtot));
+            c->hgeo_n = (size_t)(3 * P.gtot);
+        }
+        const double *hg = c->hgeo;
+        HIPCHK(hipMemcpyAsync(c->hgeo, D.g, sizeof(double) * 3 * P.gtot, hipMemcpyDeviceToHost,
                               s));
         HIPCHK(hipStreamSynchronize(s));
+        // the systems' octrees are independent: built side by side by a few
+        // workers (each tree single-threaded), joined in system order
+        std::vector<std::vector<int32_t>> sperm(n_sys), sstart(n_sys);
+        {
+            std::atomic<int> next{0};
+            auto work = [&] {
+                for (int b = next++; b < n_sys; b = next++) {
+                    const SysDesc &d = P.sd[b];
+                    build_leaves(hg + d.goff, hg + P.gtot + d.goff, hg + 2 * P.gtot + d.goff, d.n,
+                                 p->precond_leaf, sperm[b], sstart[b], false);
+                }
+            };
+            const unsigned hw = std::thread::hardware_concurrency();
+            const int nw = (int)std::min<unsigned>(std::max(1u, hw ? hw : 1u), 16u) - 1;
+            std::vector<std::thread> pool;
+            for (int k = 0; k < std::min(nw, n_sys - 1); ++k) {
+                try {
+                    pool.emplace_back(work);
+                } catch (const std::system_error &) {
+                    break;   // fewer workers; the calling thread works too
+                }
+            }
+            work();
+            for (auto &t : pool)
+                t.join();
+        }
         std::vector<int32_t> gperm, gstart(1, 0);
-        std::vector<int64_t> gboff(1, 0), pidx, qidx;
+        std::vector<int64_t> gboff(1, 0);
+        std::vector<int64_t> sbase(n_sys + 1, 0);   // first element of each system in gperm
         for (int b = 0; b < n_sys; ++b) {
             const SysDesc &d = P.sd[b];
-            std::vector<int32_t> perm, start;
-            build_leaves(hg.data() + d.goff, hg.data() + P.gtot + d.goff,
-                         hg.data() + 2 * P.gtot + d.goff, d.n, p->precond_leaf, perm, start);
+            const std::vector<int32_t> &perm = sperm[b], &start = sstart[b];
             const int32_t base = (int32_t)gperm.size();
-            for (int32_t e : perm) {
+            sbase[b] = base;
+            for (int32_t e : perm)
                 gperm.push_back((int32_t)(d.goff + e));
-                pidx.push_back(2 * d.goff + e);
-                qidx.push_back(2 * d.goff + d.npad + e);
-            }
             for (size_t l = 1; l < start.size(); ++l) {
                 gstart.push_back(base + start[l]);
                 const int64_t m2 = 2 * (int64_t)(start[l] - start[l - 1]);
                 gboff.push_back(gboff.back() + m2 * m2);
             }
         }
+        sbase[n_sys] = (int64_t)gperm.size();
         const int64_t L = (int64_t)gstart.size() - 1, ne = (int64_t)gperm.size();
         const size_t off64 = round_up(sizeof(int32_t) * (ne + L + 1), 8);
         TRY(ensure(c, c->b_pc_idx, off64 + sizeof(int64_t) * (L + 1 + 2 * ne)));
@@ -1441,8 +1506,12 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
         TRY(upload(c, D.pc_perm, gperm.data(), sizeof(int32_t) * ne));
         TRY(upload(c, D.pc_start, gstart.data(), sizeof(int32_t) * (L + 1)));
         TRY(upload(c, D.pc_boff, gboff.data(), sizeof(int64_t) * (L + 1)));
-        TRY(upload(c, D.pc_pidx, pidx.data(), sizeof(int64_t) * ne));
-        TRY(upload(c, D.pc_qidx, qidx.data(), sizeof(int64_t) * ne));
+        // phi and psi slots of every element, from its system's layout
+        TRY(ensure(c, c->b_pc_sys, sizeof(int64_t) * (n_sys + 1)));
+        TRY(upload(c, c->b_pc_sys.p, sbase.data(), sizeof(int64_t) * (n_sys + 1)));
+        hipLaunchKernelGGL(kb_pc_index, dim3(nblk(ne)), dim3(TPB), 0, s, D.pc_perm, ne,
+                           as<int64_t>(c->b_pc_sys), D.sd, n_sys, D.pc_pidx, D.pc_qidx);
+        LAUNCHCHK();
         Geo gall;
         gall.g = D.g;
         gall.n = P.gtot;

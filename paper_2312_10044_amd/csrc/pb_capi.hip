@@ -339,11 +339,11 @@ void build_subtree(const double *x, const double *y, const double *z, int n0,
 // Octree over the collocation points: a cell with more than n0 points is split
 // at its centre into octants (stable), a cell with at most n0 points is a leaf;
 // perm lists the points leaf by leaf in depth-first octant order and
-// start[l] .. start[l + 1] delimits leaf l.  The subtrees of the root's
-// children are built on their own threads (disjoint ranges of perm); the
-// result does not depend on the thread count.
+// start[l] .. start[l + 1] delimits leaf l.  With `threads`, the subtrees of
+// the root's children are built on their own threads (disjoint ranges of
+// perm); the result does not depend on it.
 void build_leaves(const double *x, const double *y, const double *z, int64_t n, int n0,
-                  std::vector<int32_t> &perm, std::vector<int32_t> &start)
+                  std::vector<int32_t> &perm, std::vector<int32_t> &start, bool threads)
 {
     double lo[3] = {x[0], y[0], z[0]}, hi[3] = {x[0], y[0], z[0]};
     for (int64_t i = 1; i < n; ++i) {
@@ -371,7 +371,7 @@ void build_leaves(const double *x, const double *y, const double *z, int64_t n, 
         return;
     }
     std::vector<std::vector<int32_t>> sub(kids.size());
-    const bool threaded = n >= 16384;
+    const bool threaded = threads && n >= 16384;
     std::vector<std::thread> pool;
     for (size_t k = 0; k < kids.size(); ++k) {
         auto job = [&, k] {
@@ -1125,7 +1125,8 @@ void pb_destroy(pb_ctx *c)
                       &c->sym_rowstart, &c->sym_rowpart, &c->sym_colpart, &c->sym_src64,
                       &c->t_nodes,
                       &c->t_ctr, &c->t_perm, &c->t_geo, &c->t_wv, &c->t_out, &c->t_mom,
-                      &c->t_cnt, &c->b_sitems, &c->b_rs, &c->b_srow, &c->b_scol};
+                      &c->t_cnt, &c->b_sitems, &c->b_rs, &c->b_srow, &c->b_scol,
+                      &c->b_pc_sys};
     for (DevBuf *b : bufs)
         if (b->p)
             (void)hipFree(b->p);

@@ -86,7 +86,7 @@ struct pb_ctx {
     // batched solves (pb_solve_batch)
     pbk::DevBuf b_geo, b_desc, b_map, b_items, b_src, b_part, b_vec, b_V, b_state, b_red, b_chg;
     pbk::DevBuf b_sitems, b_rs, b_srow, b_scol;   // pairwise sweeps of the batch
-    pbk::DevBuf b_pc_idx, b_pc_inv;
+    pbk::DevBuf b_pc_idx, b_pc_inv, b_pc_sys;
     hipGraphExec_t b_graph = nullptr;
     uint64_t b_graph_key = 0;
 };
@@ -207,7 +207,7 @@ inline void prof_collect(pb_ctx *c)
 
 // Octree leaves of n points for the block-diagonal preconditioner (pb_capi.hip).
 void build_leaves(const double *x, const double *y, const double *z, int64_t n, int n0,
-                  std::vector<int32_t> &perm, std::vector<int32_t> &start);
+                  std::vector<int32_t> &perm, std::vector<int32_t> &start, bool threads = true);
 
 // Batched solve of independent systems (pb_batch.hip).
 int tree_matvec(pb_ctx *c, const pb_params *p, double theta, int order, int n0, const double *x,
