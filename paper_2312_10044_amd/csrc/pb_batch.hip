@@ -67,7 +67,6 @@ struct SItem {
     int32_t sys, I, J0, J1, slot, pad0, pad1, pad2;
 };
 
-constexpr int SYM_TILES = 16;                 // default source tiles per pairwise work item
 
 struct GState {
     double H[(BM_MAX + 1) * BM_MAX];

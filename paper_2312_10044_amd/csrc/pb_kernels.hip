@@ -330,9 +330,9 @@ constexpr int FIN_ROWS = 64, FIN_WAVES = 4;
 template <typename CT>
 __global__ __launch_bounds__(FIN_ROWS * FIN_WAVES) void k_sym_finish(
     const double *__restrict__ rowpart, const CT *__restrict__ colpart,
-    const int32_t *__restrict__ row_start, int T, int64_t n, int64_t npad,
-    const double *__restrict__ area, const double *__restrict__ x, double alpha, double beta,
-    int trans, double scale1, double scale2, double *__restrict__ y)
+    const int32_t *__restrict__ row_start, int T, int64_t n, const double *__restrict__ area,
+    const double *__restrict__ x, double alpha, double beta, int trans, double scale1,
+    double scale2, double *__restrict__ y)
 {
     __shared__ double red[2][FIN_WAVES][FIN_ROWS];
     const int lane = threadIdx.x % FIN_ROWS, w = threadIdx.x / FIN_ROWS;
@@ -1166,7 +1166,7 @@ void launch_sym_finish(hipStream_t s, const Geo &geo, const double *rowpart,
 {
     hipLaunchKernelGGL(k_sym_finish<float>, dim3((geo.n + FIN_ROWS - 1) / FIN_ROWS),
                        dim3(FIN_ROWS * FIN_WAVES), 0, s, rowpart,
-                       colpart, row_start, n_tiles, geo.n, geo.npad, geo.g + 6 * geo.npad, x,
+                       colpart, row_start, n_tiles, geo.n, geo.g + 6 * geo.npad, x,
                        alpha, beta, transpose, scale1, scale2, y);
 }
 
@@ -1196,7 +1196,7 @@ void launch_sym_finish64(hipStream_t s, const Geo &geo, const double *rowpart,
 {
     hipLaunchKernelGGL(k_sym_finish<double>, dim3((geo.n + FIN_ROWS - 1) / FIN_ROWS),
                        dim3(FIN_ROWS * FIN_WAVES), 0, s, rowpart,
-                       colpart, row_start, n_tiles, geo.n, geo.npad, geo.g + 6 * geo.npad, x,
+                       colpart, row_start, n_tiles, geo.n, geo.g + 6 * geo.npad, x,
                        alpha, beta, transpose, 1.0, 1.0, y);
 }
 
