@@ -157,8 +157,8 @@ def run_batch(args):
     t_batch = (time.perf_counter() - t0) / max(1, args.steps)
     _log(f"batched: {t_batch:.3f} s")
 
-    def sequential(leaf_s):
-        p1 = Params(tol=tol, precision=PB_FP64, restart=10, max_iter=2000, precond_leaf=leaf_s)
+    def sequential(leaf_s, prec_s=PB_FP64):
+        p1 = Params(tol=tol, precision=prec_s, restart=10, max_iter=2000, precond_leaf=leaf_s)
         ctx.pb_forces(*sys_list[0], p1)
         t = time.perf_counter()
         es = []
@@ -172,6 +172,8 @@ def run_batch(args):
     _log(f"sequential FP64 (leaf {leaf}): {t_seq:.3f} s")
     t_seq0, e_s0 = sequential(0) if leaf > 0 else (t_seq, e_s)
     _log(f"sequential FP64 (no preconditioner): {t_seq0:.3f} s")
+    t_seq32, _e_s32 = sequential(leaf, PB_FP32_IR)
+    _log(f"sequential refined FP32 (leaf {leaf}): {t_seq32:.3f} s")
     rel = float(np.max(np.abs(np.asarray(e_b) - np.asarray(e_s)) / np.abs(e_s)))
     rel0 = float(np.max(np.abs(np.asarray(e_b) - np.asarray(e_s0)) / np.abs(e_s0)))
     out = {
@@ -191,6 +193,8 @@ def run_batch(args):
         "speedup": t_seq / t_batch,
         "sequential_fp64_no_preconditioner_s": t_seq0,
         "speedup_vs_unpreconditioned_fp64": t_seq0 / t_batch,
+        "sequential_fp32ir_same_preconditioner_s": t_seq32,
+        "speedup_vs_sequential_fp32ir": t_seq32 / t_batch,
         "max_rel_energy_diff_vs_sequential": rel,
         "max_rel_energy_diff_vs_unpreconditioned": rel0,
         "arnoldi_steps_forward_max": max(i.iters for i in inf_b),

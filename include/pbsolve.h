@@ -162,8 +162,8 @@ int pb_forces(pb_ctx *ctx, const pb_surface *s, const pb_charges *c, const pb_pa
               double *dE_dpos, double *dE_dq, pb_info *info);
 
 /* Batched solves of n_sys independent systems (surfaces[b], charges[b]) with
- * shared parameters, in shared launches: one persistent pair sweep over a
- * work list of (system, target block, source range) items per matvec, GMRES
+ * shared parameters, in shared launches: one pair sweep over a work list of
+ * (system, target block, source range) items per matvec, GMRES
  * in lockstep with per-system state, masks and convergence tests on the
  * device, one restart cycle captured in a hipGraph and replayed until all
  * systems converge.  Restart residuals are FP64; with PB_FP32_IR the Arnoldi
@@ -281,14 +281,14 @@ int pb_autotune(pb_ctx *ctx, const pb_surface *s, const pb_params *p, int *best_
 /* Batched solves (pb_solve_batch): the pairwise work items of the batched
  * sweeps take `tiles` source tiles (of 256 points) each; shorter items spread
  * the uneven systems over more blocks, longer ones reuse each target tile's
- * registers longer.  0 leaves the value unchanged; default 16. */
+ * registers longer.  0 leaves the value unchanged; default 4. */
 int pb_set_batch_tiles(pb_ctx *ctx, int tiles);
 int pb_get_batch_tiles(pb_ctx *ctx, int *tiles);
 /* Autotuner of the batched sweeps: on this batch (validated and laid out as by
  * pb_solve_batch, nothing solved), times the batched FP32 forward sweep over
  * all systems with HIP events, one warm-up and three timed launches per
- * candidate, for the pairwise kind with 4, 8, 16 and 32 source tiles per work
- * item and for the per-target kind, and keeps the fastest in the context:
+ * candidate, for the pairwise kind with 2, 4, 8, 16 and 32 source tiles per
+ * work item and for the per-target kind, and keeps the fastest in the context:
  * the sweep kind as by pb_set_sweep_config, the tiles as by
  * pb_set_batch_tiles.  best_* may be NULL.  Same errors as pb_solve_batch. */
 int pb_autotune_batch(pb_ctx *ctx, int32_t n_sys, const pb_surface *surfaces,

@@ -8,8 +8,9 @@
 // each system padded to a multiple of TPB.
 //
 // Pair sweeps run over a work list of equal-sized items (system, target
-// block, source tile range); one persistent grid walks the list with a
-// stride, so systems from 5,120 to 81,920 triangles share every launch.
+// block, source tile range), one workgroup per item, longest first, so
+// systems from 5,120 to 81,920 triangles share every launch and the
+// hardware dispatcher balances the load.
 // Each item writes its own partial slot; a second kernel sums a target's
 // slots in a fixed order (deterministic, no atomics).
 //
@@ -44,7 +45,6 @@ constexpr int HB = 2 * (BM_MAX + 1) + 2;      // per-system reduction slots
 constexpr int H_OFF1 = 0, H_OFF2 = BM_MAX + 1, H_NRM = 2 * (BM_MAX + 1);
 constexpr int MV_TILES = 32;                  // source tiles per matvec work item
 constexpr int CH_TILES = 16;                  // triangle tiles per charge-sweep item
-constexpr int BATCH_GRID = 2048;              // blocks of the persistent sweeps
 
 struct SysDesc {
     int64_t n, npad, goff;      // triangles, padded count, offset in the geometry arrays
@@ -980,22 +980,12 @@ struct BatchDev {
     GState *st = nullptr;
     double *red = nullptr, *dpart = nullptr, *per = nullptr, *e = nullptr;
     int64_t vtot = 0, nvb = 0, ld = 0;
-    // persistent grids of the pairwise sweeps: the blocks the device holds
-    unsigned grid_s32 = BATCH_GRID, grid_s64 = BATCH_GRID;
 };
 
-// Blocks of `kernel` (with `threads` per block) resident on the whole device
-// at once; BATCH_GRID if the runtime cannot tell.
-template <typename F>
-unsigned resident_blocks(F *kernel, int threads)
+// One workgroup per work item (the kernels also accept fewer and stride).
+inline unsigned item_grid(int64_t n_items)
 {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
-        cus < 1 || per < 1)
-        return BATCH_GRID;
-    return (unsigned)(cus * per);
+    return (unsigned)std::min<int64_t>(n_items, INT32_MAX);
 }
 
 void pc_apply_batch(hipStream_t s, const BatchDev &D, int trans, const double *x, double *y)
@@ -1011,7 +1001,7 @@ void enqueue_matvec(pb_ctx *c, const BatchPlan &P, BatchDev &D, bool f32, int tr
 {
     hipStream_t s = c->stream;
     const int64_t ni = (int64_t)P.items.size();
-    const unsigned grid = (unsigned)std::min<int64_t>(ni, BATCH_GRID);
+    const unsigned grid = item_grid(ni);
     const unsigned gb = nblk(P.gtot);
     const double alpha = 0.5 * (1.0 + eps), beta = 0.5 * (1.0 + 1.0 / eps);
     const int64_t nsi = (int64_t)P.sitems.size();
@@ -1019,7 +1009,7 @@ void enqueue_matvec(pb_ctx *c, const BatchPlan &P, BatchDev &D, bool f32, int tr
         // transposed: stream mode 1, eps -> 1/eps in the pair constant, rows
         // swapped and scaled by -sigma^2/eps and sigma^3 (as in the single-
         // system sweep)
-        const unsigned sgrid = (unsigned)std::min<int64_t>(nsi, D.grid_s32);
+        const unsigned sgrid = item_grid(nsi);
         const double sig = f32_sigma(kap);
         const double keps = trans ? 1.0 / eps : eps;
         hipLaunchKernelGGL(kb_pack_sym, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd, D.blk2sys,
@@ -1040,7 +1030,7 @@ void enqueue_matvec(pb_ctx *c, const BatchPlan &P, BatchDev &D, bool f32, int tr
         return;
     }
     if (!f32 && c->f64_kind == PB_SWEEP_PAIRWISE) {
-        const unsigned sgrid = (unsigned)std::min<int64_t>(nsi, D.grid_s64);
+        const unsigned sgrid = item_grid(nsi);
         hipLaunchKernelGGL(kb_pack_sym64, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd,
                            D.blk2sys, x, reinterpret_cast<Src8d *>(D.src), trans ? 1 : 0);
         if (trans)
@@ -1304,8 +1294,6 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     BatchPlan P;
     plan_batch(P, n_sys, surf, chg, c->b_sym_tiles);
     BatchDev D;
-    D.grid_s32 = resident_blocks(kb_pairs_f32_sym<true>, SYM_NT);
-    D.grid_s64 = resident_blocks(kb_pairs_f64_sym<false>, SYM64_NT);
     const int m = p->restart;
     D.vtot = 2 * P.gtot;
     D.nvb = D.vtot / TPB;
@@ -1521,7 +1509,7 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
         HIPCHK(hipStreamSynchronize(s));   // host index vectors go out of scope
         D.pc_leaves = L;
     }
-    const unsigned cgrid = (unsigned)std::min<int64_t>(nci, BATCH_GRID);
+    const unsigned cgrid = item_grid(nci);
     // charges inside: solid angle with phi = 1, psi = 0
     {
         hipLaunchKernelGGL(kb_fill, dim3(vb), dim3(TPB), 0, s, D.t, 0.0);

@@ -1776,7 +1776,7 @@ static int pb_autotune_batch_impl(pb_ctx *c, int32_t n_sys, const pb_surface *su
     TRY(enter(c));
     TRY(check_params(c, p, true));
     BatchTune tn;
-    const int tiles[] = {4, 8, 16, 32};
+    const int tiles[] = {2, 4, 8, 16, 32};
     for (int t : tiles) {
         tn.kind[tn.n] = PB_SWEEP_PAIRWISE;
         tn.tiles[tn.n++] = t;

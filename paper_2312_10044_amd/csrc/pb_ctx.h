@@ -62,7 +62,7 @@ struct pb_ctx {
     // pairwise sweep: packed points, work items and partial sums (plan cached)
     pbk::DevBuf sym_src, sym_src64, sym_items, sym_rowstart, sym_rowpart, sym_colpart;
     int f64_kind = PB_SWEEP_PAIRWISE;   // FP64 sweep: 1 per-target, or pairwise
-    int b_sym_tiles = 16;                // batch: source tiles per pairwise work item
+    int b_sym_tiles = 4;                 // batch: source tiles per pairwise work item
     pbk::SymPlan sym_plan;
     int sym_waves = 0;
     // treecode: tree, permuted geometry and weights, moments, results
