@@ -15,6 +15,7 @@ from .workloads import (
     kirkwood_sphere,
     star_protein,
     large_star_protein,
+    large_star_surface,
     batch_conformations,
     input_digest,
 )
@@ -30,6 +31,7 @@ __all__ = [
     "kirkwood_sphere",
     "star_protein",
     "large_star_protein",
+    "large_star_surface",
     "batch_conformations",
     "input_digest",
 ]

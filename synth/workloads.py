@@ -48,9 +48,15 @@ class Workload:
         return int(self.q.shape[0])
 
 
-def _star(name, freq, r0, n_charges, rng, amp=0.15, min_dist=1.5):
+def _star_shape(freq, r0, rng, amp=0.15):
+    """The star surface of a workload: its shape is drawn first from rng."""
     coef = draw_shape_coeffs(rng, 6)
     verts, tris = star_surface(freq, r0, coef, amp)
+    return verts, tris, coef
+
+
+def _star(name, freq, r0, n_charges, rng, amp=0.15, min_dist=1.5):
+    verts, tris, coef = _star_shape(freq, r0, rng, amp)
 
     def inside(p):
         rr = np.sqrt(np.sum(p * p, axis=1))
@@ -80,6 +86,13 @@ def star_protein(freq: int = 64, r0: float = 20.0, n_charges: int = 2000,
 def large_star_protein(seed: int = 3) -> Workload:
     rng = np.random.default_rng(seed)
     return _star(f"star_f128_s{seed}", 128, 40.0, 10000, rng)
+
+
+def large_star_surface(seed: int = 3):
+    """(verts, tris) of large_star_protein(seed) without its 10,000 charges,
+    which are drawn after the shape: the input of a matvec at that size."""
+    verts, tris, _coef = _star_shape(128, 40.0, np.random.default_rng(seed))
+    return verts, tris
 
 
 def batch_conformations(n_sys: int = 64, seed: int = 5, freq_range=(16, 64),

@@ -99,17 +99,47 @@ def test_pairwise_plan_sizes_and_repeat(pb, star12, waves):
     assert np.array_equal(y, y2)
 
 
-def test_pairwise_full_size_sampled_rows(pb):
+@pytest.mark.parametrize("waves", [32768, 131072])
+def test_pairwise_full_size_sampled_rows(pb, waves):
+    """81,920 triangles, forward and transposed; 131072 target waves is the
+    launch configuration the bench times."""
     m, ctx = pb
     w = synth.star_protein()
     rows = np.sort(np.random.default_rng(5).choice(w.n_tri, 160, replace=False))
     rows = np.concatenate([rows, [0, w.n_tri - 1]])
-    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 32768)
-    _say(f"pairwise full size: {w.n_tri} triangles, {len(rows)} rows")
-    err, _y = _err(m, ctx, w, rows=rows, seed=3)
+    ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, waves)
+    try:
+        for transpose in (False, True):
+            _say(f"pairwise full size: {w.n_tri} triangles, {len(rows)} rows, waves {waves}, "
+                 f"transpose {transpose}")
+            err, _y = _err(m, ctx, w, rows=rows, seed=3, transpose=transpose)
+            _say(f"  max |dy|/S = {err:.3e}")
+            assert err <= 5e-5
+    finally:
+        ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
+
+
+def test_pairwise_largest_size_sampled_rows(pb):
+    """The 327,680-triangle surface of the largest workload in the bench's
+    launch configuration: FP32 pairwise forward and transposed, FP64 pairwise
+    forward, on sampled rows plus the first and the last."""
+    import types
+    m, ctx = pb
+    verts, tris = synth.large_star_surface()
+    w = types.SimpleNamespace(verts=verts, tris=tris)
+    n = tris.shape[0]
+    rows = np.sort(np.random.default_rng(8).choice(n, 40, replace=False))
+    rows = np.concatenate([rows, [0, n - 1]])
     ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
-    _say(f"  max |dy|/S = {err:.3e}")
-    assert err <= 5e-5
+    ctx.set_fp64_sweep(m.PB_SWEEP_PAIRWISE)
+    for transpose in (False, True):
+        _say(f"pairwise largest size: {n} triangles, {len(rows)} rows, transpose {transpose}")
+        err, _y = _err(m, ctx, w, rows=rows, seed=9, transpose=transpose)
+        _say(f"  FP32 max |dy|/S = {err:.3e}")
+        assert err <= 5e-5
+    err64, _y = _err64(m, ctx, w, False, rows=rows, seed=9)
+    _say(f"  FP64 max |dy|/S = {err64:.3e}")
+    assert err64 <= 2e-12
 
 
 def test_pairwise_ir_solve_matches_fp64(pb, star12):
