@@ -79,7 +79,8 @@ typedef struct {
     int32_t precision;          /* PB_FP64 or PB_FP32_IR */
     int32_t max_refine;         /* IR: cap on refinement steps */
     double inner_tol;           /* IR: relative tolerance of the first inner FP32 GMRES
-                                   solve.  A later correction solve, with outer residual
+                                   solve, in (0, 1) (PB_ERR_ARG otherwise; unused by
+                                   PB_FP64).  A later correction solve, with outer residual
                                    r, stops at max(inner_tol, 0.3 tol |b| / |r|) (at most
                                    0.5): just enough to bring the outer residual under
                                    tol.  Values below 1e-7 (beyond what FP32 pair
