@@ -99,7 +99,7 @@ def test_autograd_function(pb):
     E = pb_energy(tv, tt, pos, q, ctx, P)
     (2.0 * E).backward()
     info, dpos, dq = ctx.pb_forces(w.verts, w.tris, w.pos, w.q, P)
-    assert float(E) == pytest.approx(info.e_solv, rel=1e-14)
+    assert float(E.detach()) == pytest.approx(info.e_solv, rel=1e-14)
     assert np.allclose(pos.grad.cpu().numpy(), 2.0 * dpos, rtol=1e-13, atol=0)
     assert np.allclose(q.grad.cpu().numpy(), 2.0 * dq, rtol=1e-13, atol=0)
     with torch.no_grad():
