@@ -135,12 +135,12 @@ __global__ __launch_bounds__(TPB) void kt_moments(const TreeNode *__restrict__ n
 // w = a psi, v = a phi.
 __device__ __forceinline__ void pair_direct(const double d[3], const double ni[3],
                                             const double nj[3], double w, double v, double eps,
-                                            double kappa, double &s1, double &s2)
+                                            double ieps, double kappa, double &s1, double &s2)
 {
     const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    const double ir = rsqrt(r2);
+    const double ir = rsqrt_pos(r2);
     const double rho = r2 * ir;
-    const double e = exp(-kappa * rho);
+    const double e = exp_neg_pair(kappa * rho);
     const double tp2 = (1.0 + kappa * rho) * e;
     const double ir2 = ir * ir, ir3 = ir2 * ir;
     const double cx = ni[0] * d[0] + ni[1] * d[1] + ni[2] * d[2];
@@ -148,7 +148,7 @@ __device__ __forceinline__ void pair_direct(const double d[3], const double ni[3
     const double nn = ni[0] * nj[0] + ni[1] * nj[1] + ni[2] * nj[2];
     const double k1 = ir - e * ir;
     const double k2 = (eps * tp2 - 1.0) * cy * ir3;
-    const double k3 = (tp2 / eps - 1.0) * cx * ir3;
+    const double k3 = (tp2 * ieps - 1.0) * cx * ir3;
     const double h0 = (nn - 3.0 * cx * cy * ir2) * ir3;
     const double k4 = (tp2 - 1.0) * h0 - kappa * kappa * cx * cy * ir2 * e * ir;
     s1 += k1 * w + k2 * v;
@@ -157,10 +157,13 @@ __device__ __forceinline__ void pair_direct(const double d[3], const double ni[3
 
 // Far field of one cluster on one target: coefficients of both kernels to
 // order P + 2 by the recurrences, each consumed as soon as it is formed.
+// 1/eps (ieps) and 1/q enter as multiplications: an FP64 division is a
+// sequence of about ten dependent instructions here, and the walk runs one
+// wave per SIMD, with nothing else to hide their latency.
 template <int P>
 __device__ __forceinline__ void far_field(const double R[3], const double ni[3],
                                           const double *__restrict__ mo, double eps,
-                                          double kappa, double &s1, double &s2)
+                                          double ieps, double kappa, double &s1, double &s2)
 {
     constexpr int Q = P + 2;
     constexpr int NQ = nterms(Q);
@@ -170,14 +173,15 @@ __device__ __forceinline__ void far_field(const double R[3], const double ni[3],
     const double rho2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
     const double irho2 = 1.0 / rho2;
     const double irho = sqrt(irho2);
-    const double e = exp(-kappa * rho2 * irho);
+    const double e = exp_neg_pair(kappa * rho2 * irho);
     A0[0] = irho;
     A[0] = e * irho;
     B[0] = e;
     s1 += (A0[0] - A[0]) * M[0];
 #pragma unroll
     for (int q = 1; q <= Q; ++q) {
-        const double iq = irho2 / q;
+        const double rq = 1.0 / q;   // a constant once the loop is unrolled
+        const double iq = irho2 * rq;
 #pragma unroll
         for (int k1 = q; k1 >= 0; --k1) {
 #pragma unroll
@@ -203,7 +207,7 @@ __device__ __forceinline__ void far_field(const double R[3], const double ni[3],
                 }
                 A0[t] = ((2 * q - 1) * l0 - (q - 1) * g0) * iq;
                 A[t] = ((2 * q - 1) * l - (q - 1) * g + kappa * (lb - gb)) * iq;
-                B[t] = kappa * (l - g) / q;
+                B[t] = kappa * (l - g) * rq;
                 // consume T^m (T0 = A0, Tk = A) at m = (k1, k2, k3)
                 if (q <= P)   // K1 on the psi moments
                     s1 += (A0[t] - A[t]) * M[t];
@@ -215,7 +219,7 @@ __device__ __forceinline__ void far_field(const double R[3], const double ni[3],
                             // K2: source normal derivative on the phi moments
                             s1 += m[d] * (eps * A[t] - A0[t]) * D[d * NT + u];
                             // K3: target normal derivative on the psi moments
-                            s2 -= m[d] * ni[d] * (A0[t] - A[t] / eps) * M[u];
+                            s2 -= m[d] * ni[d] * (A0[t] - A[t] * ieps) * M[u];
                         }
                     }
                 }
@@ -255,6 +259,7 @@ __global__ __launch_bounds__(TPB) void kt_eval(const TreeNode *__restrict__ node
         return;
     const double xi[3] = {tg[i], tg[n + i], tg[2 * n + i]};
     const double ni[3] = {tg[3 * n + i], tg[4 * n + i], tg[5 * n + i]};
+    const double ieps = 1.0 / eps;
     double s1 = 0.0, s2 = 0.0;
     int64_t n_far = 0, n_pairs = 0;
     int node = 0;
@@ -264,7 +269,7 @@ __global__ __launch_bounds__(TPB) void kt_eval(const TreeNode *__restrict__ node
         const double R[3] = {xi[0] - c.x, xi[1] - c.y, xi[2] - c.z};
         const double R2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
         if (R2 > 0.0 && c.w <= theta * sqrt(R2)) {
-            far_field<P>(R, ni, mom + (int64_t)node * 4 * NT, eps, kappa, s1, s2);
+            far_field<P>(R, ni, mom + (int64_t)node * 4 * NT, eps, ieps, kappa, s1, s2);
             ++n_far;
             node = nd.next;
         } else if (nd.leaf) {
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(TPB) void kt_eval(const TreeNode *__restrict__ node
                     continue;
                 const double d[3] = {xi[0] - tg[j], xi[1] - tg[n + j], xi[2] - tg[2 * n + j]};
                 const double nj[3] = {tg[3 * n + j], tg[4 * n + j], tg[5 * n + j]};
-                pair_direct(d, ni, nj, wv[j], wv[n + j], eps, kappa, s1, s2);
+                pair_direct(d, ni, nj, wv[j], wv[n + j], eps, ieps, kappa, s1, s2);
             }
             n_pairs += nd.hi - nd.lo - ((int)i >= nd.lo && (int)i < nd.hi);
             node = nd.next;
