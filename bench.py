@@ -487,6 +487,17 @@ def main():
             kernel_rows[name] = {"launches": n_l, "avg_ms": ms_l / n_l,
                                  "gpairs_per_s": pr_l / (ms_l * 1e-3) / 1e9}
 
+    # the same solve through the host-array entry point (surface and charges
+    # copied in, phi/dphi copied out over PCIe): reported beside `value`,
+    # which stays the device-resident rate
+    ctx.pb_solve(w.verts, w.tris, w.pos, w.q, params)
+    host_s = []
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        ctx.pb_solve(w.verts, w.tris, w.pos, w.q, params)
+        host_s.append(time.perf_counter() - ts)
+    _log(f"bench: host-array solves: median {1e3 * float(np.median(host_s)):.2f} ms")
+
     compare = {}
     if not args.no_fp64_compare:
         variants = [("fp64_same_preconditioner", PB_FP64, leaf),
@@ -525,6 +536,7 @@ def main():
         },
         "time_to_solution_s": ms_step / 1e3,
         "time_to_solution_median_s": float(np.median(step_s)),
+        "time_to_solution_host_arrays_median_s": float(np.median(host_s)),
         "step_s": [round(t, 6) for t in step_s],
         "e_solv": infos[-1].e_solv,
         "e_rel_err": max(errs),
