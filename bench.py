@@ -1,14 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the DSBI Poisson-Boltzmann hot path on one MI355X.
 
-One step = one whole solve of the star-shaped synthetic protein surface
-(81,920 triangles, 2,000 interior charges): collocation geometry, source
+One step = one whole solve of the large star-shaped synthetic protein surface
+(327,680 triangles, 10,000 interior charges): collocation geometry, source
 terms, restarted GMRES(10) with the refined-FP32 matvec (FP64 outer
 residuals, FP64 Arnoldi) and the block-diagonal leaf preconditioner (leaf
-size 16 by default), solvation energy.  Inputs are device-resident
-before the timed region starts.  The solve tolerance is the loosest of a
-fixed ladder whose energy is within 1e-6 (relative) of an FP64 solve at
-tol 1e-12; the ladder search runs before timing.
+size 24 by default), solvation energy.  Inputs are device-resident before
+the timed region starts.  The solve tolerance is the loosest of the decade
+ladder 1e-4, 1e-5, ... whose energy is within 1e-6 (relative) of an FP64
+solve at tol 1e-12; the ladder search runs before timing.
+
+The same JSON line carries two more legs, each measured the same way:
+`star81920` (81,920 triangles, 2,000 charges) and `batch64` (64 star
+surfaces of 5,120-81,920 triangles solved for E_sol and forces in one
+pb_solve_batch call, against the same 64 solves one at a time).
 
 Prints one JSON line.  `value` = matvec pair interactions per second over
 the whole step (all FP32 and FP64 matvecs, N(N-1) pairs each) in G/s;
@@ -29,22 +34,15 @@ sys.path.insert(0, ROOT)
 FLOP_PER_PAIR = 58.0          # algorithmic FLOP of one matvec pair (FMA = 2)
 PEAK_FP32_VECTOR = 157.3e12   # MI355X published FP32 vector peak
 PEAK_FP64_VECTOR = 78.6e12
-TOL_LADDER = [1e-3, 5e-4, 2e-4, 1e-4, 5e-5, 2e-5, 1e-5, 5e-6, 2e-6, 1e-6, 5e-7, 2e-7, 1e-7,
-              1e-8]
+TOL_LADDER = [1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10]
 E_TARGET = 1e-6
+PAIRWISE = 8   # pb_set_sweep_config kind of the pairwise sweep (PB_SWEEP_PAIRWISE)
 
-
-TRAFFIC_RECORDS = {   # FETCH_SIZE/WRITE_SIZE records per FP32 sweep kind
-    8: os.path.join(ROOT, "profiles", "k_pairs_f32_sym_star81920_traffic.json"),
-    1: os.path.join(ROOT, "profiles", "k_pairs_f32_star81920_traffic.json"),
-}
+WORKLOADS = {"star327680": "large_star_protein", "star81920": "star_protein"}
 
 
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
-
-
-PAIRWISE = 8   # pb_set_sweep_config kind of the pairwise sweep (PB_SWEEP_PAIRWISE)
 
 
 def fp32_kernel_name(kind: int) -> str:
@@ -69,11 +67,12 @@ def _code_only(text: str) -> str:
 
 def kernel_digest(kind: int) -> str:
     """SHA-256 of the FP32 forward sweep's code (comments and layout
-    stripped): the shared device header plus the text of the sweep kernel
+    stripped): the shared device headers plus the text of the sweep kernel
     that `kind` selects."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2312_10044_amd", "csrc")
-    dev = open(os.path.join(csrc, "pb_device.h")).read()
+    dev = "".join(open(os.path.join(csrc, f)).read()
+                  for f in ("pb_fp64math.h", "pb_device.h") if os.path.exists(os.path.join(csrc, f)))
     ker = open(os.path.join(csrc, "pb_kernels.hip")).read()
     name = fp32_kernel_name(kind)
     b0 = ker.index(f" void {name}(")
@@ -82,17 +81,20 @@ def kernel_digest(kind: int) -> str:
     return hashlib.sha256(_code_only(dev + ker[a:b]).encode()).hexdigest()
 
 
-def measured_traffic(n_tri, sweep):
-    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE record,
-    or None when the kernel source or its configuration changed since."""
+def counter_record(workload: str, sweep):
+    """The committed rocprofv3 counter record of the FP32 sweep on this
+    workload (calibrated FETCH_SIZE/WRITE_SIZE bytes, hardware-counted VALU
+    FLOPs per launch), or None when the kernel source or its launch
+    configuration changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{fp32_kernel_name(sweep[0])}_{workload}_counters.json")
     try:
-        rec = json.load(open(TRAFFIC_RECORDS[sweep[0]]))
-    except (KeyError, OSError, ValueError):
+        rec = json.load(open(path))
+    except (OSError, ValueError):
         return None
-    if (rec.get("kernel_digest") != kernel_digest(sweep[0]) or rec.get("n_tri") != n_tri
+    if (rec.get("kernel_digest") != kernel_digest(sweep[0])
             or [rec.get("sweep_kind"), rec.get("target_waves")] != list(sweep)):
         return None
-    return float(rec["bytes_per_launch"])
+    return rec
 
 
 def cpu_baseline(w, seconds=12.0):
@@ -103,11 +105,11 @@ def cpu_baseline(w, seconds=12.0):
     g = dsbi.geometry(w.verts, w.tris)
     x = np.random.default_rng(0).normal(size=2 * g.n)
     rng = np.random.default_rng(1)
-    probe = np.sort(rng.choice(g.n, 256, replace=False))
+    probe = np.sort(rng.choice(g.n, 128, replace=False))
     t0 = time.perf_counter()
     dsbi.matvec(g, w.eps_out / w.eps_in, w.kappa, x, rows=probe)
     dt = time.perf_counter() - t0
-    rows_n = int(min(g.n, max(256, 256 * seconds / max(dt, 1e-3))))
+    rows_n = int(min(g.n, max(128, 128 * seconds / max(dt, 1e-3))))
     rows = np.sort(rng.choice(g.n, rows_n, replace=False))
     t0 = time.perf_counter()
     dsbi.matvec(g, w.eps_out / w.eps_in, w.kappa, x, rows=rows)
@@ -123,16 +125,202 @@ def cpu_baseline(w, seconds=12.0):
     }
 
 
-def run_batch(args):
+def make_workload(name):
+    import synth
+    return getattr(synth, WORKLOADS[name])()
+
+
+def solve_leg(ctx, w, key, args, steps, warmup, compare=True, host_arrays=True):
+    """Time-to-solution and matvec pair rate of one workload: the reference
+    FP64 energy, the tolerance pick, `warmup` untimed and `steps` timed
+    device-resident solves, the dominant sweep's live timing, and optionally
+    the host-array solve and the comparison variants."""
+    import numpy as np
+    import torch
+    from paper_2312_10044_amd import Params, PB_FP64, PB_FP32_IR
+    from paper_2312_10044_amd import pbsolve as pbs
+
+    dev = torch.device("cuda:0")
+    N = w.n_tri
+    _log(f"bench: workload {w.name}: {N} triangles, {w.n_charges} charges")
+    tv = torch.from_numpy(w.verts).to(dev)
+    tt = torch.from_numpy(w.tris.astype(np.int32)).to(dev)
+    tp = torch.from_numpy(w.pos).to(dev)
+    tq = torch.from_numpy(w.q).to(dev)
+    phi = torch.empty(N, dtype=torch.float64, device=dev)
+    dphi = torch.empty_like(phi)
+    torch.cuda.synchronize()
+
+    def solve(params):
+        info = ctx.pb_solve_dev(tv, tt, tp, tq, params, phi, dphi)
+        if info.status != pbs.PB_OK:
+            raise RuntimeError(f"solve did not converge: {info}")
+        return info
+
+    base = dict(eps_in=w.eps_in, eps_out=w.eps_out, kappa=w.kappa, restart=10, max_iter=2000)
+    tuned = ctx.get_sweep_config()
+    ref = solve(Params(tol=1e-12, precision=PB_FP64, precond_leaf=args.precond_leaf, **base))
+    e_ref = ref.e_solv
+    _log(f"bench: FP64 reference E={e_ref:.10f} (tol 1e-12, {ref.iters} iterations)")
+
+    def params_for(precision, leaf, tol):
+        if precision == PB_FP32_IR:
+            return Params(tol=tol, precision=PB_FP32_IR, inner_tol=0.1 * tol, max_refine=20,
+                          precond_leaf=leaf, **base)
+        return Params(tol=tol, precision=PB_FP64, precond_leaf=leaf, **base)
+
+    def pick(precision, leaf):
+        for tol in TOL_LADDER:
+            p = params_for(precision, leaf, tol)
+            info = solve(p)
+            err = abs(info.e_solv - e_ref) / abs(e_ref)
+            _log(f"bench: {w.name} precision={precision} leaf={leaf} tol={tol:g} E err={err:.2e} "
+                 f"iters={info.iters} t={info.seconds:.3f}s")
+            if err <= E_TARGET:
+                return p, err
+        raise RuntimeError("no tolerance on the ladder reached the energy target")
+
+    def timed_once(p):
+        solve(p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = solve(p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return {"time_to_solution_s": dt, "tol": p.tol, "iters": info.iters,
+                "matvecs_fp32": info.matvecs_fp32, "matvecs_fp64": info.matvecs_fp64,
+                "e_rel_err": abs(info.e_solv - e_ref) / abs(e_ref),
+                "gpairs_per_s": (info.matvecs_fp32 + info.matvecs_fp64) * float(N) * (N - 1)
+                / dt / 1e9}
+
+    prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
+    leaf = args.precond_leaf
+    params, _err_pick = pick(prec, leaf)
+
+    for _ in range(warmup):
+        solve(params)
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    step_s = []
+    for k in range(steps):
+        ts = time.perf_counter()
+        infos.append(solve(params))   # returns once E_solv is on the host
+        step_s.append(time.perf_counter() - ts)
+        _log(f"bench: {w.name} step {k + 1}/{steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile_enable(False)
+    ms_step = 1e3 * elapsed / steps
+    pairs_per_mv = float(N) * float(N - 1)
+    n_mv = sum(i.matvecs_fp32 + i.matvecs_fp64 for i in infos)
+    value = n_mv * pairs_per_mv / elapsed / 1e9
+    errs = [abs(i.e_solv - e_ref) / abs(e_ref) for i in infos]
+
+    dom = pbs.PB_KERNEL_PAIRS_FP32 if prec == PB_FP32_IR else pbs.PB_KERNEL_PAIRS_FP64
+    launches, kms, kpairs = ctx.profile_read(dom)
+    avg_ms = kms / max(launches, 1)
+    pairs_launch = kpairs / max(launches, 1)
+    achieved = FLOP_PER_PAIR * pairs_launch / (avg_ms * 1e-3)
+    peak = PEAK_FP32_VECTOR if prec == PB_FP32_IR else PEAK_FP64_VECTOR
+    kernel_rows = {}
+    for name, kid in (("pairs_fp32", pbs.PB_KERNEL_PAIRS_FP32),
+                      ("pairs_fp64", pbs.PB_KERNEL_PAIRS_FP64),
+                      ("source", pbs.PB_KERNEL_SOURCE), ("charge", pbs.PB_KERNEL_CHARGE)):
+        n_l, ms_l, pr_l = ctx.profile_read(kid)
+        if n_l:
+            kernel_rows[name] = {"launches": n_l, "avg_ms": ms_l / n_l,
+                                 "gpairs_per_s": pr_l / (ms_l * 1e-3) / 1e9}
+    rec = counter_record(key, tuned) if prec == PB_FP32_IR else None
+    counted = None
+    if rec is not None:
+        fl = float(rec["valu_flop_per_launch"])
+        counted = {"flop_per_launch": fl, "achieved": fl / (avg_ms * 1e-3) / 1e12,
+                   "frac": fl / (avg_ms * 1e-3) / peak,
+                   "flop_per_ordered_pair": fl / pairs_launch}
+    roofline = {
+        "bound": "alu",
+        "kernel": (fp32_kernel_name(tuned[0]) if prec == PB_FP32_IR
+                   else fp64_kernel_name(ctx.get_fp64_sweep())),
+        "achieved": achieved / 1e12,
+        "peak": peak / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / peak,
+        "traffic": float(rec["bytes_per_launch"]) if rec is not None else None,
+        "basis": "algorithmic: 58 FLOP per ordered pair x N(N-1) pairs per launch, over the "
+                 "launch's HIP-event duration (the pairwise sweep shares work between the two "
+                 "directions of a pair, so it executes fewer FLOPs than this)",
+        "counted": counted,
+        "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+        "flop_per_pair": FLOP_PER_PAIR,
+        "pairs_per_launch": pairs_launch,
+        "avg_launch_ms": avg_ms,
+        "launches": launches,
+    }
+
+    host_med = None
+    if host_arrays:
+        # the same solve through the host-array entry point (surface and
+        # charges copied in, phi/dphi copied out over PCIe): reported beside
+        # `value`, which stays the device-resident rate
+        ctx.pb_solve(w.verts, w.tris, w.pos, w.q, params)
+        host_s = []
+        for _ in range(min(steps, 5)):
+            ts = time.perf_counter()
+            ctx.pb_solve(w.verts, w.tris, w.pos, w.q, params)
+            host_s.append(time.perf_counter() - ts)
+        host_med = float(np.median(host_s))
+        _log(f"bench: {w.name} host-array solves: median {1e3 * host_med:.2f} ms")
+
+    cmp = {}
+    if compare:
+        variants = [("fp64_same_preconditioner", PB_FP64, leaf),
+                    ("fp32_ir_no_preconditioner", PB_FP32_IR, 0),
+                    ("fp64_no_preconditioner", PB_FP64, 0)]
+        for name, pr, lf in variants:
+            if pr == prec and lf == leaf:
+                continue
+            pv, _e = pick(pr, lf)
+            cmp[name] = timed_once(pv)
+
+    return {
+        "n_tri": N,
+        "n_charges": w.n_charges,
+        "value": value,
+        "ms_per_step": ms_step,
+        "tol": params.tol,
+        "inner_tol": params.inner_tol if prec == PB_FP32_IR else None,
+        "e_ref_fp64_tol1e-12": e_ref,
+        "e_solv": infos[-1].e_solv,
+        "e_rel_err": max(errs),
+        "iters": infos[-1].iters,
+        "matvecs_fp32": infos[-1].matvecs_fp32,
+        "matvecs_fp64": infos[-1].matvecs_fp64,
+        "refinements": infos[-1].refinements,
+        "time_to_solution_median_s": float(np.median(step_s)),
+        "time_to_solution_host_arrays_median_s": host_med,
+        "step_s": [round(t, 6) for t in step_s],
+        "kernels": kernel_rows,
+        "roofline": roofline,
+        "compare": cmp,
+        "fp32_sweep": {"kind": sweep_label(tuned[0]), "target_waves": tuned[1]},
+    }
+
+
+def batch_leg(ctx, args, steps):
     """64 star surfaces of uneven size (5,120-81,920 triangles, 100-2,000
-    charges): E_sol plus forces for all of them in one pb_solve_batch call
-    (shared persistent launches, hipGraph-replayed restart cycles) against
-    the same 64 solves one at a time with pb_forces in FP64."""
+    charges): E_sol plus forces of all of them in one pb_solve_batch call
+    (shared launches, hipGraph-replayed restart cycles, autotuned tiles)
+    against the same 64 solves one at a time.  Each variant's tolerance is the
+    loosest on the decade ladder whose worst energy error over the 64 systems
+    is within 1e-6 of an FP64 batch solve at tol 1e-12."""
     import numpy as np
     import torch
 
     import synth
-    from paper_2312_10044_amd import Context, Params, PB_FP64, PB_FP32_IR
+    from paper_2312_10044_amd import Params, PB_FP64, PB_FP32_IR
 
     systems = synth.batch_conformations()
     sys_list = [(w.verts, w.tris, w.pos, w.q) for w in systems]
@@ -140,74 +328,98 @@ def run_batch(args):
     pairs = float(sum(float(n) * (n - 1) for n in n_tri))
     _log(f"bench batch: {len(systems)} systems, {sum(n_tri)} triangles, "
          f"{pairs:.3g} pairs per batched matvec")
-    ctx = Context(0)
-    tol = 1e-6
     leaf = args.precond_leaf
     prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
-    pb = Params(tol=tol, precision=prec, restart=10, max_iter=2000, precond_leaf=leaf)
-    # tile shapes of the batched sweeps picked on this batch, outside the timing
-    tuned_kind, tuned_tiles = ctx.pb_autotune_batch(sys_list, pb)
+
+    def prm(precision, tol):
+        if precision == PB_FP32_IR:
+            return Params(tol=tol, precision=PB_FP32_IR, inner_tol=0.1 * tol, restart=10,
+                          max_iter=2000, precond_leaf=leaf)
+        return Params(tol=tol, precision=PB_FP64, restart=10, max_iter=2000, precond_leaf=leaf)
+
+    tuned_kind, tuned_tiles = ctx.pb_autotune_batch(sys_list, prm(prec, 1e-6))
     _log(f"bench batch: autotuned sweep kind={tuned_kind} tiles/item={tuned_tiles}")
-    e_b, inf_b, g_b, q_b = ctx.pb_solve_batch(sys_list, pb, forces=True)   # warm-up
+    e_ref, _inf, g_ref, _q = ctx.pb_solve_batch(sys_list, prm(PB_FP64, 1e-12), forces=True)
+    e_ref = np.asarray(e_ref)
+
+    def energy_err(e):
+        return float(np.max(np.abs(np.asarray(e) - e_ref) / np.abs(e_ref)))
+
+    def force_err(g):
+        out, k = 0.0, 0
+        for w in systems:
+            a, b = g[k:k + w.n_charges], g_ref[k:k + w.n_charges]
+            out = max(out, float(np.abs(a - b).max() / np.abs(b).max()))
+            k += w.n_charges
+        return out
+
+    def pick(run):
+        for tol in TOL_LADDER:
+            e = run(tol)
+            err = energy_err(e)
+            _log(f"bench batch: tol={tol:g} worst E err={err:.2e}")
+            if err <= E_TARGET:
+                return tol, err
+        raise RuntimeError("no tolerance on the ladder reached the energy target")
+
+    def batched(tol):
+        e, infos, g, _gq = ctx.pb_solve_batch(sys_list, prm(prec, tol), forces=True)
+        if any(i.status != 0 for i in infos):
+            raise RuntimeError("a batched system did not converge")
+        return e
+
+    tol_b, err_b = pick(batched)
+    e_b, inf_b, g_b, _q = ctx.pb_solve_batch(sys_list, prm(prec, tol_b), forces=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(max(1, args.steps)):
-        e_b, inf_b, g_b, q_b = ctx.pb_solve_batch(sys_list, pb, forces=True)
+    for _ in range(steps):
+        e_b, inf_b, g_b, _q = ctx.pb_solve_batch(sys_list, prm(prec, tol_b), forces=True)
     torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / max(1, args.steps)
-    _log(f"batched: {t_batch:.3f} s")
+    t_batch = (time.perf_counter() - t0) / steps
+    _log(f"bench batch: batched {t_batch:.3f} s at tol {tol_b:g}")
 
-    def sequential(leaf_s, prec_s=PB_FP64):
-        p1 = Params(tol=tol, precision=prec_s, restart=10, max_iter=2000, precond_leaf=leaf_s)
-        ctx.pb_forces(*sys_list[0], p1)
+    def sequential(precision, tol):
+        p1 = prm(precision, tol)
         t = time.perf_counter()
         es = []
         for sysd in sys_list:
             info, _gp, _gq = ctx.pb_forces(*sysd, p1)
+            if info.status != 0:
+                raise RuntimeError("a sequential solve did not converge")
             es.append(info.e_solv)
         torch.cuda.synchronize()
         return time.perf_counter() - t, es
 
-    t_seq, e_s = sequential(leaf)
-    _log(f"sequential FP64 (leaf {leaf}): {t_seq:.3f} s")
-    t_seq0, e_s0 = sequential(0) if leaf > 0 else (t_seq, e_s)
-    _log(f"sequential FP64 (no preconditioner): {t_seq0:.3f} s")
-    t_seq32, _e_s32 = sequential(leaf, PB_FP32_IR)
-    _log(f"sequential refined FP32 (leaf {leaf}): {t_seq32:.3f} s")
-    rel = float(np.max(np.abs(np.asarray(e_b) - np.asarray(e_s)) / np.abs(e_s)))
-    rel0 = float(np.max(np.abs(np.asarray(e_b) - np.asarray(e_s0)) / np.abs(e_s0)))
-    out = {
-        "mode": "batch",
-        "metric": "solves/s (E_sol + forces), batched vs one-at-a-time FP64",
+    seq = {}
+    for name, precision in (("sequential_fp64", PB_FP64), ("sequential_fp32_ir", PB_FP32_IR)):
+        tol_s, err_s = pick(lambda t: sequential(precision, t)[1])
+        t_s, _e = sequential(precision, tol_s)
+        seq[name] = {"seconds": t_s, "solves_per_s": len(systems) / t_s, "tol": tol_s,
+                     "worst_e_rel_err": err_s, "speedup_of_batch": t_s / t_batch}
+        _log(f"bench batch: {name} {t_s:.3f} s at tol {tol_s:g}")
+    return {
+        "workload": "64 star surfaces, 5,120-81,920 triangles, 100-2,000 charges (seed 5); "
+                    "E_sol + forces",
         "n_sys": len(systems),
         "total_triangles": int(sum(n_tri)),
         "pairs_per_batched_matvec": pairs,
         "precision": "FP32 matvec + FP64 restart residuals" if prec == PB_FP32_IR else "FP64",
         "precond_leaf": leaf,
-        "tol": tol,
+        "tol": tol_b,
+        "worst_e_rel_err": energy_err(e_b),
+        "worst_force_rel_err_vs_fp64_tol1e-12": force_err(g_b),
         "autotuned": {"sweep_kind": sweep_label(tuned_kind), "tiles_per_item": tuned_tiles},
         "batched_s": t_batch,
-        "batched_solves_per_s": len(systems) / t_batch,
-        "sequential_fp64_same_preconditioner_s": t_seq,
-        "sequential_solves_per_s": len(systems) / t_seq,
-        "speedup": t_seq / t_batch,
-        "sequential_fp64_no_preconditioner_s": t_seq0,
-        "speedup_vs_unpreconditioned_fp64": t_seq0 / t_batch,
-        "sequential_fp32ir_same_preconditioner_s": t_seq32,
-        "speedup_vs_sequential_fp32ir": t_seq32 / t_batch,
-        "max_rel_energy_diff_vs_sequential": rel,
-        "max_rel_energy_diff_vs_unpreconditioned": rel0,
+        "solves_per_s": len(systems) / t_batch,
         "arnoldi_steps_forward_max": max(i.iters for i in inf_b),
         "arnoldi_steps_adjoint_max": max(i.adjoint_iters for i in inf_b),
-        "matvec_gpairs_per_s_batched": sum(
-            (i.matvecs_fp32 + i.matvecs_fp64) * float(n) * (n - 1)
-            for i, n in zip(inf_b, n_tri)) / t_batch / 1e9,
+        "matvec_gpairs_per_s": sum((i.matvecs_fp32 + i.matvecs_fp64) * float(n) * (n - 1)
+                                   for i, n in zip(inf_b, n_tri)) / t_batch / 1e9,
+        **seq,
     }
-    ctx.close()
-    print(json.dumps(out), flush=True)
 
 
-def _tree_record(ctx, w, args, pbs, Params, PB_FP64, PB_FP32_IR, PB_SWEEP_PAIRWISE):
+def _tree_record(ctx, w, args, pbs, Params, PB_FP64, PB_FP32_IR):
     import numpy as np
     import torch
     N = w.n_tri
@@ -262,15 +474,13 @@ def run_tree(args):
         works = [synth.star_protein(freq=int(f), r0=20.0 * int(f) / 64.0, n_charges=1, seed=2)
                  for f in args.tree_freqs.split(",")]
     else:
-        works = [synth.star_protein() if args.workload == "star81920"
-                 else synth.large_star_protein()]
+        works = [make_workload(args.workload)]
     ctx = Context(0)
     ctx.set_sweep_config(PB_SWEEP_PAIRWISE, 0)
     recs = []
     for w in works:
         _log(f"bench tree: {w.n_tri} triangles")
-        recs.append(_tree_record(ctx, w, args, pbs, Params, PB_FP64, PB_FP32_IR,
-                                 PB_SWEEP_PAIRWISE))
+        recs.append(_tree_record(ctx, w, args, pbs, Params, PB_FP64, PB_FP32_IR))
     solve_cmp = None
     if len(works) == 1:
         # whole solves: treecode GMRES against the direct solves, same preconditioner
@@ -316,7 +526,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32-ir", "fp64"], default="fp32-ir")
-    ap.add_argument("--workload", choices=["star81920", "star327680"], default="star81920")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="star327680",
+                    help="headline workload (default: 327,680 triangles, 10,000 charges)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 81,920-triangle leg of the solve benchmark")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-system batch leg of the solve benchmark")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--theta", type=float, default=0.8, help="treecode MAC parameter (mode tree)")
@@ -329,8 +544,8 @@ def main():
                     default="solve",
                     help="solve: the benchmark; matvec: only --steps matvecs of --precision "
                          "(for counter runs); copy: a device copy of --copy-mib MiB (the "
-                         "reference kernel that calibrates FETCH_SIZE/WRITE_SIZE); batch: 64 "
-                         "uneven systems in one call; tree: treecode matvec vs the direct sums")
+                         "reference kernel that calibrates FETCH_SIZE/WRITE_SIZE); batch: only "
+                         "the 64-system leg; tree: treecode matvec vs the direct sums")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--precond-leaf", type=int, default=24,
                     help="leaf size of the block-diagonal preconditioner (0 = none)")
@@ -345,7 +560,6 @@ def main():
     import numpy as np
     import torch
 
-    import synth
     from paper_2312_10044_amd import Context, Params, PB_FP64, PB_FP32_IR
     from paper_2312_10044_amd import pbsolve as pbs
 
@@ -362,30 +576,17 @@ def main():
         print(json.dumps({"mode": "copy", "bytes_read": n * 8, "bytes_written": n * 8,
                           "launches": max(1, args.steps)}), flush=True)
         return
-    if args.mode == "batch":
-        run_batch(args)
-        return
     if args.mode == "tree":
         run_tree(args)
         return
-    if args.workload == "star81920":
-        w = synth.star_protein()
-    else:
-        w = synth.large_star_protein()
+    ctx = Context(0, torch.cuda.current_stream())
+    if args.mode == "batch":
+        out = {"mode": "batch", **batch_leg(ctx, args, max(1, args.steps))}
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
+    w = make_workload(args.workload)
     N = w.n_tri
-    _log(f"bench: workload {w.name}: {N} triangles, {w.n_charges} charges")
-    tv = torch.from_numpy(w.verts).to(dev)
-    tt = torch.from_numpy(w.tris.astype(np.int32)).to(dev)
-    tp = torch.from_numpy(w.pos).to(dev)
-    tq = torch.from_numpy(w.q).to(dev)
-    phi = torch.empty(N, dtype=torch.float64, device=dev)
-    dphi = torch.empty_like(phi)
-    stream = torch.cuda.current_stream()
-    ctx = Context(0, stream)
-
-    def solve(params):
-        return ctx.pb_solve_dev(tv, tt, tp, tq, params, phi, dphi)
-
     base = dict(eps_in=w.eps_in, eps_out=w.eps_out, kappa=w.kappa, restart=10, max_iter=2000)
     if args.autotune:
         tuned = ctx.pb_autotune(w.verts, w.tris, Params(**base))
@@ -395,6 +596,8 @@ def main():
          f"({'autotuned' if args.autotune else 'library default'})")
     if args.mode == "matvec":
         prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
+        tv = torch.from_numpy(w.verts).to(dev)
+        tt = torch.from_numpy(w.tris.astype(np.int32)).to(dev)
         x = torch.from_numpy(np.random.default_rng(0).normal(size=2 * N)).to(dev)
         y = torch.empty_like(x)
         ctx.profile_reset()
@@ -415,108 +618,26 @@ def main():
                           "fp32_sweep": list(tuned)}), flush=True)
         ctx.close()
         return
-    ref = solve(Params(tol=1e-12, precision=PB_FP64, **base))
-    e_ref = ref.e_solv
-    _log(f"bench: FP64 reference E={e_ref:.10f} (tol 1e-12, {ref.iters} iterations)")
 
-    def pick(precision, leaf):
-        for tol in TOL_LADDER:
-            if precision == PB_FP32_IR:
-                p = Params(tol=tol, precision=PB_FP32_IR, inner_tol=0.1 * tol,
-                           max_refine=20, precond_leaf=leaf, **base)
-            else:
-                p = Params(tol=tol, precision=PB_FP64, precond_leaf=leaf, **base)
-            info = solve(p)
-            err = abs(info.e_solv - e_ref) / abs(e_ref)
-            _log(f"bench: precision={precision} leaf={leaf} tol={tol:g} E err={err:.2e} "
-                 f"iters={info.iters} t={info.seconds:.3f}s")
-            if err <= E_TARGET and info.status == 0:
-                return p, err
-        raise RuntimeError("no tolerance on the ladder reached the energy target")
-
-    def timed_once(p):
-        solve(p)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info = solve(p)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        return {"time_to_solution_s": dt, "tol": p.tol, "iters": info.iters,
-                "matvecs_fp32": info.matvecs_fp32, "matvecs_fp64": info.matvecs_fp64,
-                "e_rel_err": abs(info.e_solv - e_ref) / abs(e_ref),
-                "gpairs_per_s": (info.matvecs_fp32 + info.matvecs_fp64) * float(N) * (N - 1)
-                / dt / 1e9}
-
+    head = solve_leg(ctx, w, args.workload, args, args.steps, args.warmup,
+                     compare=not args.no_fp64_compare, host_arrays=True)
+    legs = {}
+    if not args.no_secondary and args.workload != "star81920":
+        w2 = make_workload("star81920")
+        legs["star81920"] = solve_leg(ctx, w2, "star81920", args, max(args.steps, 5), max(args.warmup, 1),
+                                      compare=False, host_arrays=False)
+    if not args.no_batch:
+        legs["batch64"] = batch_leg(ctx, args, max(1, min(args.steps, 3)))
+    ctx.close()
     prec = PB_FP32_IR if args.precision == "fp32-ir" else PB_FP64
-    leaf = args.precond_leaf
-    params, err_pick = pick(prec, leaf)
-
-    for _ in range(args.warmup):
-        solve(params)
-    ctx.profile_reset()
-    ctx.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    step_s = []
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        infos.append(solve(params))   # returns once E_solv is on the host
-        step_s.append(time.perf_counter() - ts)
-        _log(f"bench: step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.profile_enable(False)
-    elapsed = t1 - t0
-    ms_step = 1e3 * elapsed / args.steps
-    pairs_per_mv = float(N) * float(N - 1)
-    n_mv = sum(i.matvecs_fp32 + i.matvecs_fp64 for i in infos)
-    value = n_mv * pairs_per_mv / elapsed / 1e9
-    errs = [abs(i.e_solv - e_ref) / abs(e_ref) for i in infos]
-
-    dom = pbs.PB_KERNEL_PAIRS_FP32 if prec == PB_FP32_IR else pbs.PB_KERNEL_PAIRS_FP64
-    launches, kms, kpairs = ctx.profile_read(dom)
-    avg_ms = kms / max(launches, 1)
-    achieved = FLOP_PER_PAIR * (kpairs / max(launches, 1)) / (avg_ms * 1e-3)
-    peak = PEAK_FP32_VECTOR if prec == PB_FP32_IR else PEAK_FP64_VECTOR
-    kernel_rows = {}
-    for name, kid in (("pairs_fp32", pbs.PB_KERNEL_PAIRS_FP32), ("pairs_fp64", pbs.PB_KERNEL_PAIRS_FP64),
-                      ("source", pbs.PB_KERNEL_SOURCE), ("charge", pbs.PB_KERNEL_CHARGE)):
-        n_l, ms_l, pr_l = ctx.profile_read(kid)
-        if n_l:
-            kernel_rows[name] = {"launches": n_l, "avg_ms": ms_l / n_l,
-                                 "gpairs_per_s": pr_l / (ms_l * 1e-3) / 1e9}
-
-    # the same solve through the host-array entry point (surface and charges
-    # copied in, phi/dphi copied out over PCIe): reported beside `value`,
-    # which stays the device-resident rate
-    ctx.pb_solve(w.verts, w.tris, w.pos, w.q, params)
-    host_s = []
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        ctx.pb_solve(w.verts, w.tris, w.pos, w.q, params)
-        host_s.append(time.perf_counter() - ts)
-    _log(f"bench: host-array solves: median {1e3 * float(np.median(host_s)):.2f} ms")
-
-    compare = {}
-    if not args.no_fp64_compare:
-        variants = [("fp64_same_preconditioner", PB_FP64, leaf),
-                    ("fp32_ir_no_preconditioner", PB_FP32_IR, 0),
-                    ("fp64_no_preconditioner", PB_FP64, 0)]
-        for name, pr, lf in variants:
-            if pr == prec and lf == leaf:
-                continue
-            pv, _e = pick(pr, lf)
-            compare[name] = timed_once(pv)
-
     out = {
         "metric": "BIE matvec G-pair-interactions/s; time to E_solv at 1e-6 rel. error",
-        "value": value,
+        "value": head["value"],
         "unit": "G pair-interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -528,42 +649,19 @@ def main():
             "n_tri": N,
             "n_charges": w.n_charges,
             "precision": "FP32 matvec + FP64 refinement" if prec == PB_FP32_IR else "FP64",
-            "precond_leaf": leaf,
-            "tol": params.tol,
-            "inner_tol": params.inner_tol if prec == PB_FP32_IR else None,
+            "precond_leaf": args.precond_leaf,
+            "tol": head["tol"],
+            "tol_ladder": TOL_LADDER,
+            "inner_tol": head["inner_tol"],
             "gmres_restart": 10,
-            "fp32_sweep": {"kind": sweep_label(tuned[0]), "target_waves": tuned[1]},
+            "fp32_sweep": head["fp32_sweep"],
         },
-        "time_to_solution_s": ms_step / 1e3,
-        "time_to_solution_median_s": float(np.median(step_s)),
-        "time_to_solution_host_arrays_median_s": float(np.median(host_s)),
-        "step_s": [round(t, 6) for t in step_s],
-        "e_solv": infos[-1].e_solv,
-        "e_rel_err": max(errs),
-        "iters": infos[-1].iters,
-        "matvecs_fp32": infos[-1].matvecs_fp32,
-        "matvecs_fp64": infos[-1].matvecs_fp64,
-        "refinements": infos[-1].refinements,
-        "kernels": kernel_rows,
-        "compare": compare,
-        "roofline": {
-            "bound": "alu",
-            "kernel": (fp32_kernel_name(tuned[0]) if prec == PB_FP32_IR
-                       else fp64_kernel_name(ctx.get_fp64_sweep())),
-            "achieved": achieved / 1e12,
-            "peak": peak / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / peak,
-            "traffic": (measured_traffic(N, tuned) if prec == PB_FP32_IR else None),
-            "traffic_unit": "bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
-            "flop_per_pair": FLOP_PER_PAIR,
-            "pairs_per_launch": kpairs / max(launches, 1),
-            "avg_launch_ms": avg_ms,
-            "launches": launches,
-        },
+        "time_to_solution_s": head["ms_per_step"] / 1e3,
+        "roofline": head.pop("roofline"),
         "cpu_baseline": None,
+        **{k: v for k, v in head.items() if k not in ("value", "ms_per_step")},
+        "legs": legs,
     }
-    ctx.close()
     if not args.no_cpu_baseline:
         _log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w)

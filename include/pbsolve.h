@@ -43,9 +43,14 @@ extern "C" {
 /* status codes */
 #define PB_OK 0
 #define PB_NOT_CONVERGED 1      /* outputs hold the last iterate; info->rel_residual set */
-#define PB_ERR_ARG (-1)         /* NULL pointer, n <= 0, eps <= 0, kappa < 0, tol <= 0, restart < 1 ... */
+#define PB_ERR_ARG (-1)         /* NULL pointer, n <= 0, eps <= 0, kappa outside [0, 100],
+                                   tol <= 0, restart < 1 ... */
 #define PB_ERR_GEOMETRY (-2)    /* non-finite vertex, index out of range, zero-area triangle,
-                                   non-positive enclosed volume (wrong orientation) */
+                                   centroid coordinate beyond 1e5 A, two triangles with the
+                                   same centroid (the singular j = i term is skipped by
+                                   index, eqs. eqbim_5/eqbim_6), non-positive enclosed
+                                   volume (wrong orientation); the message names the
+                                   offending triangle where there is one */
 #define PB_ERR_CHARGE (-3)      /* a charge outside the surface (discrete solid angle < 2 pi) */
 #define PB_ERR_HIP (-4)         /* HIP runtime error */
 #define PB_ERR_OOM (-5)         /* device allocation failed */
@@ -72,7 +77,7 @@ typedef struct {
 
 typedef struct {
     double eps_in, eps_out;     /* dielectric constants inside / outside (> 0) */
-    double kappa;               /* inverse Debye length outside, 1/A (>= 0) */
+    double kappa;               /* inverse Debye length outside, 1/A (0 <= kappa <= 100) */
     double tol;                 /* relative residual |b - A x|_2 / |b|_2 at which to stop */
     int32_t restart;            /* GMRES restart length m (>= 1; the paper's runs use 10) */
     int32_t max_iter;           /* cap on Arnoldi steps (FP64) / outer refinements x inner cap (IR) */
@@ -295,6 +300,15 @@ int pb_get_batch_tiles(pb_ctx *ctx, int *tiles);
 int pb_autotune_batch(pb_ctx *ctx, int32_t n_sys, const pb_surface *surfaces,
                       const pb_charges *charges, const pb_params *p, int *best_kind,
                       int *best_tiles);
+
+/* ---- device memory ------------------------------------------------------ */
+/* Cap on the device memory the context holds as scratch (bytes; 0 = no cap,
+ * the default).  A call that would grow the context's buffers past the cap
+ * fails with PB_ERR_OOM before allocating, and the context stays usable;
+ * buffers already held are kept.  For processes that share a GPU.
+ * pb_get_memory_used reports the bytes held now. */
+int pb_set_memory_limit(pb_ctx *ctx, int64_t bytes);
+int pb_get_memory_used(pb_ctx *ctx, int64_t *bytes);
 
 /* ---- kernel timing hook (benchmarks, profiling) ------------------------ */
 /* When enabled, every launch of the kernels below is bracketed by a pair of

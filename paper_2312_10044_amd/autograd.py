@@ -4,13 +4,15 @@
 0-d float64 device tensor.  The surface is held fixed; gradients flow to the
 charge positions and charges.  When either needs a gradient the forward call
 runs the forward and adjoint solves together (pb_forces_dev) and keeps
-dE/dpos, dE/dq for the backward pass, which only scales them.
+dE/dpos, dE/dq for the backward pass, which only scales them.  A solve that
+stops before its tolerance (PB_NOT_CONVERGED) raises PbError instead of
+returning an unconverged energy.
 """
 from __future__ import annotations
 
 import torch
 
-from .pbsolve import Context, Params
+from .pbsolve import Context, Params, PbError, PB_OK
 
 
 class PBEnergy(torch.autograd.Function):
@@ -26,6 +28,12 @@ class PBEnergy(torch.autograd.Function):
             fctx.save_for_backward(gpos, gq)
         else:
             info = ctx.pb_solve_dev(verts, tris, pos_c, q_c, params)
+        if info.status != PB_OK:
+            # an energy or gradient of an unconverged solve is not E_sol
+            raise PbError(info.status,
+                          f"GMRES stopped before tol {params.tol:g} (relative residual "
+                          f"{info.rel_residual:.3e}, forward {info.iters} and adjoint "
+                          f"{info.adjoint_iters} Arnoldi steps); raise max_iter or max_refine")
         fctx.info = info
         return torch.tensor(info.e_solv, dtype=torch.float64, device=pos.device)
 

@@ -877,6 +877,7 @@ struct BatchPlan {
     std::vector<SItem> sitems;
     std::vector<int32_t> rs;
     int64_t n_slots = 0, cptot = 0;
+    double sigma_min = 1.0;   // FP32 length unit bound: 1 / the largest system's length scale
 };
 
 // Pairwise work items: row tile I of every system against its tiles I.. in
@@ -1010,18 +1011,18 @@ void enqueue_matvec(pb_ctx *c, const BatchPlan &P, BatchDev &D, bool f32, int tr
         // swapped and scaled by -sigma^2/eps and sigma^3 (as in the single-
         // system sweep)
         const unsigned sgrid = item_grid(nsi);
-        const double sig = f32_sigma(kap);
+        const double sig = f32_sigma(kap, P.sigma_min);
         const double keps = trans ? 1.0 / eps : eps;
         hipLaunchKernelGGL(kb_pack_sym, dim3(gb), dim3(TPB), 0, s, D.g, P.gtot, D.sd, D.blk2sys,
                            x, reinterpret_cast<Src12 *>(D.src), eps, sig, trans ? 1 : 0);
-        if (kap > 0.0)
+        if (kap > 0.0 && sig == kap)
             hipLaunchKernelGGL(kb_pairs_f32_sym<true>, dim3(sgrid), dim3(SYM_NT), 0, s,
                                reinterpret_cast<const Src12 *>(D.src), D.sd, D.sitems, nsi, mask,
-                               keps, kap, D.srow, static_cast<float *>(D.scol));
+                               keps, 1.0, D.srow, static_cast<float *>(D.scol));
         else
             hipLaunchKernelGGL(kb_pairs_f32_sym<false>, dim3(sgrid), dim3(SYM_NT), 0, s,
                                reinterpret_cast<const Src12 *>(D.src), D.sd, D.sitems, nsi, mask,
-                               keps, kap, D.srow, static_cast<float *>(D.scol));
+                               keps, kap / sig, D.srow, static_cast<float *>(D.scol));
         const double s1 = trans ? -sig * sig / eps : eps * sig * sig;
         hipLaunchKernelGGL(kb_sym_finish<float>, dim3(gb), dim3(TPB), 0, s, D.srow,
                            static_cast<const float *>(D.scol), D.rs, D.g, P.gtot, D.sd,
@@ -1365,6 +1366,10 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     TRY(ensure(c, c->in_tri, sizeof(int32_t) * 3 * max_nt));
     TRY(ensure(c, c->geo_part, sizeof(double) * GEO_RED * gblk));
     TRY(ensure(c, c->small, sizeof(double) * HSMALL));
+    const int64_t dcap = dup_table_size(max_nt);
+    TRY(ensure(c, c->dup_tab, sizeof(int32_t) * (dcap + 2)));
+    int32_t *hdup = reinterpret_cast<int32_t *>(c->hsmall + HSMALL_DUP);
+    double max_len = 0.0;
     for (int b = 0; b < n_sys; ++b) {
         SysDesc &d = P.sd[b];
         TRY(upload(c, c->in_vert.p, surf[b].vert, sizeof(double) * 3 * surf[b].n_vert));
@@ -1374,18 +1379,32 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
                         D.g + d.goff, d.npad, P.gtot, as<double>(c->geo_part), nb);
         launch_reduce_cols(s, as<double>(c->geo_part), nb, GEO_RED, as<double>(c->small));
         LAUNCHCHK();
+        launch_dup_check(s, D.g + d.goff, d.n, P.gtot, as<int32_t>(c->dup_tab), dcap);
+        LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(c->hsmall, c->small.p, sizeof(double) * GEO_RED,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hdup, as<int32_t>(c->dup_tab) + dcap, sizeof(int32_t) * 2,
                               hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         const double *r = c->hsmall;
         if (r[0] != 0.0)
             return fail(c, PB_ERR_GEOMETRY, "system %d: %.0f bad triangle(s)", b, r[0]);
+        if (r[6] != 0.0)
+            return fail(c, PB_ERR_GEOMETRY,
+                        "system %d: %.0f triangle(s) with a centroid coordinate beyond %g A", b,
+                        r[6], COORD_MAX);
+        if (hdup[1] != 0)
+            return fail(c, PB_ERR_GEOMETRY,
+                        "system %d: triangle %d shares its centroid with another triangle", b,
+                        hdup[0]);
         if (!(r[1] > 0.0))
             return fail(c, PB_ERR_GEOMETRY, "system %d: non-positive enclosed volume", b);
+        max_len = std::max(max_len, std::sqrt(r[5] / (2.0 * TWO_PI)));
         d.cx = r[2] / (double)d.n;
         d.cy = r[3] / (double)d.n;
         d.cz = r[4] / (double)d.n;
     }
+    P.sigma_min = 1.0 / max_len;
     // charges, padded per system (padding repeats the last charge with q = 0)
     {
         std::vector<double> hp(3 * P.ctot), hq(P.ctot, 0.0);

@@ -32,8 +32,8 @@ int check_params(pb_ctx *c, const pb_params *p, bool solving)
     if (!(p->eps_in > 0.0) || !(p->eps_out > 0.0) || !std::isfinite(p->eps_in) ||
         !std::isfinite(p->eps_out))
         return fail(c, PB_ERR_ARG, "eps_in and eps_out must be finite and > 0");
-    if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa))
-        return fail(c, PB_ERR_ARG, "kappa must be finite and >= 0");
+    if (!(p->kappa >= 0.0) || !(p->kappa <= KAPPA_MAX))
+        return fail(c, PB_ERR_ARG, "kappa must lie in [0, %g] 1/A", KAPPA_MAX);
     if (solving) {
         if (!(p->tol > 0.0))
             return fail(c, PB_ERR_ARG, "tol must be > 0");
@@ -78,8 +78,16 @@ int setup_geometry(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_ver
     LAUNCHCHK();
     launch_reduce_cols(c->stream, as<double>(c->geo_part), nblk, GEO_RED, as<double>(c->small));
     LAUNCHCHK();
+    // coincident centroids (the singular term is dropped by index only)
+    const int64_t cap = dup_table_size(n_tri);
+    TRY(ensure(c, c->dup_tab, sizeof(int32_t) * (cap + 2)));
+    launch_dup_check(c->stream, as<double>(c->geo), n_tri, npad, as<int32_t>(c->dup_tab), cap);
+    LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(c->hsmall, c->small.p, sizeof(double) * GEO_RED, hipMemcpyDeviceToHost,
                           c->stream));
+    int32_t *hdup = reinterpret_cast<int32_t *>(c->hsmall + HSMALL_DUP);
+    HIPCHK(hipMemcpyAsync(hdup, as<int32_t>(c->dup_tab) + cap, sizeof(int32_t) * 2,
+                          hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     const double *r = c->hsmall;
     c->g.g = as<double>(c->geo);
@@ -89,6 +97,14 @@ int setup_geometry(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_ver
         return fail(c, PB_ERR_GEOMETRY,
                     "%.0f triangle(s) with an out-of-range index, a non-finite vertex or zero area",
                     r[0]);
+    if (r[6] != 0.0)
+        return fail(c, PB_ERR_GEOMETRY,
+                    "%.0f triangle(s) with a centroid coordinate beyond %g A", r[6], COORD_MAX);
+    if (hdup[1] != 0)
+        return fail(c, PB_ERR_GEOMETRY,
+                    "triangle %d shares its centroid with another triangle (%d coincident "
+                    "pair(s)): collocation points must be distinct",
+                    hdup[0], hdup[1]);
     c->volume = r[1] / 6.0;
     c->area_sum = r[5];
     if (!(c->volume > 0.0))
@@ -99,6 +115,8 @@ int setup_geometry(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_ver
     c->center[0] = r[2] / (double)n_tri;
     c->center[1] = r[3] / (double)n_tri;
     c->center[2] = r[4] / (double)n_tri;
+    // the mesh's length scale: radius of the sphere of the same area
+    c->sigma_min = 1.0 / std::sqrt(c->area_sum / (2.0 * TWO_PI));
     return PB_OK;
 }
 
@@ -110,6 +128,7 @@ PairParams pair_params(pb_ctx *c, const pb_params *p)
     pp.cx = c->center[0];
     pp.cy = c->center[1];
     pp.cz = c->center[2];
+    pp.sigma = f32_sigma(p->kappa, c->sigma_min);
     return pp;
 }
 
@@ -147,7 +166,7 @@ int apply_pairwise(pb_ctx *c, const pb_params *p, int transpose, const double *x
     TRY(ensure(c, c->sym_colpart,
                sizeof(float) * 2 * TILE * (size_t)std::max<int64_t>(T * (T - 1) / 2, 1)));
     const PairParams pp = pair_params(c, p);
-    const double eps = pp.eps, sig = f32_sigma(pp.kappa);
+    const double eps = pp.eps, sig = pp.sigma;
     launch_pack_sym(c->stream, g, x, as<float>(c->sym_src), pp.cx, pp.cy, pp.cz, eps, sig,
                     transpose ? 1 : 0);
     LAUNCHCHK();
@@ -159,7 +178,7 @@ int apply_pairwise(pb_ctx *c, const pb_params *p, int transpose, const double *x
                              as<double>(c->sym_rowpart), as<float>(c->sym_colpart));
     }
     LAUNCHCHK();
-    // lengths in units of 1/kappa: row 1 sums P / (eps sigma^2) forward and
+    // lengths in units of 1/sigma: row 1 sums P / (eps sigma^2) forward and
     // -eps P^T / sigma^2 transposed, row 2 sums Q / sigma^3
     const double s1 = transpose ? -sig * sig / eps : eps * sig * sig;
     launch_sym_finish(c->stream, g, as<double>(c->sym_rowpart), as<float>(c->sym_colpart),
@@ -219,7 +238,7 @@ int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
     const double npairs = (double)g.n * (double)(g.n - 1);
     double scale1 = 1.0, scale2 = 1.0;
     if (fast32) {
-        const double sig = f32_sigma(pp.kappa);
+        const double sig = pp.sigma;
         TRY(ensure(c, c->src32, sizeof(float) * 8 * g.npad));
         launch_pack_f32(c->stream, g, x, as<float>(c->src32), 2, pp.cx, pp.cy, pp.cz, eps, sig);
         LAUNCHCHK();
@@ -1126,7 +1145,7 @@ void pb_destroy(pb_ctx *c)
                       &c->t_nodes,
                       &c->t_ctr, &c->t_perm, &c->t_geo, &c->t_wv, &c->t_out, &c->t_mom,
                       &c->t_cnt, &c->b_sitems, &c->b_rs, &c->b_srow, &c->b_scol,
-                      &c->b_pc_sys};
+                      &c->b_pc_sys, &c->dup_tab};
     for (DevBuf *b : bufs)
         if (b->p)
             (void)hipFree(b->p);
@@ -1815,6 +1834,24 @@ int pb_get_batch_tiles(pb_ctx *c, int *tiles)
     if (!c || !tiles)
         return PB_ERR_ARG;
     *tiles = c->b_sym_tiles;
+    return PB_OK;
+}
+
+int pb_set_memory_limit(pb_ctx *c, int64_t bytes)
+{
+    if (!c)
+        return PB_ERR_ARG;
+    if (bytes < 0)
+        return fail(c, PB_ERR_ARG, "memory limit must be >= 0");
+    c->mem_limit = (size_t)bytes;
+    return PB_OK;
+}
+
+int pb_get_memory_used(pb_ctx *c, int64_t *bytes)
+{
+    if (!c || !bytes)
+        return PB_ERR_ARG;
+    *bytes = (int64_t)c->mem_used;
     return PB_OK;
 }
 

@@ -35,6 +35,8 @@ struct pb_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     pbk::ErrorState err;
+    size_t mem_used = 0;    // bytes held in device buffers (DevBuf capacities)
+    size_t mem_limit = 0;   // pb_set_memory_limit; 0 = none
     // device scratch
     pbk::DevBuf geo, geo_part, src64, src32, part, vec, V, small, dpart, chg_part, chg_per;
     pbk::DevBuf in_vert, in_tri, in_pos, in_q, io_x, io_y;
@@ -77,6 +79,8 @@ struct pb_ctx {
     pbk::Geo g{};
     double center[3] = {0.0, 0.0, 0.0};
     double volume = 0.0, area_sum = 0.0;
+    double sigma_min = 1.0;   // inverse length scale of the mesh (f32_sigma)
+    pbk::DevBuf dup_tab;      // coincident-centroid check (launch_dup_check)
     // block-diagonal preconditioner of the current geometry
     pbk::DevBuf pc_idx, pc_inv;
     int64_t pc_leaves = 0;
@@ -94,6 +98,16 @@ struct pb_ctx {
 namespace pbk {
 
 constexpr int HSMALL = 4 * (MAX_RESTART + 2) + 64;
+constexpr int HSMALL_DUP = HSMALL - 6;   // two int32: the coincident-centroid verdict
+
+// Slots of the coincident-centroid hash table for n points: a power of two >= 2n.
+inline int64_t dup_table_size(int64_t n)
+{
+    int64_t cap = 1024;
+    while (cap < 2 * n)
+        cap *= 2;
+    return cap;
+}
 
 inline int fail(pb_ctx *c, int code, const char *fmt, ...)
 {
@@ -133,10 +147,16 @@ inline int ensure(pb_ctx *c, DevBuf &b, size_t bytes)
 {
     if (bytes <= b.cap)
         return PB_OK;
+    if (c->mem_limit && c->mem_used - b.cap + bytes > c->mem_limit)
+        return fail(c, PB_ERR_OOM,
+                    "device scratch of %zu bytes would pass the context's limit of %zu bytes "
+                    "(%zu held)",
+                    bytes, c->mem_limit, c->mem_used);
     if (b.p) {
         HIPCHK(hipStreamSynchronize(c->stream));
         HIPCHK(hipFree(b.p));
     }
+    c->mem_used -= b.cap;
     b.p = nullptr;
     b.cap = 0;
     hipError_t e = hipMalloc(&b.p, bytes);
@@ -146,6 +166,7 @@ inline int ensure(pb_ctx *c, DevBuf &b, size_t bytes)
         return fail(c, PB_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     }
     b.cap = bytes;
+    c->mem_used += bytes;
     return PB_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <cmath>
 
+#include "pb_fp64math.h"
 #include "pb_kernels.h"
 
 namespace pbk {
@@ -448,43 +449,14 @@ __device__ __forceinline__ void sweep_pairwise(const SrcTileF32 &sh, const OwnF3
 }
 
 
-// exp(-x) for 0 <= x <= 700, the range of kappa r on a pair: no overflow,
-// underflow or special value can occur, so the general function's range
-// checks are left out.  Cody-Waite reduction: e^-x = 2^-n e^g with
-// n = rint(x / ln 2) and g = n ln 2 - x, |g| <= ln 2 / 2, where ln 2 is split
-// into a 32-bit head (n times it is exact) and the rounded remainder.  e^g is
-// its Taylor series to degree 12, whose truncation error on that interval is
-// below 2.4e-16 relative.
-__device__ __forceinline__ double exp_neg_pair(double x)
-{
-    const double n = __builtin_rint(x * 1.4426950408889634);
-    const double g = fma(n, 1.9082149292705877e-10, fma(n, 0.6931471803691238, -x));
-    double p = 2.08767569878681e-09;          // 1/12!
-    p = fma(p, g, 2.505210838544172e-08);     // 1/11!
-    p = fma(p, g, 2.755731922398589e-07);
-    p = fma(p, g, 2.7557319223985893e-06);
-    p = fma(p, g, 2.48015873015873e-05);
-    p = fma(p, g, 0.0001984126984126984);
-    p = fma(p, g, 0.001388888888888889);
-    p = fma(p, g, 0.008333333333333333);
-    p = fma(p, g, 0.041666666666666664);
-    p = fma(p, g, 0.16666666666666666);
-    p = fma(p, g, 0.5);
-    p = fma(p, g, 1.0);
-    p = fma(p, g, 1.0);
-    return ldexp(p, -(int)n);
-}
+using fm::exp_neg_pair;
 
-// 1/sqrt(x) for finite x > 0: the hardware estimate y refined by one
-// third-order Householder step, y (1 + e/2 + 3 e^2/8) with e = 1 - x y^2 (the
-// series of (1 - e)^(-1/2)), which takes the estimate's relative error eps to
-// about (5/16) eps^3.  x = 0 gives NaN; callers that can meet it replace the
-// result.
+// 1/sqrt(x) for finite x > 0: the hardware estimate (relative error below
+// 2^-22) refined by fm::rsqrt_refine to about one ulp.  x = 0 gives NaN;
+// callers that can meet it replace the result.
 __device__ __forceinline__ double rsqrt_pos(double x)
 {
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-x * y, y, 1.0);
-    return fma(y * e, fma(e, 0.375, 0.5), y);
+    return fm::rsqrt_refine(x, __builtin_amdgcn_rsq(x));
 }
 
 // ---- pairwise FP64 sweep ------------------------------------------------------

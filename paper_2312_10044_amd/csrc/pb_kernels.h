@@ -12,7 +12,9 @@ namespace pbk {
 constexpr int TPB = 256;        // threads per block of every pair kernel
 constexpr int TILE = 256;       // sources staged in LDS per step (== TPB)
 constexpr int NGEO = 7;         // cx, cy, cz, nx, ny, nz, area
-constexpr int GEO_RED = 6;      // bad, 6*volume, sum cx, sum cy, sum cz, sum area
+constexpr int GEO_RED = 7;      // bad, 6*volume, sum cx, sum cy, sum cz, sum area, far
+constexpr double COORD_MAX = 1.0e5;   // |centroid coordinate| bound, A (padding sits at 2e6)
+constexpr double KAPPA_MAX = 100.0;   // 1/A: kappa r stays < 1.4e9 for every padded pair
 constexpr int MAX_RESTART = 64;
 constexpr int PADN = 512;       // collocation arrays are padded to a multiple of this
 constexpr int PC_MAX_LEAF = 32; // largest preconditioner leaf (its 2m x 2m block lives in LDS)
@@ -28,6 +30,7 @@ struct PairParams {
     double eps;         // eps_out / eps_in
     double kappa;
     double cx, cy, cz;  // origin subtracted from positions before FP32 arithmetic
+    double sigma;       // FP32 length unit: positions are multiplied by it (f32_sigma)
 };
 
 // Launch shape of one pair sweep: targets in blocks of TPB, sources split
@@ -57,10 +60,27 @@ void launch_geometry(hipStream_t s, int64_t n_vert, int64_t n_tri, const double 
 void launch_pack_f64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode);
 void launch_pack_f32(hipStream_t s, const Geo &geo, const double *x, float *src, int mode,
                      double cx, double cy, double cz, double eps, double sigma);
-// Length scale of the reduced FP32 form: coordinates are measured in units of
-// 1/kappa, so kappa r is the distance itself (1 when kappa = 0).  Row 1 of
-// the sweep then carries a factor sigma^2 and row 2 a factor sigma^3.
-inline double f32_sigma(double kappa) { return kappa > 0.0 ? kappa : 1.0; }
+// Length unit of the reduced FP32 form: positions are multiplied by sigma.
+// sigma = kappa makes kappa r the distance itself (the SCALED kernels).  When
+// kappa is below sigma_min, the inverse of the mesh's own length scale (and at
+// kappa = 0), the unit is 1/sigma_min and the kernels take kappa / sigma:
+// bounding sigma from below keeps (sigma r)^-3 of the nearest pairs far from
+// FP32 overflow however small kappa is.  Row 1 of the sweep carries a factor
+// sigma^2 and row 2 a factor sigma^3.
+inline double f32_sigma(double kappa, double sigma_min)
+{
+    return kappa >= sigma_min ? kappa : sigma_min;
+}
+inline bool f32_scaled(const PairParams &pp) { return pp.kappa > 0.0 && pp.sigma == pp.kappa; }
+
+// Exact coincidence of collocation points: the singular term is skipped by
+// index (j = i), so two triangles with the same centroid would meet at r = 0.
+// tab: cap int32 slots (cap a power of two >= 2 n) followed by out[2] =
+// {smallest index that shares its centroid with another point (INT32_MAX if
+// none), number of such coincidences}; both are independent of scheduling.
+// Triangles of zero area (rejected ones) are skipped.
+void launch_dup_check(hipStream_t s, const double *g, int64_t n, int64_t ld, int32_t *tab,
+                      int64_t cap);
 
 // Pair sweep of the matvec: part[(o * n_chunks + c) * npad + i], o in {0,1}.
 void launch_pairs_f64(hipStream_t s, const Geo &geo, const double *src, const Sweep &sw,

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(TPB) void k_geometry(int64_t n_vert, int64_t n_tri,
 {
 #pragma clang fp contract(off)
     __shared__ double sh[TPB / 64];
-    double acc[GEO_RED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[GEO_RED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < npad;
          i += (int64_t)gridDim.x * TPB) {
         double c[3] = {FAR_TGT, 0.0, 0.0}, nn[3] = {0.0, 0.0, 1.0}, a = 0.0;
@@ -77,6 +77,12 @@ __global__ __launch_bounds__(TPB) void k_geometry(int64_t n_vert, int64_t n_tri,
                     nn[k] = m[k] / mn;
                 const double chk = c[0] + c[1] + c[2] + nn[0] + nn[1] + nn[2] + a;
                 bad = !(mn > 0.0) || !isfinite(chk);
+                if (!bad && !(fabs(c[0]) <= COORD_MAX && fabs(c[1]) <= COORD_MAX &&
+                              fabs(c[2]) <= COORD_MAX)) {
+                    bad = true;   // counted apart, for a message of its own
+                    acc[6] += 1.0;
+                    acc[0] -= 1.0;
+                }
                 if (!bad) {
                     acc[1] += m[0] * c[0] + m[1] * c[1] + m[2] * c[2];
                     acc[2] += c[0];
@@ -104,6 +110,54 @@ __global__ __launch_bounds__(TPB) void k_geometry(int64_t n_vert, int64_t n_tri,
         const double s = block_sum(acc[k], sh);
         if (threadIdx.x == 0)
             part[(int64_t)k * nblk + blockIdx.x] = s;
+    }
+}
+
+// ---- coincident collocation points ------------------------------------------
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(TPB) void k_dup_clear(int32_t *__restrict__ tab, int64_t cap)
+{
+    for (int64_t k = (int64_t)blockIdx.x * TPB + threadIdx.x; k < cap + 2;
+         k += (int64_t)gridDim.x * TPB)
+        tab[k] = k < cap ? -1 : (k == cap ? INT32_MAX : 0);
+}
+
+// Open-addressing insert of every centroid, keyed by its coordinates (+0.0
+// folds -0 into 0).  Points with equal centroids probe the same slots, so each
+// one after the first to claim a slot finds that first one; the smallest index
+// over these pairs is the smallest index of any coincident group, whichever
+// point won.  The table holds >= 2n slots and at most n entries, so every
+// probe sequence reaches an empty slot.
+__global__ __launch_bounds__(TPB) void k_dup_insert(const double *__restrict__ g, int64_t n,
+                                                    int64_t ld, int32_t *__restrict__ tab,
+                                                    int64_t cap)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n || !(g[6 * ld + i] > 0.0))
+        return;
+    const double x = g[i] + 0.0, y = g[ld + i] + 0.0, z = g[2 * ld + i] + 0.0;
+    const uint64_t h = mix64((uint64_t)__double_as_longlong(x) ^
+                             mix64((uint64_t)__double_as_longlong(y) ^
+                                   mix64((uint64_t)__double_as_longlong(z))));
+    const uint64_t mask = (uint64_t)cap - 1;
+    int32_t *out = tab + cap;
+    for (uint64_t slot = h & mask;; slot = (slot + 1) & mask) {
+        const int32_t prev = atomicCAS(&tab[slot], -1, (int32_t)i);
+        if (prev < 0)
+            return;
+        if (g[prev] == x && g[ld + prev] == y && g[2 * ld + prev] == z) {
+            atomicMin(&out[0], prev < (int32_t)i ? prev : (int32_t)i);
+            atomicAdd(&out[1], 1);
+            return;
+        }
     }
 }
 
@@ -199,8 +253,8 @@ __global__ __launch_bounds__(TPB) void k_pairs_f32_fwd(const Src8<float> *__rest
     const int b = blockIdx.x;
     const int chunk = b % sw.n_chunks;
     const int tb = b / sw.n_chunks;
-    const double sig = SCALED ? pp.kappa : 1.0;   // f32_sigma(pp.kappa)
-    const double kap = pp.kappa / sig;             // kappa in scaled units
+    const double sig = pp.sigma;          // FP32 length unit
+    const double kap = pp.kappa / sig;    // kappa in that unit (1 when SCALED)
     float tg[TPT][9];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
@@ -315,7 +369,7 @@ __global__ __launch_bounds__(SYM_NT) void k_pairs_f32_sym(const Src12 *__restric
     __shared__ SrcTileF32 sh;
     __shared__ float colw[SYM_NT / 64][2 * TILE];
     const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
-    sym_item_f32<SCALED>(src, it.x, it.y, it.z, T, coef_f32(pp.eps, pp.kappa, SCALED),
+    sym_item_f32<SCALED>(src, it.x, it.y, it.z, T, coef_f32(pp.eps, pp.kappa / pp.sigma, SCALED),
                          rowpart + (int64_t)it.w * (2 * TILE), colpart, sh, colw);
 }
 
@@ -1082,6 +1136,14 @@ SymPlan plan_sym(int64_t npad, int target_waves, std::vector<int32_t> &items,
     return pl;
 }
 
+void launch_dup_check(hipStream_t s, const double *g, int64_t n, int64_t ld, int32_t *tab,
+                      int64_t cap)
+{
+    const unsigned cb = (unsigned)std::min<int64_t>((cap + 2 + TPB - 1) / TPB, 4096);
+    hipLaunchKernelGGL(k_dup_clear, dim3(cb), dim3(TPB), 0, s, tab, cap);
+    hipLaunchKernelGGL(k_dup_insert, dim3(blocks_for(n)), dim3(TPB), 0, s, g, n, ld, tab, cap);
+}
+
 int geometry_blocks(int64_t n_tri)
 {
     int64_t b = (n_tri + TPB - 1) / TPB;
@@ -1120,7 +1182,7 @@ void launch_pairs_f32_fwd(hipStream_t s, const Geo &geo, const float *src, const
 {
     const dim3 grid(sw.n_tblocks * sw.n_chunks);
     const auto *p = reinterpret_cast<const Src8<float> *>(src);
-    const bool scaled = pp.kappa > 0.0;
+    const bool scaled = f32_scaled(pp);
     if (tpt == 2 && scaled)
         hipLaunchKernelGGL((k_pairs_f32_fwd<2, true>), grid, dim3(TPB), 0, s, p, geo.g, geo.npad,
                            sw, pp, part);
@@ -1151,7 +1213,7 @@ void launch_pairs_f32_sym(hipStream_t s, const float *src, const int32_t *items,
     PairParams q = pp;
     if (transpose)
         q.eps = 1.0 / pp.eps;   // the pair constant of the transposed reduced form
-    if (q.kappa > 0.0)
+    if (f32_scaled(q))
         hipLaunchKernelGGL(k_pairs_f32_sym<true>, dim3(n_items), dim3(SYM_NT), 0, s, p, it,
                            n_tiles, q, rowpart, colpart);
     else

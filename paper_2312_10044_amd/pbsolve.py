@@ -113,6 +113,8 @@ _PROTOS = {
                                  ctypes.POINTER(_int), ctypes.POINTER(_int)]),
     "pb_set_batch_tiles": (_int, [_vp, _int]),
     "pb_get_batch_tiles": (_int, [_vp, ctypes.POINTER(_int)]),
+    "pb_set_memory_limit": (_int, [_vp, _i64]),
+    "pb_get_memory_used": (_int, [_vp, ctypes.POINTER(_i64)]),
     "pb_profile_enable": (_int, [_vp, _int]),
     "pb_profile_reset": (_int, [_vp]),
     "pb_profile_read": (_int, [_vp, _int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
@@ -494,6 +496,17 @@ class Context:
         self._check(self._L.pb_autotune(self._h, ctypes.byref(s), ctypes.byref(p),
                                         ctypes.byref(a), ctypes.byref(b)))
         return int(a.value), int(b.value)
+
+    # -- device memory -------------------------------------------------------------
+    def set_memory_limit(self, nbytes: int):
+        """Cap on the context's device scratch (0: none); past it calls fail
+        with PB_ERR_OOM before allocating."""
+        self._check(self._L.pb_set_memory_limit(self._h, int(nbytes)))
+
+    def memory_used(self) -> int:
+        v = _i64()
+        self._check(self._L.pb_get_memory_used(self._h, ctypes.byref(v)))
+        return int(v.value)
 
     # -- kernel timing hook ------------------------------------------------------
     def profile_enable(self, on: bool = True):

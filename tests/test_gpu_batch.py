@@ -43,9 +43,10 @@ def test_batch_fp64_matches_single_solves_and_oracle(pb, small_batch):
         info, _p, _d = ctx.pb_solve(v, t, pos, q, P)
         assert infos[b].status == m.PB_OK
         assert abs(e[b] - info.e_solv) <= 1e-10 * abs(info.e_solv), b
-    v, t, pos, q = small_batch[2]
-    ref = dsbi.solve(v, t, pos, q, tol=1e-12)
-    assert abs(e[2] - ref.e_solv) <= 1e-10 * abs(ref.e_solv)
+    for b, (v, t, pos, q) in enumerate(small_batch):
+        ref = dsbi.solve(v, t, pos, q, tol=1e-12)
+        _say(f"  system {b}: {t.shape[0]} triangles, E={e[b]:.12f} oracle {ref.e_solv:.12f}")
+        assert abs(e[b] - ref.e_solv) <= 1e-10 * abs(ref.e_solv), b
 
 
 def test_batch_forces_match_single_forces(pb, small_batch):
@@ -61,6 +62,65 @@ def test_batch_forces_match_single_forces(pb, small_batch):
         assert np.abs(gpos[off:off + n] - dpos).max() <= 1e-8 * np.abs(dpos).max()
         assert np.abs(gq[off:off + n] - dq).max() <= 1e-8 * np.abs(dq).max()
         off += n
+
+
+def test_batch_forces_match_oracle_adjoint(pb, small_batch):
+    """Batch gradients of two systems (the largest and a small one) against
+    the oracle's adjoint method (its own transpose GMRES and gradient sums)."""
+    m, ctx = pb
+    P = m.Params(tol=1e-12)
+    e, infos, gpos, gq = ctx.pb_solve_batch(small_batch, P, forces=True)
+    offs = np.cumsum([0] + [s[3].shape[0] for s in small_batch])
+    for b in (1, 4):
+        v, t, pos, q = small_batch[b]
+        sol = dsbi.solve(v, t, pos, q, tol=1e-12)
+        o_pos, o_q, _lam, _i = dsbi.forces(sol, pos, q, tol=1e-12)
+        a, z = offs[b], offs[b + 1]
+        err = np.abs(gpos[a:z] - o_pos).max() / np.abs(o_pos).max()
+        _say(f"  system {b}: forces max rel err vs oracle adjoint {err:.2e}")
+        assert err <= 1e-8
+        assert np.abs(gq[a:z] - o_q).max() <= 1e-8 * np.abs(o_q).max()
+        assert abs(e[b] - sol.e_solv) <= 1e-10 * abs(sol.e_solv)
+
+
+def test_batch_eight_systems_spanning_the_batch_workload_sizes(pb):
+    """Eight star systems of 5,120 to 81,920 triangles (the size range of the
+    64-system batch workload), E_sol and forces in one call: FP64 batch against
+    one-at-a-time FP64 solves, the refined-FP32 preconditioned batch (the
+    benchmarked configuration) within 1e-6, and the smallest system's energy
+    against the oracle."""
+    m, ctx = pb
+    specs = [(16, 10.0, 100), (23, 12.0, 300), (30, 14.0, 500), (37, 16.0, 800),
+             (44, 18.0, 1100), (51, 20.0, 1400), (58, 22.0, 1700), (64, 25.0, 2000)]
+    systems = []
+    for k, (f, r0, nc) in enumerate(specs):
+        w = synth.star_protein(freq=f, r0=r0, n_charges=nc, seed=70 + k)
+        systems.append((w.verts, w.tris, w.pos, w.q))
+    sizes = [s[1].shape[0] for s in systems]
+    _say(f"batch of 8: {sizes} triangles")
+    assert min(sizes) == 5120 and max(sizes) == 81920
+    P64 = m.Params(tol=1e-12, precond_leaf=24, max_iter=2000)
+    e, infos, gpos, gq = ctx.pb_solve_batch(systems, P64, forces=True)
+    off = 0
+    for b, (v, t, pos, q) in enumerate(systems):
+        info, dpos, dq = ctx.pb_forces(v, t, pos, q, P64)
+        n = q.shape[0]
+        _say(f"  system {b}: E batch {e[b]:.12f} single {info.e_solv:.12f}")
+        assert infos[b].status == m.PB_OK and info.status == m.PB_OK
+        assert abs(e[b] - info.e_solv) <= 1e-10 * abs(info.e_solv), b
+        assert np.abs(gpos[off:off + n] - dpos).max() <= 1e-8 * np.abs(dpos).max()
+        assert np.abs(gq[off:off + n] - dq).max() <= 1e-8 * np.abs(dq).max()
+        off += n
+    P32 = m.Params(tol=1e-6, precision=m.PB_FP32_IR, inner_tol=1e-7, precond_leaf=24,
+                   max_iter=2000)
+    e32, i32, g32, _q = ctx.pb_solve_batch(systems, P32, forces=True)
+    rel = np.abs(e32 - e) / np.abs(e)
+    _say(f"  refined FP32 batch: worst E rel err {rel.max():.2e}")
+    assert all(i.status == m.PB_OK for i in i32)
+    assert rel.max() <= 1e-6
+    v, t, pos, q = systems[0]
+    ref = dsbi.solve(v, t, pos, q, tol=1e-12)
+    assert abs(e[0] - ref.e_solv) <= 1e-10 * abs(ref.e_solv)
 
 
 def test_batch_fp32_refined_energies(pb, small_batch):

@@ -105,3 +105,25 @@ def test_autograd_function(pb):
     with torch.no_grad():
         E2 = pb_energy(tv, tt, pos, q, ctx, P)
     assert float(E2) == pytest.approx(info.e_solv, rel=1e-12)
+
+
+def test_autograd_function_raises_when_not_converged(pb):
+    """An unconverged forward or adjoint solve is an error, not an energy."""
+    import torch
+    from paper_2312_10044_amd.autograd import pb_energy
+    m, ctx = pb
+    w = synth.star_protein(freq=8, r0=8.0, n_charges=20, seed=12)
+    dev = torch.device("cuda:0")
+    tv = torch.from_numpy(w.verts).to(dev)
+    tt = torch.from_numpy(w.tris.astype(np.int32)).to(dev)
+    pos = torch.from_numpy(w.pos).to(dev).requires_grad_(True)
+    q = torch.from_numpy(w.q).to(dev)
+    _say("autograd: max_iter 1 must raise")
+    for grad in (True, False):
+        with torch.set_grad_enabled(grad):
+            with pytest.raises(m.PbError) as e:
+                pb_energy(tv, tt, pos, q, ctx, m.Params(tol=1e-12, max_iter=1))
+        assert e.value.status == m.PB_NOT_CONVERGED
+    # the context still solves afterwards
+    E = pb_energy(tv, tt, pos, q, ctx, m.Params(tol=1e-10))
+    assert np.isfinite(float(E.detach()))

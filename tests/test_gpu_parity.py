@@ -2,9 +2,10 @@
 
 Tolerances (derived in the design notes):
 * geometry: same IEEE operations in the same order -> <= 1 ulp-level.
-* FP64 pair sums: |dy_i| <= 2e-12 * S_i, S_i = sum of |terms| of row i (the
-  oracle reports it).  The K4 difference loses ~u/(kappa r)^2 relative on
-  the nearest pairs on both sides; everything else is a few ulps per term.
+* FP64 pair sums: |dy_i| <= 1e-14 * S_i, S_i = sum of |terms| of row i (the
+  oracle reports it): a few ulps per term (the exponential and 1/r are within
+  2.3 and 1 ulp), summed in different orders; the K4 difference, which loses
+  ~u/(kappa r)^2 of its own size on the nearest pairs, is a small part of S_i.
 * FP32 pair sums: |dy_i| <= 5e-5 * S_i (FP32 coordinates after recentring:
   ~1e-6 A position error against 0.1 A neighbour spacing, tile-blocked
   compensated accumulation).
@@ -24,6 +25,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KAPPA = 0.1257
+FP64_BAR = 1e-14
 
 
 def _say(msg):
@@ -96,7 +98,7 @@ def test_matvec_fp64_all_rows_ragged(pb, star12, transpose):
     _say(f"matvec fp64 transpose={transpose}: {star12.n_tri} triangles")
     err = _matvec_case(m, ctx, star12, transpose, m.PB_FP64)
     _say(f"  max |dy|/S = {err:.3e}")
-    assert err <= 2e-12
+    assert err <= FP64_BAR
 
 
 @pytest.mark.parametrize("transpose", [False, True])
@@ -108,7 +110,7 @@ def test_matvec_fp32_all_rows_ragged(pb, star12, transpose):
     assert err <= 5e-5
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 2e-12), (1, 5e-5)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-14), (1, 5e-5)])
 def test_matvec_full_size_sampled_rows(pb, star64, precision, tol):
     m, ctx = pb
     rows = np.sort(np.random.default_rng(5).choice(star64.n_tri, 192, replace=False))
