@@ -220,6 +220,21 @@ int pb_forces_dev(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_ve
                   const double *d_q, const pb_params *p, double *d_dE_dpos, double *d_dE_dq,
                   pb_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation as pb_matvec_dev (y = A x or A^T x, FP64 or FP32 pair arithmetic,
+ * device arrays), computed with the per-target sweeps in a fixed device
+ * scratch array that the library holds on each GPU from the first pb_create
+ * there until the process ends (about 14 MB).  The call allocates nothing;
+ * n_tri <= 32768 (PB_ERR_ARG beyond, naming the limit).  Results agree with
+ * pb_matvec_dev up to rounding (another summation order).  Every call on one
+ * GPU shares that GPU's scratch: calls that overlap in time on one GPU, from
+ * any context or thread, race.  Same validation and status codes as
+ * pb_matvec_dev. */
+int pb_matvec_dev_noalloc(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                          const int32_t *d_tri, const pb_params *p, const double *d_x,
+                          double *d_y, int transpose, int precision);
+
 /* ---- preconditioner hooks (tests) ------------------------------------- */
 /* The octree leaves used by the preconditioner for leaf size `leaf` (1..32):
  * perm [n_tri] lists the elements leaf by leaf, leaf_start [n_tri + 1] (only

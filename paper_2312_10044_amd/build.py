@@ -5,7 +5,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pb_kernels.hip", "pb_batch.hip", "pb_tree.hip", "pb_capi.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pb_kernels.hip", "pb_batch.hip", "pb_tree.hip", "pb_noalloc.hip", "pb_capi.hip")]
 LIB = os.path.join(HERE, "libpbdsbi.so")
 ARCH = "gfx950"
 

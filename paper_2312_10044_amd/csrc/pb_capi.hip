@@ -1125,6 +1125,15 @@ int pb_create(int device, void *hip_stream, pb_ctx **out)
         delete c;
         return PB_ERR_OOM;
     }
+    // the device address of this GPU's no-allocation scratch, once per device
+    const int na = noalloc_init(device);
+    if (na != PB_OK) {
+        (void)hipHostFree(c->hsmall);
+        if (c->own_stream)
+            (void)hipStreamDestroy(c->stream);
+        delete c;
+        return na;
+    }
     *out = c;
     return PB_OK;
 }
@@ -1453,6 +1462,17 @@ int pb_matvec_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert
     return leave(c, guarded(c, [&] {
         return pb_matvec_dev_impl(c, n_vert, n_tri, d_vert, d_tri, p, d_x, d_y, transpose,
                                   precision);
+    }));
+}
+
+int pb_matvec_dev_noalloc(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                          const int32_t *d_tri, const pb_params *p, const double *d_x,
+                          double *d_y, int transpose, int precision)
+{
+    return leave(c, guarded(c, [&]() -> int {
+        TRY(enter(c));
+        return matvec_noalloc(c, n_vert, n_tri, d_vert, d_tri, p, d_x, d_y, transpose ? 1 : 0,
+                              precision);
     }));
 }
 

@@ -243,6 +243,11 @@ struct BatchTune {
     double ms[8] = {0.0};
     int best = -1;
 };
+// No-allocation matvec (pb_noalloc.hip): set-up once per device, and the call.
+int noalloc_init(int device);
+int matvec_noalloc(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                   const int32_t *d_tri, const pb_params *p, const double *d_x, double *d_y,
+                   int transpose, int precision);
 int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
                 const pb_params *p, int want_forces, double *e_solv, double *dE_dpos,
                 double *dE_dq, pb_info *info, BatchTune *tune = nullptr);

@@ -85,6 +85,8 @@ _PROTOS = {
                         ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
     "pb_matvec_dev": (_int, [_vp, _i64, _i64, _vp, _vp, ctypes.POINTER(_Params), _vp, _vp,
                              _int, _int]),
+    "pb_matvec_dev_noalloc": (_int, [_vp, _i64, _i64, _vp, _vp, ctypes.POINTER(_Params), _vp,
+                                     _vp, _int, _int]),
     "pb_solve_dev": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp,
                             ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
     "pb_forces": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
@@ -402,6 +404,17 @@ class Context:
                                           _dev(verts, "float64"), _dev(tris, "int32"), ctypes.byref(p),
                                           _dev(x, "float64"), _dev(y, "float64"),
                                           int(bool(transpose)), int(precision)))
+        return y
+
+    def pb_matvec_dev_noalloc(self, verts, tris, x, y, params: Params, transpose=False,
+                              precision=PB_FP64):
+        """pb_matvec_dev without device allocation (fixed library scratch)."""
+        p = params.c()
+        self._check(self._L.pb_matvec_dev_noalloc(self._h, verts.shape[0], tris.shape[0],
+                                                  _dev(verts, "float64"), _dev(tris, "int32"),
+                                                  ctypes.byref(p), _dev(x, "float64"),
+                                                  _dev(y, "float64"), int(bool(transpose)),
+                                                  int(precision)))
         return y
 
     def pb_solve_dev(self, verts, tris, pos, q, params: Params, phi=None, dphi=None) -> Info:
