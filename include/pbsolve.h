@@ -92,9 +92,10 @@ typedef struct {
                                    arithmetic resolves) are raised to 1e-7, and an inner
                                    solve also ends when a restart cycle gains less
                                    than 10 % */
-    int32_t precond_leaf;       /* 0: no preconditioner.  1..32: block-diagonal leaf
+    int32_t precond_leaf;       /* 0: no preconditioner.  1..100: block-diagonal leaf
                                    preconditioner of Sec. 2.2.4 with at most this many
-                                   elements per octree leaf; GMRES then runs on the left-
+                                   elements per octree leaf (N0; the paper's runs use
+                                   100); GMRES then runs on the left-
                                    preconditioned system M^-1 A x = M^-1 b and tol applies
                                    to its residual |M^-1 (b - A x)| / |M^-1 b| (FP64 path,
                                    IR inner solves and IR outer test alike; the outer
@@ -236,7 +237,7 @@ int pb_matvec_dev_noalloc(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const doub
                           double *d_y, int transpose, int precision);
 
 /* ---- preconditioner hooks (tests) ------------------------------------- */
-/* The octree leaves used by the preconditioner for leaf size `leaf` (1..32):
+/* The octree leaves used by the preconditioner for leaf size `leaf` (1..100):
  * perm [n_tri] lists the elements leaf by leaf, leaf_start [n_tri + 1] (only
  * the first *n_leaves + 1 entries are written) the leaf boundaries. */
 int pb_precond_leaves(pb_ctx *ctx, const pb_surface *s, int leaf, int32_t *perm,

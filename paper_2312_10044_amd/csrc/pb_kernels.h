@@ -17,7 +17,7 @@ constexpr double COORD_MAX = 1.0e5;   // |centroid coordinate| bound, A (padding
 constexpr double KAPPA_MAX = 100.0;   // 1/A: kappa r stays < 1.4e9 for every padded pair
 constexpr int MAX_RESTART = 64;
 constexpr int PADN = 512;       // collocation arrays are padded to a multiple of this
-constexpr int PC_MAX_LEAF = 32; // largest preconditioner leaf (its 2m x 2m block lives in LDS)
+constexpr int PC_MAX_LEAF = 100; // largest preconditioner leaf (N0 of Sec. 2.2.4's runs)
 
 // Device-side collocation geometry, SoA: array k at g + k * npad.
 struct Geo {

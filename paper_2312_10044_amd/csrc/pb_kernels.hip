@@ -767,6 +767,7 @@ __global__ __launch_bounds__(TPB) void k_pc_index(const int32_t *__restrict__ pe
 // block, so inverse(r, c) = A(piv[r], q[c]) with q the inverse permutation of
 // piv.
 constexpr int PC_LANES = 64;
+constexpr int PC_SMALL_M2 = 64;   // largest block k_pc_build inverts in one wave
 
 // Gauss-Jordan inversion of the 2m x 2m block held in LDS rows of stride LD
 // (lane i: row i in registers, W >= 2m columns unrolled); writes the inverse
@@ -832,6 +833,44 @@ __device__ __forceinline__ void pc_invert(double *A, double *prow, int *piv, int
     }
 }
 
+// The four entries -K_1..-K_4 (times a_q / 4 pi) that the leaf pair (r, q)
+// contributes to the 2m x 2m block (rows/columns in leaf order, gp holds the
+// leaf's centroids, normals and areas); all zero for r = q (j = i omitted).
+// out[0]: (r, m + q), out[1]: (r, q), out[2]: (m + r, m + q), out[3]: (m + r, q).
+template <int LMAX>
+__device__ __forceinline__ void pc_pair(const double (*gp)[LMAX], int r, int q, double eps,
+                                        double kappa, double (&out)[4])
+{
+    double k1 = 0.0, k2 = 0.0, k3 = 0.0, k4 = 0.0;
+    if (r != q) {
+        const double epsm1 = eps - 1.0, ieps = 1.0 / eps, iepsm1 = 1.0 / eps - 1.0;
+        const double dx = gp[0][r] - gp[0][q], dy = gp[1][r] - gp[1][q];
+        const double dz = gp[2][r] - gp[2][q];
+        const double nxi = gp[3][r], nyi = gp[4][r], nzi = gp[5][r];
+        const double nxj = gp[3][q], nyj = gp[4][q], nzj = gp[5][q];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double ir = rsqrt(r2);
+        const double ir2 = ir * ir, u = ir2 * ir;
+        const double kr = kappa * (r2 * ir);
+        const double ee = exp(-kr);
+        const double em1 = ee - 1.0;
+        const double tm1 = fma(kr, ee, em1);
+        const double cx = nxi * dx + nyi * dy + nzi * dz;
+        const double cy = nxj * dx + nyj * dy + nzj * dz;
+        const double nn = nxi * nxj + nyi * nyj + nzi * nzj;
+        const double h = fma(tm1, 3.0 * ir2, kappa * kappa * ee);
+        k1 = -em1 * ir;
+        k2 = fma(eps, tm1, epsm1) * cy * u;
+        k3 = fma(ieps, tm1, iepsm1) * cx * u;
+        k4 = u * (tm1 * nn - cx * cy * h);
+    }
+    const double aj = gp[6][q] * INV_4PI;
+    out[0] = -k1 * aj;
+    out[1] = -k2 * aj;
+    out[2] = -k3 * aj;
+    out[3] = -k4 * aj;
+}
+
 template <int MM>
 __global__ __launch_bounds__(PC_LANES) void k_pc_build(const double *__restrict__ g,
                                                        int64_t npad,
@@ -858,36 +897,14 @@ __global__ __launch_bounds__(PC_LANES) void k_pc_build(const double *__restrict_
             gp[k][lane] = g[k * npad + i];
     }
     __syncthreads();
-    const double epsm1 = eps - 1.0, ieps = 1.0 / eps, iepsm1 = 1.0 / eps - 1.0;
     for (int e = lane; e < m * m; e += PC_LANES) {
         const int r = e / m, q = e - r * m;   // rows and columns in leaf order
-        double k1 = 0.0, k2 = 0.0, k3 = 0.0, k4 = 0.0;
-        if (r != q) {
-            const double dx = gp[0][r] - gp[0][q], dy = gp[1][r] - gp[1][q];
-            const double dz = gp[2][r] - gp[2][q];
-            const double nxi = gp[3][r], nyi = gp[4][r], nzi = gp[5][r];
-            const double nxj = gp[3][q], nyj = gp[4][q], nzj = gp[5][q];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double ir = rsqrt(r2);
-            const double ir2 = ir * ir, u = ir2 * ir;
-            const double kr = kappa * (r2 * ir);
-            const double ee = exp(-kr);
-            const double em1 = ee - 1.0;
-            const double tm1 = fma(kr, ee, em1);
-            const double cx = nxi * dx + nyi * dy + nzi * dz;
-            const double cy = nxj * dx + nyj * dy + nzj * dz;
-            const double nn = nxi * nxj + nyi * nyj + nzi * nzj;
-            const double h = fma(tm1, 3.0 * ir2, kappa * kappa * ee);
-            k1 = -em1 * ir;
-            k2 = fma(eps, tm1, epsm1) * cy * u;
-            k3 = fma(ieps, tm1, iepsm1) * cx * u;
-            k4 = u * (tm1 * nn - cx * cy * h);
-        }
-        const double aj = gp[6][q] * INV_4PI;
-        A[r][q] = -k2 * aj;
-        A[r][m + q] = -k1 * aj;
-        A[m + r][q] = -k4 * aj;
-        A[m + r][m + q] = -k3 * aj;
+        double k[4];
+        pc_pair<MM / 2>(gp, r, q, eps, kappa, k);
+        A[r][q] = k[1];
+        A[r][m + q] = k[0];
+        A[m + r][q] = k[3];
+        A[m + r][m + q] = k[2];
     }
     __syncthreads();
     double *out = inv + boff[l];
@@ -902,6 +919,144 @@ __global__ __launch_bounds__(PC_LANES) void k_pc_build(const double *__restrict_
                 pc_invert<48, MM + 1>(&A[0][0], prow, piv, qinv, m, eps, out);
             else if constexpr (MM >= 64)
                 pc_invert<64, MM + 1>(&A[0][0], prow, piv, qinv, m, eps, out);
+        }
+    }
+}
+
+// Leaves with 64 < 2m <= 2 PC_MAX_LEAF: the block no longer fits one wave's
+// registers (nor, in FP64, the LDS), so it is spread over the registers of a
+// whole workgroup.  Thread t = 200 grp + c (t < 1000) owns the entries of
+// column c in the rows r = grp + 5 j, j < 40, the same entries at every step
+// (every register index is a compile-time constant but one, the pivot row's,
+// which is uniform over the block).  Per column k: the five owners of column k
+// publish it in LDS with their candidates for the pivot (largest |A(r, k)|
+// over rows not yet used, ties to the lower row); the owners of the pivot row
+// publish it scaled; every thread then updates its entries.  The pivoting
+// rule and the read-out through the pivot permutation are those of pc_invert,
+// so both kernels compute the same inverse up to rounding.
+constexpr int PCB_COLS = 2 * PC_MAX_LEAF;            // 200
+constexpr int PCB_GROUPS = 5;
+constexpr int PCB_ROWS = PCB_COLS / PCB_GROUPS;       // 40 rows per thread
+constexpr int PCB_THREADS = 1024;                     // 1000 working, 24 idle
+static_assert(PCB_ROWS * PCB_GROUPS == PCB_COLS, "row groups must tile the block");
+
+__global__ __launch_bounds__(PCB_THREADS) void k_pc_build_big(
+    const double *__restrict__ g, int64_t npad, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ lstart, const int64_t *__restrict__ boff, double eps,
+    double kappa, double *__restrict__ inv)
+{
+    __shared__ double gp[7][PC_MAX_LEAF];
+    __shared__ double colk[PCB_COLS], prow[PCB_COLS];
+    __shared__ double cv[PCB_GROUPS];
+    __shared__ int ci[PCB_GROUPS];
+    __shared__ int piv[PCB_COLS], qinv[PCB_COLS], used[PCB_COLS];
+    const int l = blockIdx.x, t = threadIdx.x;
+    const int s0 = lstart[l];
+    const int m = lstart[l + 1] - s0;
+    const int m2 = 2 * m;
+    if (m2 <= PC_SMALL_M2 || m > PC_MAX_LEAF)
+        return;   // small leaves are k_pc_build's; the test is uniform over the block
+    const int c = t % PCB_COLS, grp = t / PCB_COLS;
+    const bool active = grp < PCB_GROUPS && c < m2;
+    for (int e = t; e < m; e += PCB_THREADS) {
+        const int64_t i = perm[s0 + e];
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            gp[k][e] = g[k * npad + i];
+    }
+    for (int e = t; e < m2; e += PCB_THREADS)
+        used[e] = 0;
+    __syncthreads();
+    const double alpha = 0.5 * (1.0 + eps), beta = 0.5 * (1.0 + 1.0 / eps);
+    double a[PCB_ROWS];
+#pragma unroll
+    for (int j = 0; j < PCB_ROWS; ++j) {
+        const int r = grp + PCB_GROUPS * j;
+        double v = 0.0;
+        if (active && r < m2) {
+            double k[4];
+            const int rr = r < m ? r : r - m, cc = c < m ? c : c - m;
+            pc_pair<PC_MAX_LEAF>(gp, rr, cc, eps, kappa, k);
+            // quadrant: (phi, psi) rows against (phi, psi) columns
+            v = r < m ? (c < m ? k[1] : k[0]) : (c < m ? k[3] : k[2]);
+            if (r == c)
+                v += r < m ? alpha : beta;
+        }
+        a[j] = v;
+    }
+    for (int k = 0; k < m2; ++k) {
+        if (active && c == k) {
+            double best = -1.0;
+            int bi = PCB_COLS;
+#pragma unroll
+            for (int j = 0; j < PCB_ROWS; ++j) {
+                const int r = grp + PCB_GROUPS * j;
+                if (r < m2) {
+                    colk[r] = a[j];
+                    const double v = used[r] ? -1.0 : fabs(a[j]);
+                    if (v > best) {   // rows ascend with j: ties keep the lower row
+                        best = v;
+                        bi = r;
+                    }
+                }
+            }
+            cv[grp] = best;
+            ci[grp] = bi;
+        }
+        __syncthreads();
+        double bv = cv[0];
+        int p = ci[0];
+#pragma unroll
+        for (int q = 1; q < PCB_GROUPS; ++q) {
+            const double v = cv[q];
+            const int i = ci[q];
+            if (v > bv || (v == bv && i < p)) {
+                bv = v;
+                p = i;
+            }
+        }
+        const double pinv = 1.0 / colk[p];
+        if (active && grp == p % PCB_GROUPS) {
+            const int jp = p / PCB_GROUPS;   // uniform over the block
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < PCB_ROWS; ++j)
+                v = (j == jp) ? a[j] : v;
+            prow[c] = (c == k) ? pinv : v * pinv;
+            if (c == k) {
+                used[p] = 1;
+                piv[k] = p;
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const double pc = prow[c];
+#pragma unroll
+            for (int j = 0; j < PCB_ROWS; ++j) {
+                const int r = grp + PCB_GROUPS * j;
+                if (r < m2) {
+                    if (r == p) {
+                        a[j] = pc;
+                    } else {
+                        const double f = colk[r];
+                        a[j] = (c == k) ? -f * pinv : fma(-f, pc, a[j]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int k = t; k < m2; k += PCB_THREADS)
+        qinv[piv[k]] = k;
+    __syncthreads();
+    if (active) {
+        double *out = inv + boff[l];
+        const int pc = piv[c];
+#pragma unroll
+        for (int j = 0; j < PCB_ROWS; ++j) {
+            const int r = grp + PCB_GROUPS * j;
+            if (r < m2)
+                out[(int64_t)qinv[r] * m2 + pc] = a[j];
         }
     }
 }
@@ -1364,8 +1519,11 @@ void launch_pc_build(hipStream_t s, const Geo &geo, const int32_t *perm, const i
                      const int64_t *boff, int64_t n_leaves, int max_leaf, double eps,
                      double kappa, double *inv)
 {
-    const int mm = 2 * std::min(std::max(max_leaf, 1), PC_MAX_LEAF);
+    const int mm = std::min(2 * std::min(std::max(max_leaf, 1), PC_MAX_LEAF), PC_SMALL_M2);
     const dim3 grid((unsigned)n_leaves), block(PC_LANES);
+    if (2 * max_leaf > PC_SMALL_M2)   // leaves of more than 32 elements, if any
+        hipLaunchKernelGGL(k_pc_build_big, grid, dim3(PCB_THREADS), 0, s, geo.g, geo.npad, perm,
+                           lstart, boff, eps, kappa, inv);
     if (mm <= 16)
         hipLaunchKernelGGL(k_pc_build<16>, grid, block, 0, s, geo.g, geo.npad, perm, lstart,
                            boff, eps, kappa, inv);
