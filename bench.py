@@ -37,6 +37,7 @@ PEAK_FP64_VECTOR = 78.6e12
 TOL_LADDER = [1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9, 1e-10]
 E_TARGET = 1e-6
 PAIRWISE = 8   # pb_set_sweep_config kind of the pairwise sweep (PB_SWEEP_PAIRWISE)
+BANDED = 16    # the banded pairwise FP32 sweep (PB_SWEEP_BANDED)
 
 WORKLOADS = {"star327680": "large_star_protein", "star81920": "star_protein"}
 
@@ -46,7 +47,7 @@ def _log(msg):
 
 
 def fp32_kernel_name(kind: int) -> str:
-    return "k_pairs_f32_sym" if kind == PAIRWISE else "k_pairs_f32_fwd"
+    return {PAIRWISE: "k_pairs_f32_sym", BANDED: "k_pairs_f32_band"}.get(kind, "k_pairs_f32_fwd")
 
 
 def fp64_kernel_name(kind: int) -> str:
@@ -54,7 +55,8 @@ def fp64_kernel_name(kind: int) -> str:
 
 
 def sweep_label(kind: int) -> str:
-    return "pairwise" if kind == PAIRWISE else f"per-target, {kind} targets per thread"
+    return {PAIRWISE: "pairwise", BANDED: "pairwise, banded"}.get(
+        kind, f"per-target, {kind} targets per thread")
 
 
 def _code_only(text: str) -> str:
@@ -551,6 +553,8 @@ def main():
                     help="leaf size of the block-diagonal preconditioner (0 = none)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the FP32 sweep configurations first and use the fastest")
+    ap.add_argument("--fp32-sweep", choices=["default", "pairwise", "banded", "1", "2"],
+                    default="default", help="FP32 sweep kind (default: the library's)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -588,6 +592,9 @@ def main():
     w = make_workload(args.workload)
     N = w.n_tri
     base = dict(eps_in=w.eps_in, eps_out=w.eps_out, kappa=w.kappa, restart=10, max_iter=2000)
+    if args.fp32_sweep != "default":
+        ctx.set_sweep_config({"pairwise": PAIRWISE, "banded": BANDED}.get(args.fp32_sweep)
+                             or int(args.fp32_sweep), 0)
     if args.autotune:
         tuned = ctx.pb_autotune(w.verts, w.tris, Params(**base))
     else:

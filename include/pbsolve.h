@@ -221,6 +221,28 @@ int pb_forces_dev(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_ve
                   const double *d_q, const pb_params *p, double *d_dE_dpos, double *d_dE_dq,
                   pb_info *info);
 
+/* Step 2 (eq. source_terms) on device arrays: d_b [2 n_tri] receives [S1; S2]. */
+int pb_source_dev(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                  const int32_t *d_tri, int64_t n_charges, const double *d_pos,
+                  const double *d_q, const pb_params *p, double *d_b);
+
+/* Step 5 (eq. solvation_energy) of a device-resident surface solution
+ * d_phi, d_dphi [n_tri]; the energy (kcal/mol) is written to the host double
+ * *e_solv. */
+int pb_energy_dev(pb_ctx *ctx, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                  const int32_t *d_tri, int64_t n_charges, const double *d_pos,
+                  const double *d_q, const pb_params *p, const double *d_phi,
+                  const double *d_dphi, double *e_solv);
+
+/* pb_solve_batch with the arrays of every surfaces[b] and charges[b] (vert,
+ * tri, pos, q) in device memory, and the gradients d_dE_dpos [sum_b n_b][3],
+ * d_dE_dq [sum_b n_b] (both NULL: energies only) written to device memory.
+ * e_solv [n_sys] and info [n_sys] stay host arrays.  Same semantics, errors
+ * and results as pb_solve_batch. */
+int pb_solve_batch_dev(pb_ctx *ctx, int32_t n_sys, const pb_surface *surfaces,
+                       const pb_charges *charges, const pb_params *p, double *e_solv,
+                       double *d_dE_dpos, double *d_dE_dq, pb_info *info);
+
 /* For callers that cannot allocate device memory (code under HIP stream
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * operation as pb_matvec_dev (y = A x or A^T x, FP64 or FP32 pair arithmetic,
@@ -286,6 +308,12 @@ int pb_solve_tree(pb_ctx *ctx, const pb_surface *s, const pb_charges *q, const p
  * value unchanged.  Defaults: PB_SWEEP_PAIRWISE, 131072.  Both kinds give the
  * same matvec up to FP32 rounding; only the summation order differs. */
 #define PB_SWEEP_PAIRWISE 8
+/* FP32 only: the pairwise sweep with each workgroup holding four target tiles
+ * and sweeping them over a run of source tiles for a band of such groups,
+ * which keeps its partial-sum records to about T^2 / (2 run) + T^2 / (8 band)
+ * for T tiles of 256 points (the pairwise kind writes one per tile pair);
+ * target_waves / 64 is the number of work items it aims at. */
+#define PB_SWEEP_BANDED 16
 int pb_set_sweep_config(pb_ctx *ctx, int targets_per_thread, int target_waves);
 int pb_get_sweep_config(pb_ctx *ctx, int *targets_per_thread, int *target_waves);
 /* The FP64 pair sweeps (forward and transposed: FP64 solves, refinement

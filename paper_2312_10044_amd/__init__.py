@@ -18,6 +18,7 @@ from .pbsolve import (  # noqa: F401
     PB_FP64,
     PB_FP32_IR,
     PB_SWEEP_PAIRWISE,
+    PB_SWEEP_BANDED,
     load_library,
     exported_symbols,
 )

@@ -2,10 +2,13 @@
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pb_kernels.hip", "pb_batch.hip", "pb_tree.hip", "pb_noalloc.hip", "pb_capi.hip")]
+# plain C++ host logic (no device code), also built by the host sanitizer test
+HOST_SOURCES = [os.path.join(HERE, "csrc", "pb_host.cpp")]
 LIB = os.path.join(HERE, "libpbdsbi.so")
 ARCH = "gfx950"
 
@@ -23,15 +26,41 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def device_targets(path: str = LIB) -> set:
+    """The offload targets of the device code objects bundled in a library."""
+    with open(path, "rb") as f:
+        data = f.read()
+    return {m.decode() for m in re.findall(rb"amdgcn-amd-amdhsa-[a-z0-9:+-]*gfx[0-9a-z]+", data)}
+
+
 def build(verbose: bool = False) -> str:
-    """Always recompiles; writes libpbdsbi.so atomically next to this file."""
+    """Always recompiles; writes libpbdsbi.so atomically next to this file.
+
+    The plain C++ host sources are compiled to objects by the host compiler
+    first: given to hipcc as C++ sources next to the .hip files, they make it
+    drop --offload-arch and build the device code for its default target."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *SOURCES]
+    objs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(HERE, os.path.splitext(os.path.basename(src))[0] + ".o")
+        cmd = [os.environ.get("CXX", "g++"), "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall",
+               "-c", src, "-o", obj]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("host compile failed:\n" + " ".join(cmd) + "\n" + res.stderr)
+        objs.append(obj)
+    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *SOURCES, "-x", "none", *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
+    for obj in objs:
+        os.remove(obj)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
     if verbose and (res.stdout or res.stderr):
         print(res.stdout + res.stderr)
+    targets = device_targets(tmp)
+    if targets != {f"amdgcn-amd-amdhsa--{ARCH}"}:
+        os.remove(tmp)
+        raise RuntimeError(f"built device code targets {sorted(targets)}, expected only {ARCH}")
     os.replace(tmp, LIB)
     return LIB
 

@@ -77,6 +77,23 @@ struct GState {
 
 // ---- packing --------------------------------------------------------------
 
+// Charge padding of system b (one block each): entries nc .. ncpad-1 repeat
+// the last charge's position with q = 0, so padded charge slots add nothing.
+__global__ __launch_bounds__(TPB) void kb_pad_charges(const SysDesc *__restrict__ sd,
+                                                      double *__restrict__ pos,
+                                                      double *__restrict__ q)
+{
+    const SysDesc d = sd[blockIdx.x];
+    const int64_t last = d.coff + d.nc - 1;
+    for (int64_t k = d.nc + threadIdx.x; k < d.ncpad; k += TPB) {
+        const int64_t e = d.coff + k;
+        pos[3 * e] = pos[3 * last];
+        pos[3 * e + 1] = pos[3 * last + 1];
+        pos[3 * e + 2] = pos[3 * last + 2];
+        q[e] = 0.0;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(TPB) void kb_pack(const double *__restrict__ g, int64_t gtot,
                                                const SysDesc *__restrict__ sd,
@@ -806,8 +823,16 @@ __global__ void kb_begin(GState *__restrict__ st, const double *__restrict__ red
         active[0] = (int32_t)tot;
 }
 
+// Arnoldi step j of each running system: Hessenberg column, Givens rotations,
+// and the end of the cycle's Krylov steps.  An FP64 cycle steps until its
+// residual estimate reaches tol |b|.  An FP32 cycle is one refinement step:
+// as the single-system inner solves, it steps until the estimate reaches
+// max(inner |r|, 0.3 tol |b|) (at most |r| / 2; inner > 0), |r| the cycle's
+// starting residual, so that the FP64 residual formed after it lands below
+// tol rather than at it.
 __global__ void kb_givens(GState *__restrict__ st, const double *__restrict__ red, int n_sys,
-                          int j, int m, double tol, int max_iter, int32_t *__restrict__ mask_step)
+                          int j, int m, double tol, double inner, int max_iter,
+                          int32_t *__restrict__ mask_step)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n_sys)
@@ -835,8 +860,10 @@ __global__ void kb_givens(GState *__restrict__ st, const double *__restrict__ re
     s.g[j] = s.cs[j] * s.g[j];
     s.k = j + 1;
     s.iters += 1;
-    if (fabs(s.g[j + 1]) <= tol * s.bnorm || s.iters >= max_iter || !(hn > 0.0) ||
-        !isfinite(hn)) {
+    const double target = inner > 0.0
+                              ? fmin(0.5 * s.beta, fmax(inner * s.beta, 0.3 * tol * s.bnorm))
+                              : tol * s.bnorm;
+    if (fabs(s.g[j + 1]) <= target || s.iters >= max_iter || !(hn > 0.0) || !isfinite(hn)) {
         s.step = 0;
         mask_step[b] = 0;
     }
@@ -1113,7 +1140,7 @@ int enqueue_cycle(pb_ctx *c, const BatchPlan &P, BatchDev &D, const pb_params *p
         hipLaunchKernelGGL(kb_scale, dim3(vb), dim3(TPB), 0, s, wv, D.red, D.vblk2sys,
                            D.V + (int64_t)(j + 1) * D.ld);
         hipLaunchKernelGGL(kb_givens, dim3(sb), dim3(256), 0, s, D.st, D.red, ns, j, m, p->tol,
-                           p->max_iter, D.mask_step);
+                           f32 ? std::max(p->inner_tol, 1e-7) : 0.0, p->max_iter, D.mask_step);
     }
     hipLaunchKernelGGL(kb_solve_y, dim3(sb), dim3(256), 0, s, D.st, ns, m);
     hipLaunchKernelGGL(kb_add_basis, dim3(vb), dim3(TPB), 0, s, D.V, D.ld, m, D.st, D.vblk2sys, x);
@@ -1277,7 +1304,7 @@ int batch_tune_run(pb_ctx *c, BatchPlan &P, BatchDev &D, const pb_params *p, Bat
 
 int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
                 const pb_params *p, int want_forces, double *e_solv, double *dE_dpos,
-                double *dE_dq, pb_info *info, BatchTune *tune)
+                double *dE_dq, pb_info *info, BatchTune *tune, bool device_inputs)
 {
     if (n_sys < 1 || !surf || !chg || (!e_solv && !tune))
         return fail(c, PB_ERR_ARG, "batch needs n_sys >= 1, surfaces, charges and e_solv");
@@ -1372,11 +1399,17 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     double max_len = 0.0;
     for (int b = 0; b < n_sys; ++b) {
         SysDesc &d = P.sd[b];
-        TRY(upload(c, c->in_vert.p, surf[b].vert, sizeof(double) * 3 * surf[b].n_vert));
-        TRY(upload(c, c->in_tri.p, surf[b].tri, sizeof(int32_t) * 3 * surf[b].n_tri));
+        const double *dv = surf[b].vert;
+        const int32_t *dt = surf[b].tri;
+        if (!device_inputs) {
+            TRY(upload(c, c->in_vert.p, surf[b].vert, sizeof(double) * 3 * surf[b].n_vert));
+            TRY(upload(c, c->in_tri.p, surf[b].tri, sizeof(int32_t) * 3 * surf[b].n_tri));
+            dv = as<double>(c->in_vert);
+            dt = as<int32_t>(c->in_tri);
+        }
         const int nb = geometry_blocks(d.npad);
-        launch_geometry(s, surf[b].n_vert, d.n, as<double>(c->in_vert), as<int32_t>(c->in_tri),
-                        D.g + d.goff, d.npad, P.gtot, as<double>(c->geo_part), nb);
+        launch_geometry(s, surf[b].n_vert, d.n, dv, dt, D.g + d.goff, d.npad, P.gtot,
+                        as<double>(c->geo_part), nb);
         launch_reduce_cols(s, as<double>(c->geo_part), nb, GEO_RED, as<double>(c->small));
         LAUNCHCHK();
         launch_dup_check(s, D.g + d.goff, d.n, P.gtot, as<int32_t>(c->dup_tab), dcap);
@@ -1407,19 +1440,32 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
     P.sigma_min = 1.0 / max_len;
     // charges, padded per system (padding repeats the last charge with q = 0)
     {
-        std::vector<double> hp(3 * P.ctot), hq(P.ctot, 0.0);
-        for (int b = 0; b < n_sys; ++b) {
-            const SysDesc &d = P.sd[b];
-            for (int64_t k = 0; k < d.ncpad; ++k) {
-                const int64_t src_k = std::min(k, d.nc - 1);
-                for (int e = 0; e < 3; ++e)
-                    hp[3 * (d.coff + k) + e] = chg[b].pos[3 * src_k + e];
-                hq[d.coff + k] = k < d.nc ? chg[b].q[k] : 0.0;
+        std::vector<double> hp, hq;
+        if (device_inputs) {
+            for (int b = 0; b < n_sys; ++b) {
+                const SysDesc &d = P.sd[b];
+                HIPCHK(hipMemcpyAsync(D.pos + 3 * d.coff, chg[b].pos, sizeof(double) * 3 * d.nc,
+                                      hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(D.q + d.coff, chg[b].q, sizeof(double) * d.nc,
+                                      hipMemcpyDeviceToDevice, s));
             }
+        } else {
+            hp.assign(3 * P.ctot, 0.0);
+            hq.assign(P.ctot, 0.0);
+            for (int b = 0; b < n_sys; ++b) {
+                const SysDesc &d = P.sd[b];
+                for (int64_t k = 0; k < d.nc; ++k) {
+                    for (int e = 0; e < 3; ++e)
+                        hp[3 * (d.coff + k) + e] = chg[b].pos[3 * k + e];
+                    hq[d.coff + k] = chg[b].q[k];
+                }
+            }
+            TRY(upload(c, D.pos, hp.data(), sizeof(double) * 3 * P.ctot));
+            TRY(upload(c, D.q, hq.data(), sizeof(double) * P.ctot));
         }
-        TRY(upload(c, D.pos, hp.data(), sizeof(double) * 3 * P.ctot));
-        TRY(upload(c, D.q, hq.data(), sizeof(double) * P.ctot));
         TRY(upload(c, D.sd, P.sd.data(), sizeof(SysDesc) * n_sys));
+        hipLaunchKernelGGL(kb_pad_charges, dim3(n_sys), dim3(TPB), 0, s, D.sd, D.pos, D.q);
+        LAUNCHCHK();
         TRY(upload(c, D.blk2sys, P.blk2sys.data(), sizeof(int32_t) * P.blk2sys.size()));
         TRY(upload(c, D.vblk2sys, P.vblk2sys.data(), sizeof(int32_t) * P.vblk2sys.size()));
         TRY(upload(c, D.cblk2sys, P.cblk2sys.data(), sizeof(int32_t) * P.cblk2sys.size()));
@@ -1598,17 +1644,24 @@ int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charg
                            D.cblk2sys, D.per);
         hipLaunchKernelGGL(kb_energy, dim3(n_sys), dim3(TPB), 0, s, D.per, 8, D.q, D.sd,
                            0.5 * 332.0716, D.e);
-        // outputs straight into caller host arrays go through device staging
+        // caller host arrays are filled through device staging, device arrays directly
         int64_t nct = 0;
         for (int b = 0; b < n_sys; ++b)
             nct += P.sd[b].nc;
-        TRY(ensure(c, c->io_y, sizeof(double) * 4 * nct));
-        double *gpos = as<double>(c->io_y), *gq = gpos + 3 * nct;
+        double *gpos = dE_dpos, *gq = dE_dq;
+        if (!device_inputs) {
+            TRY(ensure(c, c->io_y, sizeof(double) * 4 * nct));
+            gpos = as<double>(c->io_y);
+            gq = gpos + 3 * nct;
+        }
         hipLaunchKernelGGL(kb_force_out, dim3(cbk), dim3(TPB), 0, s, D.per, D.q, D.sd, D.cblk2sys,
                            0.5 * 332.0716, 1.0 / (4.0 * M_PI * p->eps_in), gpos, gq);
         LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(dE_dpos, gpos, sizeof(double) * 3 * nct, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(dE_dq, gq, sizeof(double) * nct, hipMemcpyDeviceToHost, s));
+        if (!device_inputs) {
+            HIPCHK(hipMemcpyAsync(dE_dpos, gpos, sizeof(double) * 3 * nct, hipMemcpyDeviceToHost,
+                                  s));
+            HIPCHK(hipMemcpyAsync(dE_dq, gq, sizeof(double) * nct, hipMemcpyDeviceToHost, s));
+        }
     }
     HIPCHK(hipMemcpyAsync(e_solv, D.e, sizeof(double) * n_sys, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

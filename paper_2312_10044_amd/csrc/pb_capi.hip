@@ -4,6 +4,7 @@
 // fed by one small device-to-host copy per Arnoldi step.
 #include "../../include/pbsolve.h"
 #include "pb_ctx.h"
+#include "pb_host.h"
 #include "pb_kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -188,6 +189,60 @@ int apply_pairwise(pb_ctx *c, const pb_params *p, int transpose, const double *x
     return PB_OK;
 }
 
+// Banded pairwise FP32 sweep: work items and record lists for the current
+// geometry and item target (target_waves / 64 items).
+int ensure_band_plan(pb_ctx *c)
+{
+    const Geo &g = c->g;
+    const int target = std::max(1, c->f32_waves / 64);
+    if (c->band_plan.npad == g.npad && c->band_plan.target == target)
+        return PB_OK;
+    std::vector<BandItem> items;
+    std::vector<int32_t> rec_start, rec_idx;
+    const BandPlan pl = plan_band(g.npad, target, items, rec_start, rec_idx);
+    TRY(ensure(c, c->band_items, sizeof(BandItem) * items.size()));
+    TRY(ensure(c, c->band_lists, sizeof(int32_t) * (rec_start.size() + rec_idx.size())));
+    HIPCHK(hipMemcpyAsync(c->band_items.p, items.data(), sizeof(BandItem) * items.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    int32_t *lists = as<int32_t>(c->band_lists);
+    HIPCHK(hipMemcpyAsync(lists, rec_start.data(), sizeof(int32_t) * rec_start.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(lists + rec_start.size(), rec_idx.data(),
+                          sizeof(int32_t) * rec_idx.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));   // host vectors go out of scope
+    c->band_plan = pl;
+    return PB_OK;
+}
+
+int apply_band(pb_ctx *c, const pb_params *p, int transpose, const double *x, double *y)
+{
+    const Geo &g = c->g;
+    TRY(ensure_band_plan(c));
+    const BandPlan &pl = c->band_plan;
+    TRY(ensure(c, c->sym_src, sizeof(float) * 12 * g.npad));
+    TRY(ensure(c, c->band_recs, sizeof(float) * 2 * TILE * (size_t)std::max<int64_t>(pl.n_records, 1)));
+    const PairParams pp = pair_params(c, p);
+    const double eps = pp.eps, sig = pp.sigma;
+    launch_pack_sym(c->stream, g, x, as<float>(c->sym_src), pp.cx, pp.cy, pp.cz, eps, sig,
+                    transpose ? 1 : 0);
+    LAUNCHCHK();
+    {
+        ProfScope ps(c, transpose ? PB_KERNEL_PAIRS_FP32_T : PB_KERNEL_PAIRS_FP32,
+                     (double)g.n * (double)(g.n - 1));
+        launch_pairs_f32_band(c->stream, as<float>(c->sym_src), as<BandItem>(c->band_items),
+                              pl.n_items, pl.n_tiles, pp, transpose ? 1 : 0,
+                              as<float>(c->band_recs));
+    }
+    LAUNCHCHK();
+    const int32_t *lists = as<int32_t>(c->band_lists);
+    const double s1 = transpose ? -sig * sig / eps : eps * sig * sig;
+    launch_band_finish(c->stream, g, as<float>(c->band_recs), lists, lists + pl.n_tiles + 1, x,
+                       0.5 * (1.0 + eps), 0.5 * (1.0 + 1.0 / eps), transpose ? 1 : 0, s1,
+                       sig * sig * sig, y);
+    LAUNCHCHK();
+    return PB_OK;
+}
+
 // Pairwise FP64 sweep, forward or transposed, on the same work items.
 int apply_pairwise64(pb_ctx *c, const pb_params *p, int transpose, const double *x, double *y)
 {
@@ -227,6 +282,8 @@ int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
     }
     if (precision == PB_FP32_IR && c->f32_tpt == PB_SWEEP_PAIRWISE)
         return apply_pairwise(c, p, transpose, x, y);
+    if (precision == PB_FP32_IR && c->f32_tpt == PB_SWEEP_BANDED)
+        return apply_band(c, p, transpose, x, y);
     if (precision == PB_FP64 && c->f64_kind == PB_SWEEP_PAIRWISE)
         return apply_pairwise64(c, p, transpose, x, y);
     const bool fast32 = precision == PB_FP32_IR && !transpose;
@@ -274,147 +331,6 @@ int apply(pb_ctx *c, const pb_params *p, int precision, int transpose, const dou
 
 }  // namespace
 
-namespace pbk {
-
-// Leaves of the octree over the collocation points (Sec. 2.2.3): the root is
-// the cube around the bounding box of the points; a cluster with more than n0
-// points splits into its eight child cubes (octant = (x >= cx) + 2 (y >= cy)
-// + 4 (z >= cz), child centres c +- h/2), empty children are dropped, leaves
-// are listed depth first in octant order, points in increasing index order.
-// The tree is built in place: each cluster is one range of `perm`, split by a
-// stable counting sort into its octants, so the ranges of the children follow
-// each other in octant order and the final `perm` lists the leaves depth
-// first.
-namespace {
-
-struct LeafFrame {
-    int64_t a, b;   // range of perm
-    double c[3], h;
-    int depth;
-};
-
-// Splits frame f of perm by octant (stable) and returns the child frames in
-// octant order; or, if f is a leaf, appends its leaf ends to `ends`.
-void split_frame(const double *x, const double *y, const double *z, int n0, const LeafFrame &f,
-                 int32_t *perm, int32_t *tmp, uint8_t *oct, std::vector<LeafFrame> &kids,
-                 std::vector<int32_t> &ends)
-{
-    kids.clear();
-    const int64_t m = f.b - f.a;
-    if (m <= n0 || f.depth >= 40) {
-        // at the depth limit (coincident points) the leaf is cut into
-        // consecutive runs of at most n0 points
-        for (int64_t a = f.a; a < f.b; a += n0)
-            ends.push_back((int32_t)std::min(f.b, a + (int64_t)n0));
-        return;
-    }
-    int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t k = f.a; k < f.b; ++k) {
-        const int32_t i = perm[k];
-        const int o =
-            (x[i] >= f.c[0] ? 1 : 0) + (y[i] >= f.c[1] ? 2 : 0) + (z[i] >= f.c[2] ? 4 : 0);
-        oct[k] = (uint8_t)o;
-        ++cnt[o];
-    }
-    int64_t off[9];
-    off[0] = f.a;
-    for (int o = 0; o < 8; ++o)
-        off[o + 1] = off[o] + cnt[o];
-    int64_t put[8];
-    for (int o = 0; o < 8; ++o)
-        put[o] = off[o];
-    for (int64_t k = f.a; k < f.b; ++k)
-        tmp[put[oct[k]]++] = perm[k];
-    std::copy(tmp + f.a, tmp + f.b, perm + f.a);
-    const double hh = 0.5 * f.h;
-    for (int o = 0; o < 8; ++o) {
-        if (cnt[o] == 0)
-            continue;
-        kids.push_back(LeafFrame{off[o], off[o + 1],
-                                 {f.c[0] + ((o & 1) ? hh : -hh), f.c[1] + ((o & 2) ? hh : -hh),
-                                  f.c[2] + ((o & 4) ? hh : -hh)},
-                                 hh, f.depth + 1});
-    }
-}
-
-// Depth-first build of the subtree of `root`; leaf ends in octant order.
-void build_subtree(const double *x, const double *y, const double *z, int n0,
-                   const LeafFrame &root, int32_t *perm, int32_t *tmp, uint8_t *oct,
-                   std::vector<int32_t> &ends)
-{
-    std::vector<LeafFrame> stack{root}, kids;
-    while (!stack.empty()) {
-        const LeafFrame f = stack.back();
-        stack.pop_back();
-        split_frame(x, y, z, n0, f, perm, tmp, oct, kids, ends);
-        // children pushed in reverse so they pop in octant order
-        for (auto it = kids.rbegin(); it != kids.rend(); ++it)
-            stack.push_back(*it);
-    }
-}
-
-}  // namespace
-
-// Octree over the collocation points: a cell with more than n0 points is split
-// at its centre into octants (stable), a cell with at most n0 points is a leaf;
-// perm lists the points leaf by leaf in depth-first octant order and
-// start[l] .. start[l + 1] delimits leaf l.  With `threads`, the subtrees of
-// the root's children are built on their own threads (disjoint ranges of
-// perm); the result does not depend on it.
-void build_leaves(const double *x, const double *y, const double *z, int64_t n, int n0,
-                  std::vector<int32_t> &perm, std::vector<int32_t> &start, bool threads)
-{
-    double lo[3] = {x[0], y[0], z[0]}, hi[3] = {x[0], y[0], z[0]};
-    for (int64_t i = 1; i < n; ++i) {
-        const double p[3] = {x[i], y[i], z[i]};
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = std::min(lo[k], p[k]);
-            hi[k] = std::max(hi[k], p[k]);
-        }
-    }
-    perm.resize(n);
-    for (int64_t i = 0; i < n; ++i)
-        perm[i] = (int32_t)i;
-    std::vector<int32_t> tmp(n);
-    std::vector<uint8_t> oct(n);
-    LeafFrame root{0, n, {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])},
-                   0.0, 0};
-    for (int k = 0; k < 3; ++k)
-        root.h = std::max(root.h, 0.5 * (hi[k] - lo[k]));
-    start.assign(1, 0);
-    std::vector<LeafFrame> kids;
-    std::vector<int32_t> ends;
-    split_frame(x, y, z, n0, root, perm.data(), tmp.data(), oct.data(), kids, ends);
-    if (kids.empty()) {
-        start.insert(start.end(), ends.begin(), ends.end());
-        return;
-    }
-    std::vector<std::vector<int32_t>> sub(kids.size());
-    const bool threaded = threads && n >= 16384;
-    std::vector<std::thread> pool;
-    for (size_t k = 0; k < kids.size(); ++k) {
-        auto job = [&, k] {
-            build_subtree(x, y, z, n0, kids[k], perm.data(), tmp.data(), oct.data(), sub[k]);
-        };
-        bool spawned = false;
-        if (threaded) {
-            try {
-                pool.emplace_back(job);
-                spawned = true;
-            } catch (const std::system_error &) {
-                // no thread available: build this subtree here
-            }
-        }
-        if (!spawned)
-            job();
-    }
-    for (auto &t : pool)
-        t.join();
-    for (const auto &s : sub)
-        start.insert(start.end(), s.begin(), s.end());
-}
-
-}  // namespace pbk
 
 namespace {
 
@@ -1154,7 +1070,8 @@ void pb_destroy(pb_ctx *c)
                       &c->t_nodes,
                       &c->t_ctr, &c->t_perm, &c->t_geo, &c->t_wv, &c->t_out, &c->t_mom,
                       &c->t_cnt, &c->b_sitems, &c->b_rs, &c->b_srow, &c->b_scol,
-                      &c->b_pc_sys, &c->dup_tab};
+                      &c->b_pc_sys, &c->dup_tab, &c->band_items, &c->band_lists,
+                      &c->band_recs};
     for (DevBuf *b : bufs)
         if (b->p)
             (void)hipFree(b->p);
@@ -1290,6 +1207,41 @@ static int pb_matvec_dev_impl(pb_ctx *c, int64_t n_vert, int64_t n_tri, const do
     TRY(apply(c, p, precision, transpose ? 1 : 0, d_x, d_y));
     HIPCHK(hipStreamSynchronize(c->stream));
     return PB_OK;
+}
+
+static int pb_source_dev_impl(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                              const int32_t *d_tri, int64_t nc, const double *d_pos,
+                              const double *d_q, const pb_params *p, double *d_b)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    TRY(check_charges_args(c, nc, d_pos, d_q));
+    if (!d_b)
+        return fail(c, PB_ERR_ARG, "output b is NULL");
+    TRY(setup_geometry(c, n_vert, n_tri, d_vert, d_tri));
+    launch_source(c->stream, c->g, nc, d_pos, d_q, p->eps_in, d_b);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PB_OK;
+}
+
+static int pb_energy_dev_impl(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                              const int32_t *d_tri, int64_t nc, const double *d_pos,
+                              const double *d_q, const pb_params *p, const double *d_phi,
+                              const double *d_dphi, double *e_solv)
+{
+    TRY(enter(c));
+    TRY(check_params(c, p, false));
+    TRY(check_charges_args(c, nc, d_pos, d_q));
+    if (!d_phi || !d_dphi || !e_solv)
+        return fail(c, PB_ERR_ARG, "phi, dphi or e_solv is NULL");
+    TRY(setup_geometry(c, n_vert, n_tri, d_vert, d_tri));
+    TRY(ensure(c, c->io_x, sizeof(double) * 2 * n_tri));
+    HIPCHK(hipMemcpyAsync(c->io_x.p, d_phi, sizeof(double) * n_tri, hipMemcpyDeviceToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(as<double>(c->io_x) + n_tri, d_dphi, sizeof(double) * n_tri,
+                          hipMemcpyDeviceToDevice, c->stream));
+    return energy_dev(c, p, nc, d_pos, d_q, as<double>(c->io_x), e_solv);
 }
 
 static int pb_energy_impl(pb_ctx *c, const pb_surface *s, const pb_charges *q, const pb_params *p,
@@ -1473,6 +1425,26 @@ int pb_matvec_dev_noalloc(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double
         TRY(enter(c));
         return matvec_noalloc(c, n_vert, n_tri, d_vert, d_tri, p, d_x, d_y, transpose ? 1 : 0,
                               precision);
+    }));
+}
+
+int pb_source_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                  const int32_t *d_tri, int64_t n_charges, const double *d_pos, const double *d_q,
+                  const pb_params *p, double *d_b)
+{
+    return leave(c, guarded(c, [&] {
+        return pb_source_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p,
+                                  d_b);
+    }));
+}
+
+int pb_energy_dev(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_vert,
+                  const int32_t *d_tri, int64_t n_charges, const double *d_pos, const double *d_q,
+                  const pb_params *p, const double *d_phi, const double *d_dphi, double *e_solv)
+{
+    return leave(c, guarded(c, [&] {
+        return pb_energy_dev_impl(c, n_vert, n_tri, d_vert, d_tri, n_charges, d_pos, d_q, p,
+                                  d_phi, d_dphi, e_solv);
     }));
 }
 
@@ -1678,8 +1650,9 @@ int pb_set_sweep_config(pb_ctx *c, int targets_per_thread, int target_waves)
     if (!c)
         return PB_ERR_ARG;
     if (targets_per_thread != 0 && targets_per_thread != 1 && targets_per_thread != 2 &&
-        targets_per_thread != PB_SWEEP_PAIRWISE)
-        return fail(c, PB_ERR_ARG, "sweep kind must be 1, 2 or PB_SWEEP_PAIRWISE");
+        targets_per_thread != PB_SWEEP_PAIRWISE && targets_per_thread != PB_SWEEP_BANDED)
+        return fail(c, PB_ERR_ARG,
+                    "sweep kind must be 1, 2, PB_SWEEP_PAIRWISE or PB_SWEEP_BANDED");
     if (target_waves < 0 || target_waves > (1 << 22))
         return fail(c, PB_ERR_ARG, "target_waves out of range");
     if (targets_per_thread)
@@ -1734,7 +1707,7 @@ static int pb_autotune_impl(pb_ctx *c, const pb_surface *s, const pb_params *p, 
     TRY(ensure(c, c->io_y, sizeof(double) * n2));
     launch_fill(c->stream, as<double>(c->io_x), 1.0, n2);
     LAUNCHCHK();
-    static const int tpts[] = {PB_SWEEP_PAIRWISE, 1, 2};
+    static const int tpts[] = {PB_SWEEP_PAIRWISE, PB_SWEEP_BANDED, 1, 2};
     static const int waves[] = {8192, 16384, 32768, 65536, 131072, 262144};
     hipEvent_t e0 = pool_event(c, 0), e1 = pool_event(c, 1);
     if (!e0 || !e1)
@@ -1805,6 +1778,33 @@ int pb_solve_batch(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_ch
 {
     return leave(c, guarded(c, [&] {
         return pb_solve_batch_impl(c, n_sys, surf, chg, p, e_solv, dE_dpos, dE_dq, info);
+    }));
+}
+
+static int pb_solve_batch_dev_impl(pb_ctx *c, int32_t n_sys, const pb_surface *surf,
+                                   const pb_charges *chg, const pb_params *p, double *e_solv,
+                                   double *d_dE_dpos, double *d_dE_dq, pb_info *info)
+{
+    const double t0 = now_s();
+    TRY(enter(c));
+    TRY(check_params(c, p, true));
+    const int want = (d_dE_dpos != nullptr) || (d_dE_dq != nullptr);
+    const int st = batch_solve(c, n_sys, surf, chg, p, want, e_solv, d_dE_dpos, d_dE_dq, info,
+                               nullptr, true);
+    if (info && st >= 0) {
+        const double dt = now_s() - t0;
+        for (int b = 0; b < n_sys; ++b)
+            info[b].seconds = dt;
+    }
+    return st;
+}
+
+int pb_solve_batch_dev(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
+                       const pb_params *p, double *e_solv, double *d_dE_dpos, double *d_dE_dq,
+                       pb_info *info)
+{
+    return leave(c, guarded(c, [&] {
+        return pb_solve_batch_dev_impl(c, n_sys, surf, chg, p, e_solv, d_dE_dpos, d_dE_dq, info);
     }));
 }
 

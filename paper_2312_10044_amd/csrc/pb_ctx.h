@@ -3,6 +3,7 @@
 #pragma once
 
 #include "../../include/pbsolve.h"
+#include "pb_host.h"
 #include "pb_kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -66,6 +67,9 @@ struct pb_ctx {
     int f64_kind = PB_SWEEP_PAIRWISE;   // FP64 sweep: 1 per-target, or pairwise
     int b_sym_tiles = 4;                 // batch: source tiles per pairwise work item
     pbk::SymPlan sym_plan;
+    // banded pairwise FP32 sweep: items, record lists (start, index), records
+    pbk::DevBuf band_items, band_lists, band_recs;
+    pbk::BandPlan band_plan;
     int sym_waves = 0;
     // treecode: tree, permuted geometry and weights, moments, results
     pbk::DevBuf t_nodes, t_ctr, t_perm, t_geo, t_wv, t_out, t_mom, t_cnt;
@@ -226,9 +230,6 @@ inline void prof_collect(pb_ctx *c)
 }
 
 
-// Octree leaves of n points for the block-diagonal preconditioner (pb_capi.hip).
-void build_leaves(const double *x, const double *y, const double *z, int64_t n, int n0,
-                  std::vector<int32_t> &perm, std::vector<int32_t> &start, bool threads = true);
 
 // Batched solve of independent systems (pb_batch.hip).
 int tree_matvec(pb_ctx *c, const pb_params *p, double theta, int order, int n0, const double *x,
@@ -250,6 +251,7 @@ int matvec_noalloc(pb_ctx *c, int64_t n_vert, int64_t n_tri, const double *d_ver
                    int transpose, int precision);
 int batch_solve(pb_ctx *c, int32_t n_sys, const pb_surface *surf, const pb_charges *chg,
                 const pb_params *p, int want_forces, double *e_solv, double *dE_dpos,
-                double *dE_dq, pb_info *info, BatchTune *tune = nullptr);
+                double *dE_dq, pb_info *info, BatchTune *tune = nullptr,
+                bool device_inputs = false);
 
 }  // namespace pbk

@@ -383,19 +383,19 @@ __device__ __forceinline__ void pair_both(const Src12 &s, const OwnF32 &o, const
     cq = FIRST ? u * yr : fmaf(u, yr, cq);
 }
 
-// Diagonal tile (sources = the block's own targets): forward direction, j = i
-// dropped.  Each thread owns TT targets, k * (TILE / TT) + threadIdx.x.
+// Diagonal tile (sources = the thread's own tile): forward direction, j = i
+// dropped.  The thread owns TT targets, k * (TILE / TT) + self of the tile.
 template <bool SCALED, int TT>
 __device__ __forceinline__ void sweep_diag(const SrcTileF32 &sh, const OwnF32 (&o)[TT],
-                                           const CoefF32 &cf, float (&P)[TT], float (&Q)[TT])
+                                           const CoefF32 &cf, float (&P)[TT], float (&Q)[TT],
+                                           int self)
 {
 #pragma unroll 2
     for (int jj = 0; jj < TILE; ++jj) {
         const Src12 s = sh.get(jj);
 #pragma unroll
         for (int k = 0; k < TT; ++k)
-            pair_fwd<SCALED, true>(s, o[k], cf, jj == k * (TILE / TT) + (int)threadIdx.x, P[k],
-                                   Q[k]);
+            pair_fwd<SCALED, true>(s, o[k], cf, jj == k * (TILE / TT) + self, P[k], Q[k]);
     }
 }
 
@@ -634,7 +634,7 @@ __device__ __forceinline__ void sym_item_f32(const Src12 *__restrict__ src, int 
         for (int k = 0; k < TT; ++k)
             P[k] = Q[k] = 0.f;
         if (J == I) {
-            sweep_diag<SCALED, TT>(sh, o, cf, P, Q);
+            sweep_diag<SCALED, TT>(sh, o, cf, P, Q, (int)threadIdx.x);
         } else {
             sweep_pairwise<SCALED, TT>(sh, o, cf, P, Q, colw[wid], lane);
             __syncthreads();
@@ -709,6 +709,94 @@ __device__ __forceinline__ void sym_item_f64(const Src8d *__restrict__ src, int 
         rp[k * NT + t] = aP[k];
         rp[TILE + k * NT + t] = aQ[k];
     }
+}
+
+// ---- banded pairwise FP32 sweep ----------------------------------------------
+//
+// A block of BAND_WAVES waves holds BAND_MT target tiles at once (two waves per
+// tile, two targets per lane, as in sym_item_f32), a macro tile.  A work item
+// is a band of consecutive macro tiles [m0, m1) against a run of source tiles
+// [j0, j1) (j0 at or after the band's first tile): for each macro tile the
+// block streams the run's tiles through LDS once; each wave evaluates its tile
+// against the source tile (both directions when J > I, forward only with j = i
+// dropped when J = I, nothing when J < I), keeps its row sums in registers
+// across the run, and leaves its column sums for the source tile in colw; the
+// block adds the waves' column sums, in wave order, to an LDS accumulator per
+// source tile of the run, which thus collects every target tile of the band.
+// Records (2 x TILE floats: row 1 then row 2) go to recs: one per (item, target
+// tile I) at rslot + I - first tile of the band, when the run reaches J >= I,
+// and one per (item, source tile J) at cslot + J - j0.  Every unordered tile
+// pair is evaluated by exactly one item.
+struct BandSmem {
+    SrcTileF32 sh;
+    float colw[BAND_WAVES][2 * TILE];
+    float colacc[BAND_RUN_MAX][2 * TILE];
+    int flags[BAND_WAVES];
+};
+
+template <bool SCALED>
+__device__ __forceinline__ void band_item_f32(const Src12 *__restrict__ src, const BandItem &it,
+                                              int T, const CoefF32 &cf, float *__restrict__ recs,
+                                              BandSmem &sm)
+{
+    constexpr int TT = SYM_TT, NT = TILE / SYM_TT, NB = BAND_WAVES * 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tw = w >> 1, tt = (w & 1) * 64 + lane;   // tile of the macro, thread within it
+    const int run = it.j1 - it.j0, i0 = it.m0 * BAND_MT;
+    for (int e = threadIdx.x; e < run * 2 * TILE; e += NB)
+        sm.colacc[e / (2 * TILE)][e % (2 * TILE)] = 0.f;
+    for (int M = it.m0; M < it.m1; ++M) {
+        const int I = M * BAND_MT + tw;
+        const bool mine = I < T;   // the last macro tile may reach past the mesh
+        OwnF32 o[TT];
+#pragma unroll
+        for (int k = 0; k < TT; ++k)
+            o[k] = own_point(src[(int64_t)(mine ? I : 0) * TILE + k * NT + tt]);
+        Acc<float> aP[TT], aQ[TT];
+        for (int J = it.j0; J < it.j1; ++J) {
+            __syncthreads();
+            if (threadIdx.x < TILE)
+                sm.sh.put(threadIdx.x, src[(int64_t)J * TILE + threadIdx.x]);
+            __syncthreads();
+            const int mode = (!mine || J < I) ? 0 : (J == I ? 1 : 2);
+            float P[TT], Q[TT];
+#pragma unroll
+            for (int k = 0; k < TT; ++k)
+                P[k] = Q[k] = 0.f;
+            if (mode == 2)
+                sweep_pairwise<SCALED, TT>(sm.sh, o, cf, P, Q, sm.colw[w], lane);
+            else if (mode == 1)
+                sweep_diag<SCALED, TT>(sm.sh, o, cf, P, Q, tt);
+            if (lane == 0)
+                sm.flags[w] = mode == 2;
+#pragma unroll
+            for (int k = 0; k < TT; ++k) {
+                aP[k].add(P[k]);
+                aQ[k].add(Q[k]);
+            }
+            __syncthreads();
+            float *acc = sm.colacc[J - it.j0];
+            for (int e = threadIdx.x; e < 2 * TILE; e += NB) {
+                float v = acc[e];
+#pragma unroll
+                for (int ww = 0; ww < BAND_WAVES; ++ww)
+                    v += sm.flags[ww] ? sm.colw[ww][e] : 0.f;
+                acc[e] = v;
+            }
+        }
+        if (mine && it.j1 > I) {
+            float *rr = recs + (int64_t)(it.rslot + I - i0) * (2 * TILE);
+#pragma unroll
+            for (int k = 0; k < TT; ++k) {
+                rr[k * NT + tt] = (float)aP[k].value();
+                rr[TILE + k * NT + tt] = (float)aQ[k].value();
+            }
+        }
+    }
+    __syncthreads();
+    float *cr = recs + (int64_t)it.cslot * (2 * TILE);
+    for (int e = threadIdx.x; e < run * 2 * TILE; e += NB)
+        cr[e] = sm.colacc[e / (2 * TILE)][e % (2 * TILE)];
 }
 
 inline __device__ CoefF32 coef_f32(double eps, double kappa, bool scaled)

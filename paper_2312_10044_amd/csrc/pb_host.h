@@ -1,0 +1,47 @@
+// Host-side logic of the library that needs no GPU: the octree leaves of the
+// block-diagonal preconditioner and the work plan of the banded pair sweep.  Plain C++17 (no HIP), so that a host build
+// with sanitizers tests it on the CPU.  Internal; not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace pbk {
+
+constexpr int TILE = 256;   // points per tile of the pair sweeps (staged in LDS per step)
+
+// Banded pairwise sweep (pb_kernels.h, sweep kind PB_SWEEP_BANDED): a block
+// of BAND_WAVES waves holds BAND_MT target tiles (a macro tile); a work item
+// is a band of macro tiles [m0, m1) against a run of source tiles [j0, j1),
+// j0 at or after the band's first tile.  Its records (2 x TILE floats each)
+// hold the rows of each target tile I of the band over the run (slot
+// rslot + I - BAND_MT m0, written when j1 > I) and the column sums of each
+// source tile J of the run over the band (slot cslot + J - j0).
+constexpr int BAND_WAVES = 8;
+constexpr int BAND_MT = 2 * BAND_WAVES * 64 / TILE;   // target tiles per macro tile (4)
+constexpr int BAND_RUN_MAX = 24;                      // source tiles per item (LDS)
+struct BandItem {
+    int32_t m0, m1, j0, j1, rslot, cslot, pad0, pad1;
+};
+struct BandPlan {
+    int64_t npad = 0;
+    int n_tiles = 0, n_items = 0, run = 0, band = 0, target = 0;
+    int64_t n_records = 0;
+};
+// Items for npad points (npad / TILE tiles), about target_items of them,
+// longest first; rec_start[K]..rec_start[K+1] of rec_idx list the records of
+// tile K's rows: its row records in run order, then its column records in
+// band order.  Every unordered tile pair (I <= J) belongs to exactly one item.
+BandPlan plan_band(int64_t npad, int target_items, std::vector<BandItem> &items,
+                   std::vector<int32_t> &rec_start, std::vector<int32_t> &rec_idx);
+
+// Octree leaves of n points (Sec. 2.2.3's tree, used for the leaf blocks of
+// Sec. 2.2.4): a cell with more than n0 points is split at its centre into
+// octants (stable), a cell with at most n0 points is a leaf; perm lists the
+// points leaf by leaf in depth-first octant order and start[l] .. start[l + 1]
+// delimits leaf l.  With `threads`, the subtrees of the root's children are
+// built on their own threads; the result does not depend on it.
+void build_leaves(const double *x, const double *y, const double *z, int64_t n, int n0,
+                  std::vector<int32_t> &perm, std::vector<int32_t> &start, bool threads = true);
+
+}  // namespace pbk

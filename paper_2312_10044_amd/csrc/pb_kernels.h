@@ -2,6 +2,8 @@
 // driver (pb_capi.hip).  Not part of the public ABI.
 #pragma once
 
+#include "pb_host.h"
+
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -10,7 +12,7 @@
 namespace pbk {
 
 constexpr int TPB = 256;        // threads per block of every pair kernel
-constexpr int TILE = 256;       // sources staged in LDS per step (== TPB)
+static_assert(TILE == TPB, "a tile is one block's worth of targets");
 constexpr int NGEO = 7;         // cx, cy, cz, nx, ny, nz, area
 constexpr int GEO_RED = 7;      // bad, 6*volume, sum cx, sum cy, sum cz, sum area, far
 constexpr double COORD_MAX = 1.0e5;   // |centroid coordinate| bound, A (padding sits at 2e6)
@@ -109,6 +111,22 @@ __host__ __device__ inline int64_t sym_pair_index(int64_t I, int64_t J, int64_t 
 {
     return I * T - I * (I + 1) / 2 + (J - I - 1);
 }
+// Banded pairwise FP32 sweep (sweep kind PB_SWEEP_BANDED): blocks of
+// BAND_WAVES waves hold BAND_MT target tiles (a macro tile); a work item is a
+// band of macro tiles [m0, m1) against a run of source tiles [j0, j1).  Its
+// records (2 x TILE floats each) hold the rows of each target tile I of the
+// band over the run (rslot + I - BAND_MT m0, written when j1 > I) and the
+// column sums of each source tile J of the run over the band (cslot + J - j0).
+// rec_start[K]..rec_start[K+1] of rec_idx list the records of tile K's rows:
+// its row records in run order, then its column records in band order.
+// (BandItem, BandPlan and plan_band live in pb_host.h.)
+void launch_pairs_f32_band(hipStream_t s, const float *src, const BandItem *items, int n_items,
+                           int n_tiles, const PairParams &pp, int transpose, float *recs);
+void launch_band_finish(hipStream_t s, const Geo &geo, const float *recs,
+                        const int32_t *rec_start, const int32_t *rec_idx, const double *x,
+                        double alpha, double beta, int transpose, double scale1, double scale2,
+                        double *y);
+
 // mode / transpose: 0 forward, 1 transposed (x = [l1; l2]).
 void launch_pack_sym(hipStream_t s, const Geo &geo, const double *x, float *src, double cx,
                      double cy, double cz, double eps, double sigma, int mode);

@@ -373,6 +373,63 @@ __global__ __launch_bounds__(SYM_NT) void k_pairs_f32_sym(const Src12 *__restric
                          rowpart + (int64_t)it.w * (2 * TILE), colpart, sh, colw);
 }
 
+template <bool SCALED>
+__global__ __launch_bounds__(BAND_WAVES * 64) void k_pairs_f32_band(const Src12 *__restrict__ src,
+                                                                   const BandItem *__restrict__ items,
+                                                                   int T, PairParams pp,
+                                                                   float *__restrict__ recs)
+{
+    __shared__ BandSmem sm;
+    const BandItem it = items[blockIdx.x];
+    band_item_f32<SCALED>(src, it, T, coef_f32(pp.eps, pp.kappa / pp.sigma, SCALED), recs, sm);
+}
+
+// Rows of the banded sweep: row k = K*TILE + l sums the records rec_idx
+// [rec_start[K], rec_start[K+1]); as in k_sym_finish, wave w of the block's
+// FIN_WAVES sums every FIN_WAVES-th record from record w on and the partial
+// sums are added in wave order.
+constexpr int BFIN_ROWS = 64, BFIN_WAVES = 4;
+
+__global__ __launch_bounds__(BFIN_ROWS * BFIN_WAVES) void k_band_finish(
+    const float *__restrict__ recs, const int32_t *__restrict__ rec_start,
+    const int32_t *__restrict__ rec_idx, int64_t n, const double *__restrict__ area,
+    const double *__restrict__ x, double alpha, double beta, int trans, double scale1,
+    double scale2, double *__restrict__ y)
+{
+    __shared__ double red[2][BFIN_WAVES][BFIN_ROWS];
+    const int lane = threadIdx.x % BFIN_ROWS, w = threadIdx.x / BFIN_ROWS;
+    const int64_t k = (int64_t)blockIdx.x * BFIN_ROWS + lane;
+    double s1 = 0.0, s2 = 0.0;
+    if (k < n) {
+        const int K = (int)(k / TILE), l = (int)(k % TILE);
+        for (int q = rec_start[K] + w; q < rec_start[K + 1]; q += BFIN_WAVES) {
+            const float *r = recs + (int64_t)rec_idx[q] * (2 * TILE);
+            s1 += (double)r[l];
+            s2 += (double)r[TILE + l];
+        }
+    }
+    red[0][w][lane] = s1;
+    red[1][w][lane] = s2;
+    __syncthreads();
+    if (w != 0 || k >= n)
+        return;
+    s1 = red[0][0][lane];
+    s2 = red[1][0][lane];
+#pragma unroll
+    for (int v = 1; v < BFIN_WAVES; ++v) {
+        s1 += red[0][v][lane];
+        s2 += red[1][v][lane];
+    }
+    if (trans) {
+        const double sc = area[k] * INV_4PI;
+        y[k] = alpha * x[k] - sc * scale2 * s2;
+        y[n + k] = beta * x[n + k] - sc * scale1 * s1;
+    } else {
+        y[k] = alpha * x[k] - INV_4PI * scale1 * s1;
+        y[n + k] = beta * x[n + k] - INV_4PI * scale2 * s2;
+    }
+}
+
 // Row k = K*TILE + l: item rows of tile K, then the contributions of every tile
 // I < K.  Blocks of 64 rows (one tile's worth of lanes, all in tile K); wave w
 // of the 4 sums every 4th record of both lists, from record w on, and the four
@@ -1083,6 +1140,26 @@ __global__ __launch_bounds__(TPB) void k_pc_apply(const double *__restrict__ inv
         v[r] = (r < m) ? x[pidx[s0 + r]] : x[qidx[s0 + r - m]];
     __syncthreads();
     const double *B = inv + boff[l];
+    if (!trans && m2 > 64) {
+        // y_r = sum_c B(r, c) v_c with the row-major block read along rows:
+        // one wave per row, lanes over columns, a wave sum per row
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        for (int r = w; r < m2; r += TPB / 64) {
+            double s = 0.0;
+            for (int c = lane; c < m2; c += 64)
+                s = fma(B[(int64_t)r * m2 + c], v[c], s);
+            s = wave_sum(s);
+            if (lane == 0) {
+                if (r < m)
+                    y[pidx[s0 + r]] = s;
+                else
+                    y[qidx[s0 + r - m]] = s;
+            }
+        }
+        return;
+    }
+    // a thread per row: the transposed product reads along the block's rows;
+    // small forward blocks (2m <= 64) stay in cache whichever way they are read
     for (int r = threadIdx.x; r < m2; r += TPB) {
         double s = 0.0;
         if (!trans) {
@@ -1385,6 +1462,31 @@ void launch_sym_finish(hipStream_t s, const Geo &geo, const double *rowpart,
                        dim3(FIN_ROWS * FIN_WAVES), 0, s, rowpart,
                        colpart, row_start, n_tiles, geo.n, geo.g + 6 * geo.npad, x,
                        alpha, beta, transpose, scale1, scale2, y);
+}
+
+void launch_pairs_f32_band(hipStream_t s, const float *src, const BandItem *items, int n_items,
+                           int n_tiles, const PairParams &pp, int transpose, float *recs)
+{
+    const auto *p = reinterpret_cast<const Src12 *>(src);
+    PairParams q = pp;
+    if (transpose)
+        q.eps = 1.0 / pp.eps;   // the pair constant of the transposed reduced form
+    if (f32_scaled(q))
+        hipLaunchKernelGGL(k_pairs_f32_band<true>, dim3(n_items), dim3(BAND_WAVES * 64), 0, s, p,
+                           items, n_tiles, q, recs);
+    else
+        hipLaunchKernelGGL(k_pairs_f32_band<false>, dim3(n_items), dim3(BAND_WAVES * 64), 0, s,
+                           p, items, n_tiles, q, recs);
+}
+
+void launch_band_finish(hipStream_t s, const Geo &geo, const float *recs,
+                        const int32_t *rec_start, const int32_t *rec_idx, const double *x,
+                        double alpha, double beta, int transpose, double scale1, double scale2,
+                        double *y)
+{
+    hipLaunchKernelGGL(k_band_finish, dim3((geo.n + BFIN_ROWS - 1) / BFIN_ROWS),
+                       dim3(BFIN_ROWS * BFIN_WAVES), 0, s, recs, rec_start, rec_idx, geo.n,
+                       geo.g + 6 * geo.npad, x, alpha, beta, transpose, scale1, scale2, y);
 }
 
 void launch_pack_sym64(hipStream_t s, const Geo &geo, const double *x, double *src, int mode)

@@ -26,6 +26,7 @@ PB_ERR_OOM = -5
 PB_FP64 = 0
 PB_FP32_IR = 1
 PB_SWEEP_PAIRWISE = 8   # pb_set_sweep_config kind: each unordered pair once
+PB_SWEEP_BANDED = 16    # FP32: pairwise with four target tiles per workgroup, banded items
 PB_KERNEL_PAIRS_FP64 = 0
 PB_KERNEL_PAIRS_FP32 = 1
 PB_KERNEL_PAIRS_FP64_T = 2
@@ -89,6 +90,13 @@ _PROTOS = {
                                      _vp, _int, _int]),
     "pb_solve_dev": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp,
                             ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
+    "pb_source_dev": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp,
+                             ctypes.POINTER(_Params), _vp]),
+    "pb_energy_dev": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp,
+                             ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_dbl)]),
+    "pb_solve_batch_dev": (_int, [_vp, ctypes.c_int32, ctypes.POINTER(_Surface),
+                                  ctypes.POINTER(_Charges), ctypes.POINTER(_Params), _vp, _vp,
+                                  _vp, ctypes.POINTER(_Info)]),
     "pb_forces": (_int, [_vp, ctypes.POINTER(_Surface), ctypes.POINTER(_Charges),
                          ctypes.POINTER(_Params), _vp, _vp, ctypes.POINTER(_Info)]),
     "pb_forces_dev": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp,
@@ -436,6 +444,43 @@ class Context:
                                           _dev(dE_dpos, "float64"), _dev(dE_dq, "float64"),
                                           ctypes.byref(info)))
         return Info.of(info)
+
+    def pb_source_dev(self, verts, tris, pos, q, params: Params, b):
+        """b [2 n_tri] <- [S1; S2] on device tensors."""
+        p = params.c()
+        self._check(self._L.pb_source_dev(self._h, verts.shape[0], tris.shape[0],
+                                          _dev(verts, "float64"), _dev(tris, "int32"), q.shape[0],
+                                          _dev(pos, "float64"), _dev(q, "float64"),
+                                          ctypes.byref(p), _dev(b, "float64")))
+        return b
+
+    def pb_energy_dev(self, verts, tris, pos, q, phi, dphi, params: Params) -> float:
+        p = params.c()
+        e = _dbl()
+        self._check(self._L.pb_energy_dev(self._h, verts.shape[0], tris.shape[0],
+                                          _dev(verts, "float64"), _dev(tris, "int32"), q.shape[0],
+                                          _dev(pos, "float64"), _dev(q, "float64"),
+                                          ctypes.byref(p), _dev(phi, "float64"),
+                                          _dev(dphi, "float64"), ctypes.byref(e)))
+        return float(e.value)
+
+    def pb_solve_batch_dev(self, systems, params: Params, dE_dpos=None, dE_dq=None):
+        """systems: list of (verts, tris, pos, q) device tensors (float64, int32,
+        float64, float64).  Returns (e [n_sys], infos); gradients, when wanted,
+        go to the device tensors dE_dpos [sum n_b, 3] and dE_dq [sum n_b]."""
+        n = len(systems)
+        surfs = (_Surface * n)()
+        chgs = (_Charges * n)()
+        for b, (v, t, pos, q) in enumerate(systems):
+            surfs[b] = _Surface(v.shape[0], t.shape[0], _dev(v, "float64"), _dev(t, "int32"))
+            chgs[b] = _Charges(q.shape[0], _dev(pos, "float64"), _dev(q, "float64"))
+        e = np.empty(n)
+        infos = (_Info * n)()
+        p = params.c()
+        self._check(self._L.pb_solve_batch_dev(self._h, n, surfs, chgs, ctypes.byref(p),
+                                               _vp(e.ctypes.data), _dev(dE_dpos, "float64"),
+                                               _dev(dE_dq, "float64"), infos))
+        return e, [Info.of(infos[b]) for b in range(n)]
 
     def pb_potential(self, verts, tris, pos, q, phi, dphi, points, params: Params):
         """(reaction, total) potential at interior points (BIE units)."""

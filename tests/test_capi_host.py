@@ -28,6 +28,13 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert L.pb_abi_version() == 1
 
 
+def test_library_carries_gfx950_device_code_only():
+    """The device code objects bundled in the library are built for gfx950 and
+    nothing else (a library without them cannot run on an MI355X)."""
+    from paper_2312_10044_amd import build
+    assert build.device_targets() == {"amdgcn-amd-amdhsa--gfx950"}
+
+
 def test_binding_prototypes_cover_the_header():
     from paper_2312_10044_amd import exported_symbols
     assert sorted(exported_symbols()) == _header_functions()

@@ -123,6 +123,32 @@ def test_batch_eight_systems_spanning_the_batch_workload_sizes(pb):
     assert abs(e[0] - ref.e_solv) <= 1e-10 * abs(ref.e_solv)
 
 
+def test_batch_device_entry_point_matches_host_one(pb, small_batch):
+    """pb_solve_batch_dev on device tensors gives the host entry point's
+    energies and gradients bit for bit (same kernels, same order)."""
+    import torch
+    m, ctx = pb
+    dev = torch.device("cuda:0")
+    P = m.Params(tol=1e-10, precond_leaf=16)
+    e_h, i_h, g_h, q_h = ctx.pb_solve_batch(small_batch, P, forces=True)
+    sys_d = [(torch.from_numpy(v).to(dev), torch.from_numpy(t.astype(np.int32)).to(dev),
+              torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev))
+             for v, t, pos, q in small_batch]
+    nct = sum(s[3].shape[0] for s in small_batch)
+    gpos = torch.empty((nct, 3), dtype=torch.float64, device=dev)
+    gq = torch.empty(nct, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    e_d, i_d = ctx.pb_solve_batch_dev(sys_d, P, gpos, gq)
+    _say(f"batch dev: E {e_d}")
+    assert np.array_equal(e_d, e_h)
+    assert [i.iters for i in i_d] == [i.iters for i in i_h]
+    assert np.array_equal(gpos.cpu().numpy(), g_h) and np.array_equal(gq.cpu().numpy(), q_h)
+    e_e, _i = ctx.pb_solve_batch_dev(sys_d, P)   # energies only (their own charge sweep)
+    e_e2, _i, _g, _q = ctx.pb_solve_batch(small_batch, P)
+    assert np.array_equal(e_e, e_e2)
+    assert np.max(np.abs(e_e - e_h) / np.abs(e_h)) <= 1e-13
+
+
 def test_batch_fp32_refined_energies(pb, small_batch):
     m, ctx = pb
     e64, _i, _g, _q = ctx.pb_solve_batch(small_batch, m.Params(tol=1e-12))

@@ -45,11 +45,11 @@ def _err(m, ctx, w, kappa=KAPPA, rows=None, seed=0, transpose=False):
     return max((np.abs(y[rows] - y1) / s1).max(), (np.abs(y[g.n + rows] - y2) / s2).max()), y
 
 
-@pytest.mark.parametrize("kind", ["pairwise", 1, 2])
+@pytest.mark.parametrize("kind", ["pairwise", "banded", 1, 2])
 @pytest.mark.parametrize("kappa", [KAPPA, 0.0])
 def test_fp32_sweep_kinds_all_rows(pb, star12, kind, kappa):
     m, ctx = pb
-    k = m.PB_SWEEP_PAIRWISE if kind == "pairwise" else kind
+    k = {"pairwise": m.PB_SWEEP_PAIRWISE, "banded": m.PB_SWEEP_BANDED}.get(kind, kind)
     ctx.set_sweep_config(k, 32768)
     _say(f"fp32 sweep kind={kind} kappa={kappa}: {star12.n_tri} triangles")
     err, _y = _err(m, ctx, star12, kappa=kappa)
@@ -199,3 +199,63 @@ def test_fp64_pairwise_full_size_sampled_rows(pb):
         err, _y = _err64(m, ctx, w, transpose, rows=rows, seed=2)
         _say(f"fp64 pairwise full size transpose={transpose}: {err:.3e}")
         assert err <= FP64_BAR
+
+
+@pytest.mark.parametrize("waves", [256, 8192, 131072, 1048576])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_banded_plan_shapes_both_directions_and_repeat(pb, star12, waves, transpose):
+    """The banded sweep over plans from a few long items (runs of up to 24
+    source tiles, bands of several macro tiles) to many short ones: the
+    oracle's matvec in both directions, and a repeated call bitwise
+    identical."""
+    m, ctx = pb
+    ctx.set_sweep_config(m.PB_SWEEP_BANDED, waves)
+    try:
+        err, y = _err(m, ctx, star12, seed=5, transpose=transpose)
+        _e2, y2 = _err(m, ctx, star12, seed=5, transpose=transpose)
+    finally:
+        ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
+    _say(f"banded waves={waves} transpose={transpose}: max |dy|/S = {err:.3e}")
+    assert err <= 5e-5
+    assert np.array_equal(y, y2)
+
+
+@pytest.mark.parametrize("freq,r0", [(2, 3.0), (8, 2.0)])
+def test_banded_small_meshes(pb, freq, r0):
+    """80 triangles (one tile: a macro tile of one real tile) and 1,280."""
+    m, ctx = pb
+    w = synth.star_protein(freq=freq, r0=r0, n_charges=1, seed=7) if freq == 2 else \
+        synth.kirkwood_sphere()
+    ctx.set_sweep_config(m.PB_SWEEP_BANDED, 131072)
+    try:
+        err, _y = _err(m, ctx, w)
+        err_t, _y = _err(m, ctx, w, transpose=True)
+    finally:
+        ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
+    assert err <= 5e-5 and err_t <= 5e-5
+
+
+def test_banded_full_sizes_sampled_rows_and_solve(pb):
+    """81,920 and 327,680 triangles on sampled rows, both directions, and a
+    refined solve with the banded sweep against the FP64 solve."""
+    import types
+    m, ctx = pb
+    ctx.set_sweep_config(m.PB_SWEEP_BANDED, 131072)
+    try:
+        w = synth.star_protein()
+        verts, tris = synth.large_star_surface()
+        big = types.SimpleNamespace(verts=verts, tris=tris)
+        for surf, n in ((w, w.n_tri), (big, tris.shape[0])):
+            rows = np.sort(np.random.default_rng(n).choice(n, 40, replace=False))
+            rows = np.concatenate([rows, [0, n - 1]])
+            for transpose in (False, True):
+                err, _y = _err(m, ctx, surf, rows=rows, seed=11, transpose=transpose)
+                _say(f"banded {n} triangles transpose={transpose}: max |dy|/S = {err:.3e}")
+                assert err <= 5e-5
+        i32, _p, _d = ctx.pb_solve(w.verts, w.tris, w.pos, w.q,
+                                   m.Params(tol=1e-7, precision=m.PB_FP32_IR, precond_leaf=24))
+    finally:
+        ctx.set_sweep_config(m.PB_SWEEP_PAIRWISE, 131072)
+    i64, _p, _d = ctx.pb_solve(w.verts, w.tris, w.pos, w.q, m.Params(tol=1e-12, precond_leaf=24))
+    assert i32.status == m.PB_OK
+    assert abs(i32.e_solv - i64.e_solv) <= 1e-6 * abs(i64.e_solv)

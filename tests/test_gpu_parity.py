@@ -293,6 +293,13 @@ def test_device_entry_points_match_host_ones(pb, star12):
     info_h, ph, dh = ctx.pb_solve(w.verts, w.tris, w.pos, w.q, _params(m, tol=1e-8))
     assert info.e_solv == info_h.e_solv
     assert np.array_equal(phi.cpu().numpy(), ph)
+    # sources and energy on device arrays: the host entry points' values
+    tb = torch.empty(2 * w.n_tri, dtype=torch.float64, device=dev)
+    ctx.pb_source_dev(tv, tt, tp, tq, _params(m), tb)
+    assert np.array_equal(tb.cpu().numpy(), ctx.pb_source(w.verts, w.tris, w.pos, w.q, _params(m)))
+    e_dev = ctx.pb_energy_dev(tv, tt, tp, tq, phi, dphi, _params(m))
+    assert e_dev == ctx.pb_energy(w.verts, w.tris, w.pos, w.q, ph, dh, _params(m))
+    assert e_dev == info.e_solv
 
 
 def test_interior_potential_and_coulomb_energy(pb, star12):

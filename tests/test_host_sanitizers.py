@@ -1,0 +1,157 @@
+"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer, on the CPU.
+
+* The oracle's C loops (oracle/dsbi_oracle.c), every entry point, on a
+  320-triangle icosphere: no sanitizer report, and the matvec loops agree
+  with the oracle's own dense matrix.
+* The library's host-side octree (paper_2312_10044_amd/csrc/pb_host.cpp, the
+  preconditioner's leaves): no sanitizer report, threaded and single-threaded
+  builds identical, and the leaves identical to the oracle's (index work:
+  bit-exact), including a cloud with coincident points that reaches the
+  depth limit.
+
+Any sanitizer report aborts the program (-fno-sanitize-recover=all).
+"""
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dsbi, precond
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+       "-g", "-O1"]
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+           UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+
+pytestmark = pytest.mark.skipif(shutil.which("gcc") is None or shutil.which("g++") is None,
+                                reason="needs gcc/g++")
+
+
+def _build(tmp_path, compiler, srcs, name, extra=()):
+    exe = os.path.join(str(tmp_path), name)
+    cmd = [compiler, *SAN, *extra, *srcs, "-o", exe, "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def test_oracle_loops_under_sanitizers(tmp_path):
+    exe = _build(tmp_path, "gcc", [os.path.join(ROOT, "tests", "c", "oracle_sanitize.c"),
+                                   os.path.join(ROOT, "oracle", "dsbi_oracle.c")],
+                 "oracle_sanitize", ["-std=c99", "-Wno-unknown-pragmas"])
+    w = synth.star_protein(freq=4, r0=6.0, n_charges=7, seed=3)
+    g = dsbi.geometry(w.verts, w.tris)
+    path = os.path.join(str(tmp_path), "in.bin")
+    with open(path, "wb") as f:
+        f.write(struct.pack("<2q", g.n, w.n_charges))
+        for a in (g.cen, g.nrm, g.area, w.pos, w.q):
+            f.write(np.ascontiguousarray(a, dtype="<f8").tobytes())
+    r = subprocess.run([exe, path], capture_output=True, text=True, timeout=300, env=ENV)
+    assert r.returncode == 0, r.stdout + r.stderr
+    vals = dict(line.split() for line in r.stdout.splitlines())
+    print(vals)
+    assert float(vals["matvec_vs_dense"]) <= 1e-13
+    assert float(vals["rows_subset"]) == 0.0
+    assert float(vals["subset_block"]) == 0.0
+    assert vals["finite"] == "1"
+
+
+def _leaves_run(exe, tmp_path, pts, n0):
+    inp = os.path.join(str(tmp_path), "pts.bin")
+    out = os.path.join(str(tmp_path), "leaves.bin")
+    with open(inp, "wb") as f:
+        f.write(struct.pack("<2q", pts.shape[0], n0))
+        f.write(np.ascontiguousarray(pts.T, dtype="<f8").tobytes())
+    r = subprocess.run([exe, inp, out], capture_output=True, text=True, timeout=300, env=ENV)
+    assert r.returncode == 0, r.stdout + r.stderr
+    data = np.fromfile(out, dtype="<i8")
+    n = pts.shape[0]
+    res, k = [], 0
+    for _ in range(2):
+        L = int(data[k])
+        start = data[k + 1:k + 2 + L]
+        perm = data[k + 2 + L:k + 2 + L + n]
+        k += 2 + L + n
+        res.append([perm[start[i]:start[i + 1]] for i in range(L)])
+    return res
+
+
+@pytest.mark.parametrize("n0", [1, 7, 24, 100])
+def test_host_octree_under_sanitizers_matches_the_oracle(tmp_path, n0):
+    exe = _build(tmp_path, "g++", [os.path.join(ROOT, "tests", "c", "host_leaves_check.cpp"),
+                                   os.path.join(ROOT, "paper_2312_10044_amd", "csrc",
+                                                "pb_host.cpp")],
+                 "host_leaves_check",
+                 ["-std=c++17", "-pthread", "-I",
+                  os.path.join(ROOT, "paper_2312_10044_amd", "csrc")])
+    w = synth.star_protein(freq=40, r0=12.0, n_charges=1, seed=9)   # 32,000 points: threaded
+    cen = dsbi.geometry(w.verts, w.tris).cen
+    rng = np.random.default_rng(n0)
+    cloud = rng.normal(size=(3000, 3))
+    cloud[100:160] = cloud[7]          # 61 coincident points: the depth limit cuts them
+    for pts in (cen, cloud):
+        threaded, single = _leaves_run(exe, tmp_path, pts, n0)
+        ref = precond.leaves(pts, n0)
+        assert len(threaded) == len(single) == len(ref)
+        for a, b, c in zip(threaded, single, ref):
+            assert np.array_equal(a, c) and np.array_equal(b, c)
+
+
+def test_banded_sweep_plan_under_sanitizers(tmp_path):
+    """Every unordered tile pair (I <= J) belongs to exactly one item; each
+    tile's record list holds exactly the row records of the items that sweep
+    it as a target (run reaching it) and the column records of the items whose
+    run holds it and whose band starts below it; record slots are distinct and
+    within n_records; run and band stay within their bounds."""
+    exe = _build(tmp_path, "g++", [os.path.join(ROOT, "tests", "c", "host_plan_check.cpp"),
+                                   os.path.join(ROOT, "paper_2312_10044_amd", "csrc",
+                                                "pb_host.cpp")],
+                 "host_plan_check",
+                 ["-std=c++17", "-pthread", "-I",
+                  os.path.join(ROOT, "paper_2312_10044_amd", "csrc")])
+    cases = [(256, 2048), (512, 1), (2560, 2048), (3072, 4), (3072, 100000), (81920, 2048),
+             (81920, 128), (327680, 2048), (327680, 64)]
+    args = [str(v) for c in cases for v in c]
+    r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=600, env=ENV)
+    assert r.returncode == 0, r.stderr
+    blocks = r.stdout.split("case ")[1:]
+    assert len(blocks) == len(cases)
+    MT, RUN_MAX = 4, 24
+    for blk in blocks:
+        lines = blk.splitlines()
+        npad, target, n_items, run, band, n_rec = (int(v) for v in lines[0].split())
+        T = npad // 256
+        assert 1 <= run <= RUN_MAX and band >= 1
+        items = [tuple(int(v) for v in ln.split()[1:]) for ln in lines if ln.startswith("item")]
+        lists = {int(ln.split()[1]): [int(v) for v in ln.split()[2:]]
+                 for ln in lines if ln.startswith("list")}
+        assert len(items) == n_items and len(lists) == T
+        cover = np.zeros((T, T), dtype=np.int32)
+        rows = {K: [] for K in range(T)}
+        cols = {K: [] for K in range(T)}
+        slots = []
+        for m0, m1, j0, j1, rslot, cslot in items:
+            i0, i1 = m0 * MT, min(T, m1 * MT)
+            assert 0 < j1 - j0 <= run and i0 <= j0 and m1 - m0 <= band
+            for I in range(i0, i1):
+                for J in range(max(j0, I), j1):
+                    cover[I, J] += 1
+                if j1 > I:
+                    rows[I].append(rslot + I - i0)
+            for J in range(j0, j1):
+                if J > i0:
+                    cols[J].append(cslot + J - j0)
+            slots += list(range(rslot, rslot + (i1 - i0))) + list(range(cslot, cslot + j1 - j0))
+        assert len(set(slots)) == len(slots) and max(slots) < n_rec
+        assert np.all(cover[np.triu_indices(T)] == 1) and np.all(cover[np.tril_indices(T, -1)] == 0)
+        for K in range(T):
+            assert sorted(lists[K]) == sorted(rows[K] + cols[K])
+            assert len(set(lists[K])) == len(lists[K])
+        # far fewer records than one per tile pair (the pairwise sweep's count)
+        if target == 2048 and T >= 320:
+            assert n_rec < T * (T + 1) // 2 * (0.5 if T < 1000 else 0.15)
