@@ -142,7 +142,7 @@ int ensure_sym_plan(pb_ctx *c)
     if (c->sym_plan.npad == g.npad && c->sym_waves == c->f32_waves)
         return PB_OK;
     std::vector<int32_t> items, row_start;
-    const SymPlan pl = plan_sym(g.npad, c->f32_waves, items, row_start);
+    const SymPlan pl = plan_sym(g.npad, std::max(1, c->f32_waves / (TPB / 64)), items, row_start);
     TRY(ensure(c, c->sym_items, sizeof(int32_t) * items.size()));
     TRY(ensure(c, c->sym_rowstart, sizeof(int32_t) * row_start.size()));
     HIPCHK(hipMemcpyAsync(c->sym_items.p, items.data(), sizeof(int32_t) * items.size(),

@@ -150,6 +150,71 @@ void build_leaves(const double *x, const double *y, const double *z, int64_t n, 
         start.insert(start.end(), s.begin(), s.end());
 }
 
+SymPlan plan_sym(int64_t npad, int target_blocks, std::vector<int32_t> &items,
+                 std::vector<int32_t> &row_start)
+{
+    SymPlan pl;
+    pl.npad = npad;
+    const int T = (int)(npad / TILE);
+    pl.n_tiles = T;
+    const int64_t work = (int64_t)T * (T + 1) / 2;   // tile pairs incl. the diagonal
+    const int64_t want = std::max(1, target_blocks);
+    const int L = (int)std::max<int64_t>(1, (work + want - 1) / want);
+    pl.tiles_per_item = L;
+    // strips only where the source stream is well past an XCD's 4 MB L2 (12 KB
+    // per FP32 tile, 16 KB per FP64 tile: 6 and 8 MB at 512 tiles); at 320
+    // tiles (81,920 points) the unsplit runs measured faster
+    const int NS = T >= SYM_STRIP_MIN_TILES ? 2 * XCDS : 1;
+    pl.strips = NS;
+    std::vector<int> edge(NS + 1);
+    for (int k = 0; k <= NS; ++k)
+        edge[k] = (int)((int64_t)k * T / NS);
+    struct Row {
+        int32_t I, j0, j1, slot;
+        int xcd;
+    };
+    std::vector<Row> rows;
+    row_start.assign(T + 1, 0);
+    int slot = 0;
+    for (int I = 0; I < T; ++I) {
+        row_start[I] = slot;
+        for (int k = 0; k < NS; ++k) {
+            const int a = std::max(I, edge[k]), e = edge[k + 1];
+            if (a >= e)
+                continue;
+            // the strip's part of the row in runs of at most L, of near-equal length
+            const int len = e - a, nr = (len + L - 1) / L;
+            for (int r = 0; r < nr; ++r) {
+                const int j0 = a + (int)((int64_t)r * len / nr);
+                const int j1 = a + (int)((int64_t)(r + 1) * len / nr);
+                rows.push_back({I, j0, j1, slot++, NS == 1 ? 0 : (k < XCDS ? k : NS - 1 - k)});
+            }
+        }
+    }
+    row_start[T] = slot;
+    pl.n_items = slot;
+    // per XCD, longest first (stable: ascending I, then J0, among equals)
+    std::vector<std::vector<int>> per(XCDS);
+    for (int k = 0; k < slot; ++k)
+        per[rows[k].xcd].push_back(k);
+    for (auto &v : per)
+        std::stable_sort(v.begin(), v.end(), [&](int a, int b) {
+            return rows[a].j1 - rows[a].j0 > rows[b].j1 - rows[b].j0;
+        });
+    items.clear();
+    items.reserve(4 * (size_t)slot);
+    size_t longest = 0;
+    for (const auto &v : per)
+        longest = std::max(longest, v.size());
+    for (size_t q = 0; q < longest; ++q)
+        for (int x = 0; x < XCDS; ++x)
+            if (q < per[x].size()) {
+                const Row &r = rows[per[x][q]];
+                items.insert(items.end(), {r.I, r.j0, r.j1, r.slot});
+            }
+    return pl;
+}
+
 BandPlan plan_band(int64_t npad, int target_items, std::vector<BandItem> &items,
                    std::vector<int32_t> &rec_start, std::vector<int32_t> &rec_idx)
 {

@@ -1,6 +1,7 @@
 // Host-side logic of the library that needs no GPU: the octree leaves of the
-// block-diagonal preconditioner and the work plan of the banded pair sweep.  Plain C++17 (no HIP), so that a host build
-// with sanitizers tests it on the CPU.  Internal; not part of the public ABI.
+// block-diagonal preconditioner and the work plans of the pairwise and banded
+// pair sweeps.  Plain C++17 (no HIP), so that a host build with sanitizers
+// tests it on the CPU.  Internal; not part of the public ABI.
 #pragma once
 
 #include <cstdint>
@@ -9,6 +10,32 @@
 namespace pbk {
 
 constexpr int TILE = 256;   // points per tile of the pair sweeps (staged in LDS per step)
+
+// The hardware hands the workgroups of a launch to the XCDs in turn
+// (workgroup b to XCD b mod XCDS); each XCD has its own L2.
+constexpr int XCDS = 8;
+
+// Work items of the pairwise sweeps (4 int32 each: I, J0, J1, slot): target
+// tile I against source tiles J0..J1-1 (J0 >= I; the tile J = I runs forward
+// only); slot is the item's row record, and row_start[K]..row_start[K+1] are
+// the slots of target tile K, in ascending J0.  Every tile pair I <= J < T
+// belongs to exactly one item.  From SYM_STRIP_MIN_TILES tiles on, the source
+// tiles are cut into 2 XCDS strips of equal width and no item crosses a strip
+// boundary; strips k and
+// 2 XCDS - 1 - k (equal numbers of tile pairs between them) belong to XCD k,
+// and the items are ordered so that launch position b holds an item of XCD
+// b mod XCDS, longest first on each XCD.  Each XCD then streams an eighth of
+// the sources through its L2.  About target_blocks items.
+constexpr int SYM_STRIP_MIN_TILES = 512;
+struct SymPlan {
+    int64_t npad = 0;
+    int n_tiles = 0;      // T = npad / TILE
+    int tiles_per_item = 0;
+    int n_items = 0;
+    int strips = 1;       // 2 XCDS, or 1 below SYM_STRIP_MIN_TILES tiles
+};
+SymPlan plan_sym(int64_t npad, int target_blocks, std::vector<int32_t> &items,
+                 std::vector<int32_t> &row_start);
 
 // Banded pairwise sweep (pb_kernels.h, sweep kind PB_SWEEP_BANDED): a block
 // of BAND_WAVES waves holds BAND_MT target tiles (a macro tile); a work item

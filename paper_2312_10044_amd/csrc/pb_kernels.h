@@ -98,14 +98,7 @@ void launch_pairs_f32_fwd(hipStream_t s, const Geo &geo, const float *src, const
 // rowpart[k][2][TILE] (FP64); the contributions of off-diagonal tile pair
 // (I, J) to the rows of tile J land in colpart[pair_index(I, J)][2][TILE]
 // (FP32).  row_start[K]..row_start[K+1] are the item slots of target tile K.
-struct SymPlan {
-    int64_t npad = 0;
-    int n_tiles = 0;      // T = npad / TILE
-    int tiles_per_item = 0;
-    int n_items = 0;
-};
-SymPlan plan_sym(int64_t npad, int target_waves, std::vector<int32_t> &items,
-                 std::vector<int32_t> &row_start);
+// SymPlan and plan_sym (the work items) are host code, in pb_host.h.
 // Upper-triangle index of tile pair (I, J), I < J < T.
 __host__ __device__ inline int64_t sym_pair_index(int64_t I, int64_t J, int64_t T)
 {

@@ -1326,48 +1326,6 @@ Sweep plan_sweep(int64_t n_targets, int64_t n_sources, int target_waves, int tpt
     return s;
 }
 
-SymPlan plan_sym(int64_t npad, int target_waves, std::vector<int32_t> &items,
-                 std::vector<int32_t> &row_start)
-{
-    SymPlan pl;
-    pl.npad = npad;
-    const int T = (int)(npad / TILE);
-    pl.n_tiles = T;
-    const int64_t work = (int64_t)T * (T + 1) / 2;   // tiles incl. the diagonal
-    int64_t want = target_waves / (TPB / 64);        // blocks
-    if (want < 1)
-        want = 1;
-    int L = (int)((work + want - 1) / want);
-    if (L < 1)
-        L = 1;
-    pl.tiles_per_item = L;
-    std::vector<int32_t> rows;   // (I, J0, J1, slot) in slot order
-    row_start.assign(T + 1, 0);
-    int slot = 0;
-    for (int I = 0; I < T; ++I) {
-        row_start[I] = slot;
-        for (int J0 = I; J0 < T; J0 += L) {
-            const int J1 = J0 + L < T ? J0 + L : T;
-            rows.insert(rows.end(), {I, J0, J1, slot});
-            ++slot;
-        }
-    }
-    row_start[T] = slot;
-    pl.n_items = slot;
-    // longest items first, so that the short tails fill in at the end
-    std::vector<int> order(slot);
-    for (int k = 0; k < slot; ++k)
-        order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return rows[4 * a + 2] - rows[4 * a + 1] > rows[4 * b + 2] - rows[4 * b + 1];
-    });
-    items.resize(4 * (size_t)slot);
-    for (int k = 0; k < slot; ++k)
-        for (int f = 0; f < 4; ++f)
-            items[4 * k + f] = rows[4 * order[k] + f];
-    return pl;
-}
-
 void launch_dup_check(hipStream_t s, const double *g, int64_t n, int64_t ld, int32_t *tab,
                       int64_t cap)
 {

@@ -35,6 +35,33 @@ def test_library_carries_gfx950_device_code_only():
     assert build.device_targets() == {"amdgcn-amd-amdhsa--gfx950"}
 
 
+def test_device_code_has_no_packed_fp32_arithmetic(tmp_path):
+    """The library is compiled with the packed-FP32 target feature turned off
+    (some packed forms have given wrong results on these GPUs).  The flag
+    reaches the host pass as well, which only warns that it does not know it;
+    what matters is the device code: its disassembly holds no packed FP32
+    add, multiply or FMA."""
+    import subprocess
+    from paper_2312_10044_amd import build
+    llvm = "/opt/rocm/lib/llvm/bin"
+    tools = [os.path.join(llvm, t) for t in ("llvm-objcopy", "clang-offload-bundler", "llvm-objdump")]
+    if not all(os.path.exists(t) for t in tools):
+        pytest.skip("ROCm LLVM tools not found")
+    objcopy, bundler, objdump = tools
+    fat, co = str(tmp_path / "fat.bin"), str(tmp_path / "co.elf")
+    subprocess.run([objcopy, f"--dump-section=.hip_fatbin={fat}", build.LIB], check=True,
+                   capture_output=True, timeout=60)
+    subprocess.run([bundler, "--type=o", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
+                    f"--input={fat}", f"--output={co}", "--unbundle"], check=True,
+                   capture_output=True, timeout=60)
+    asm = subprocess.run([objdump, "-d", "--mcpu=gfx950", co], check=True, capture_output=True,
+                         text=True, timeout=120).stdout
+    mnemonics = re.findall(r"^\s+(v_\w+)", asm, flags=re.M)
+    assert len(mnemonics) > 10000            # the kernels are there
+    packed = [m for m in mnemonics if re.fullmatch(r"v_pk_(?:add|mul|fma)_f32", m)]
+    assert packed == []
+
+
 def test_binding_prototypes_cover_the_header():
     from paper_2312_10044_amd import exported_symbols
     assert sorted(exported_symbols()) == _header_functions()

@@ -102,29 +102,86 @@ def test_host_octree_under_sanitizers_matches_the_oracle(tmp_path, n0):
             assert np.array_equal(a, c) and np.array_equal(b, c)
 
 
+def _plans(tmp_path, kind, cases):
+    exe = os.path.join(str(tmp_path), "host_plan_check")
+    if not os.path.exists(exe):
+        _build(tmp_path, "g++", [os.path.join(ROOT, "tests", "c", "host_plan_check.cpp"),
+                                 os.path.join(ROOT, "paper_2312_10044_amd", "csrc", "pb_host.cpp")],
+               "host_plan_check",
+               ["-std=c++17", "-pthread", "-I", os.path.join(ROOT, "paper_2312_10044_amd", "csrc")])
+    args = [str(v) for c in cases for v in (kind, *c)]
+    r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=600, env=ENV)
+    assert r.returncode == 0, r.stderr
+    blocks = r.stdout.split("case ")[1:]
+    assert len(blocks) == len(cases)
+    return blocks
+
+
+def test_pairwise_sweep_plan_under_sanitizers(tmp_path):
+    """Every tile pair (I <= J) belongs to exactly one item; row_start lists
+    each target tile's items in ascending J0 with consecutive slots; no item
+    crosses a strip of T/16 source tiles (from 512 tiles on; one strip
+    below); launch position b holds an item of XCD b mod 8 (strips k and
+    15 - k) in every round where all XCDs still have items, the items of an
+    XCD come longest first, and the XCDs get equal shares of the tile pairs
+    (within 10 %)."""
+    cases = [(256, 1), (512, 64), (2560, 8), (3072, 100000), (130816, 2048), (131072, 2048),
+             (81920, 16384), (81920, 1024), (327680, 32768), (327680, 4096)]
+    blocks = _plans(tmp_path, "sym", cases)
+    for blk in blocks:
+        lines = blk.splitlines()
+        npad, target, n_items, L, ns = (int(v) for v in lines[0].split()[1:])
+        T = npad // 256
+        assert ns == (16 if T >= 512 else 1)
+        items = [tuple(int(v) for v in ln.split()[1:]) for ln in lines if ln.startswith("item")]
+        rs = [int(v) for v in next(ln for ln in lines if ln.startswith("rowstart")).split()[1:]]
+        assert len(items) == n_items and len(rs) == T + 1 and rs[0] == 0 and rs[T] == n_items
+        edge = [k * T // ns for k in range(ns + 1)]
+        strip = np.searchsorted(edge, np.arange(T), side="right") - 1
+        xcd_of_strip = [k if k < 8 else 15 - k for k in range(16)] if ns == 16 else [0]
+        cover = np.zeros((T, T), dtype=np.int32)
+        by_slot = {}
+        work = np.zeros(8)
+        per_xcd = {x: [] for x in range(8)}
+        for b, (I, j0, j1, slot) in enumerate(items):
+            assert I <= j0 < j1 <= T and j1 - j0 <= L
+            assert strip[j0] == strip[j1 - 1]
+            cover[I, j0:j1] += 1
+            assert slot not in by_slot
+            by_slot[slot] = (I, j0)
+            x = xcd_of_strip[strip[j0]]
+            per_xcd[x].append((b, j1 - j0))
+            work[x] += j1 - j0
+        assert np.all(cover[np.triu_indices(T)] == 1) and np.all(cover[np.tril_indices(T, -1)] == 0)
+        for I in range(T):
+            got = [by_slot[s] for s in range(rs[I], rs[I + 1])]
+            assert all(g[0] == I for g in got)
+            assert [g[1] for g in got] == sorted(g[1] for g in got)
+        for x, v in per_xcd.items():
+            assert [n for _, n in v] == sorted((n for _, n in v), reverse=True)
+        if ns == 16:
+            rounds = min(len(v) for v in per_xcd.values())
+            for x, v in per_xcd.items():
+                assert all(b % 8 == x for b, _n in v[:rounds])
+            assert work.max() <= 1.1 * work.min()
+        else:
+            assert [b for b, _n in per_xcd[0]] == list(range(n_items))
+        print(f"T={T} target={target}: {n_items} items, L={L}, XCD work {work.min():.0f}-{work.max():.0f}")
+
+
 def test_banded_sweep_plan_under_sanitizers(tmp_path):
     """Every unordered tile pair (I <= J) belongs to exactly one item; each
     tile's record list holds exactly the row records of the items that sweep
     it as a target (run reaching it) and the column records of the items whose
     run holds it and whose band starts below it; record slots are distinct and
     within n_records; run and band stay within their bounds."""
-    exe = _build(tmp_path, "g++", [os.path.join(ROOT, "tests", "c", "host_plan_check.cpp"),
-                                   os.path.join(ROOT, "paper_2312_10044_amd", "csrc",
-                                                "pb_host.cpp")],
-                 "host_plan_check",
-                 ["-std=c++17", "-pthread", "-I",
-                  os.path.join(ROOT, "paper_2312_10044_amd", "csrc")])
     cases = [(256, 2048), (512, 1), (2560, 2048), (3072, 4), (3072, 100000), (81920, 2048),
              (81920, 128), (327680, 2048), (327680, 64)]
-    args = [str(v) for c in cases for v in c]
-    r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=600, env=ENV)
-    assert r.returncode == 0, r.stderr
-    blocks = r.stdout.split("case ")[1:]
-    assert len(blocks) == len(cases)
+    blocks = _plans(tmp_path, "band", cases)
     MT, RUN_MAX = 4, 24
     for blk in blocks:
         lines = blk.splitlines()
-        npad, target, n_items, run, band, n_rec = (int(v) for v in lines[0].split())
+        npad, target, n_items, run, band, n_rec = (int(v) for v in lines[0].split()[1:])
         T = npad // 256
         assert 1 <= run <= RUN_MAX and band >= 1
         items = [tuple(int(v) for v in ln.split()[1:]) for ln in lines if ln.startswith("item")]
