@@ -553,12 +553,14 @@ def main():
     ap.add_argument("--tree-freqs", default="",
                     help="mode tree: comma-separated star frequencies f (20 f^2 triangles, "
                          "radius scaled with f) for a break-even sweep")
-    ap.add_argument("--mode", choices=["solve", "matvec", "copy", "batch", "tree"],
+    ap.add_argument("--mode", choices=["solve", "matvec", "copy", "batch", "tree", "probe"],
                     default="solve",
                     help="solve: the benchmark; matvec: only --steps matvecs of --precision "
                          "(for counter runs); copy: a device copy of --copy-mib MiB (the "
                          "reference kernel that calibrates FETCH_SIZE/WRITE_SIZE); batch: only "
-                         "the 64-system leg; tree: treecode matvec vs the direct sums")
+                         "the 64-system leg; tree: treecode matvec vs the direct sums; probe: "
+                         "the library's counter-calibration kernels (known VALU operation "
+                         "counts), --steps launches of each kind")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--precond-leaf", type=int, default=None,
                     help="leaf size of the block-diagonal preconditioner (0 = none; default "
@@ -597,6 +599,15 @@ def main():
         run_tree(args)
         return
     ctx = Context(0, torch.cuda.current_stream())
+    if args.mode == "probe":
+        rec = {}
+        for name, kind in (("fma_f32", pbs.PB_PROBE_FMA_F32), ("fma_f64", pbs.PB_PROBE_FMA_F64),
+                           ("exp_f32", pbs.PB_PROBE_EXP_F32)):
+            ops = [ctx.probe_valu(kind) for _ in range(max(1, args.steps))]
+            rec[name] = {"launches": len(ops), "lane_ops_per_launch": ops[0]}
+        ctx.close()
+        print(json.dumps({"mode": "probe", **rec}), flush=True)
+        return
     if args.mode == "batch":
         out = {"mode": "batch", **batch_leg(ctx, args, max(1, args.steps))}
         ctx.close()

@@ -374,6 +374,24 @@ int pb_profile_reset(pb_ctx *ctx);
 /* launches, total_ms, pairs may each be NULL. */
 int pb_profile_read(pb_ctx *ctx, int kernel, int64_t *launches, double *total_ms, double *pairs);
 
+/* ---- counter calibration (profiling) ------------------------------------ */
+/* One launch of a probe kernel whose operation count is known exactly, on the
+ * context's stream; returns once it has finished.  For calibrating hardware
+ * counters (rocprofv3's VALU instruction and FLOP counts) against a known
+ * workload before reading them on the pair sweeps.  262,144 threads (1,024
+ * workgroups of 256) each run 8 independent chains of 1,024 steps:
+ *   PB_PROBE_FMA_F32: one FP32 fused multiply-add per step;
+ *   PB_PROBE_FMA_F64: one FP64 fused multiply-add per step;
+ *   PB_PROBE_EXP_F32: one FP32 hardware exp2 (a transcendental) and one FP32
+ *                     fused multiply-add per step.
+ * *lane_ops receives the number of steps summed over all lanes (2^31); the
+ * chains' set-up and final sum add 8 operations per thread at most.  Errors:
+ * PB_ERR_ARG for an unknown kind or NULL arguments. */
+#define PB_PROBE_FMA_F32 0
+#define PB_PROBE_FMA_F64 1
+#define PB_PROBE_EXP_F32 2
+int pb_probe_valu(pb_ctx *ctx, int kind, int64_t *lane_ops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1071,7 +1071,7 @@ void pb_destroy(pb_ctx *c)
                       &c->t_ctr, &c->t_perm, &c->t_geo, &c->t_wv, &c->t_out, &c->t_mom,
                       &c->t_cnt, &c->b_sitems, &c->b_rs, &c->b_srow, &c->b_scol,
                       &c->b_pc_sys, &c->dup_tab, &c->band_items, &c->band_lists,
-                      &c->band_recs};
+                      &c->band_recs, &c->probe_out};
     for (DevBuf *b : bufs)
         if (b->p)
             (void)hipFree(b->p);
@@ -1908,6 +1908,20 @@ int pb_profile_read(pb_ctx *c, int kernel, int64_t *launches, double *total_ms, 
         *total_ms = c->prof_ms[kernel];
     if (pairs)
         *pairs = c->prof_pairs[kernel];
+    return PB_OK;
+}
+
+int pb_probe_valu(pb_ctx *c, int kind, int64_t *lane_ops)
+{
+    if (!c || !lane_ops)
+        return PB_ERR_ARG;
+    if (kind < PB_PROBE_FMA_F32 || kind > PB_PROBE_EXP_F32)
+        return fail(c, PB_ERR_ARG, "probe kind %d out of range", kind);
+    HIPCHK(hipSetDevice(c->device));
+    TRY(ensure(c, c->probe_out, sizeof(double) * (size_t)PROBE_THREADS));
+    *lane_ops = launch_probe_valu(c->stream, kind, as<double>(c->probe_out));
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(c->stream));
     return PB_OK;
 }
 

@@ -85,6 +85,7 @@ struct pb_ctx {
     double volume = 0.0, area_sum = 0.0;
     double sigma_min = 1.0;   // inverse length scale of the mesh (f32_sigma)
     pbk::DevBuf dup_tab;      // coincident-centroid check (launch_dup_check)
+    pbk::DevBuf probe_out;    // pb_probe_valu's per-thread results
     // block-diagonal preconditioner of the current geometry
     pbk::DevBuf pc_idx, pc_inv;
     int64_t pc_leaves = 0;

@@ -190,6 +190,11 @@ void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, cons
                      const double *x, int trans, double *y);
 
 // out_k = scale * sum_l q_l / |x_k - y_l| over npts points (skip l == k).
+// Counter-calibration probe (pb_probe_valu): PROBE_THREADS threads run chains
+// of one operation kind; returns the number of probed operations (summed
+// over lanes); each thread writes its result to out[thread].
+constexpr int64_t PROBE_THREADS = 1024 * 256;
+int64_t launch_probe_valu(hipStream_t s, int kind, double *out);
 void launch_point_coulomb(hipStream_t s, int64_t npts, const double *pts, int64_t nc,
                           const double *pos, const double *q, double scale, int skip_self,
                           double *out);

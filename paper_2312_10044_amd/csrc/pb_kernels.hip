@@ -802,8 +802,10 @@ __global__ __launch_bounds__(TPB) void k_force_finish(const double *__restrict__
 // One workgroup per leaf of m <= PC_MAX_LEAF elements: the 2m x 2m block of A
 // on the leaf's indices (rows/columns [phi; psi] of the leaf) is assembled in
 // LDS and inverted in place by Gauss-Jordan elimination with partial (row)
-// pivoting; the inverse is stored row-major at inv + boff[leaf].  Applying
-// M^-1 is then one small dense matvec per leaf.  The index table pq holds the
+// pivoting; the inverse is stored column-major at inv + boff[leaf], so that
+// the forward apply (every GMRES step) reads it along columns, consecutive
+// rows in consecutive threads.  Applying M^-1 is then one small dense matvec
+// per leaf.  The index table pq holds the
 // phi and psi slots of the elements in leaf order.
 
 __global__ __launch_bounds__(TPB) void k_pc_index(const int32_t *__restrict__ perm, int64_t n,
@@ -828,7 +830,7 @@ constexpr int PC_SMALL_M2 = 64;   // largest block k_pc_build inverts in one wav
 
 // Gauss-Jordan inversion of the 2m x 2m block held in LDS rows of stride LD
 // (lane i: row i in registers, W >= 2m columns unrolled); writes the inverse
-// row-major to out.
+// column-major to out.
 template <int W, int LD>
 __device__ __forceinline__ void pc_invert(double *A, double *prow, int *piv, int *qinv, int m,
                                           double eps, double *__restrict__ out)
@@ -885,7 +887,7 @@ __device__ __forceinline__ void pc_invert(double *A, double *prow, int *piv, int
     }
     __syncthreads();
     for (int e = lane; e < m2 * m2; e += PC_LANES) {
-        const int r = e / m2, c = e - r * m2;
+        const int c = e / m2, r = e - c * m2;
         out[e] = A[piv[r] * LD + qinv[c]];
     }
 }
@@ -1113,7 +1115,7 @@ __global__ __launch_bounds__(PCB_THREADS) void k_pc_build_big(
         for (int j = 0; j < PCB_ROWS; ++j) {
             const int r = grp + PCB_GROUPS * j;
             if (r < m2)
-                out[(int64_t)qinv[r] * m2 + pc] = a[j];
+                out[(int64_t)pc * m2 + qinv[r]] = a[j];   // column-major
         }
     }
 }
@@ -1139,40 +1141,72 @@ __global__ __launch_bounds__(TPB) void k_pc_apply(const double *__restrict__ inv
     for (int r = threadIdx.x; r < m2; r += TPB)
         v[r] = (r < m) ? x[pidx[s0 + r]] : x[qidx[s0 + r - m]];
     __syncthreads();
-    const double *B = inv + boff[l];
-    if (!trans && m2 > 64) {
-        // y_r = sum_c B(r, c) v_c with the row-major block read along rows:
-        // one wave per row, lanes over columns, a wave sum per row
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        for (int r = w; r < m2; r += TPB / 64) {
-            double s = 0.0;
-            for (int c = lane; c < m2; c += 64)
-                s = fma(B[(int64_t)r * m2 + c], v[c], s);
-            s = wave_sum(s);
-            if (lane == 0) {
-                if (r < m)
-                    y[pidx[s0 + r]] = s;
-                else
-                    y[qidx[s0 + r - m]] = s;
-            }
-        }
-        return;
-    }
-    // a thread per row: the transposed product reads along the block's rows;
-    // small forward blocks (2m <= 64) stay in cache whichever way they are read
+    const double *B = inv + boff[l];   // column-major: B(r, c) = B[c m2 + r]
+    // a thread per row; forward reads down the columns (consecutive rows in
+    // consecutive threads), transposed along the rows
     for (int r = threadIdx.x; r < m2; r += TPB) {
         double s = 0.0;
         if (!trans) {
             for (int c = 0; c < m2; ++c)
-                s = fma(B[(int64_t)r * m2 + c], v[c], s);
+                s = fma(B[(int64_t)c * m2 + r], v[c], s);
         } else {
             for (int c = 0; c < m2; ++c)
-                s = fma(B[(int64_t)c * m2 + r], v[c], s);
+                s = fma(B[(int64_t)r * m2 + c], v[c], s);
         }
         if (r < m)
             y[pidx[s0 + r]] = s;
         else
             y[qidx[s0 + r - m]] = s;
+    }
+}
+
+// ---- counter-calibration probe ------------------------------------------------
+// Each thread runs PROBE_CH independent chains of PROBE_ITER steps of one
+// operation, so the count of that operation is known exactly:
+// KIND 0: x = fma(x, a, b) in FP32; 1: the same in FP64; 2: x = fma(exp2(x),
+// a, b) in FP32 (one hardware exp2, a transcendental, and one FMA per step;
+// with a = 1/2, b = 0 the chain stays at x = 1).  The chains are summed and
+// stored so that nothing is dropped as dead code.
+constexpr int PROBE_CH = 8, PROBE_ITER = 1024;
+
+template <int KIND>
+__global__ __launch_bounds__(TPB) void k_probe_valu(float a, float b, double *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if constexpr (KIND == 1) {
+        double x[PROBE_CH];
+#pragma unroll
+        for (int c = 0; c < PROBE_CH; ++c)
+            x[c] = 1.0 + (double)c * 0.125;
+        for (int it = 0; it < PROBE_ITER; ++it) {
+#pragma unroll
+            for (int c = 0; c < PROBE_CH; ++c)
+                x[c] = fma(x[c], (double)a, (double)b);
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int c = 0; c < PROBE_CH; ++c)
+            sum += x[c];
+        out[t] = sum;
+    } else {
+        float x[PROBE_CH];
+#pragma unroll
+        for (int c = 0; c < PROBE_CH; ++c)
+            x[c] = 1.0f + (float)c * 0.125f;
+        for (int it = 0; it < PROBE_ITER; ++it) {
+#pragma unroll
+            for (int c = 0; c < PROBE_CH; ++c) {
+                if constexpr (KIND == 0)
+                    x[c] = fmaf(x[c], a, b);
+                else
+                    x[c] = fmaf(__builtin_amdgcn_exp2f(x[c]), a, b);
+            }
+        }
+        float sum = 0.f;
+#pragma unroll
+        for (int c = 0; c < PROBE_CH; ++c)
+            sum += x[c];
+        out[t] = (double)sum;
     }
 }
 
@@ -1604,6 +1638,18 @@ void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, cons
 {
     hipLaunchKernelGGL(k_pc_apply, dim3((unsigned)n_leaves), dim3(TPB), 0, s, inv, boff, pidx,
                        qidx, lstart, x, trans, y);
+}
+
+int64_t launch_probe_valu(hipStream_t s, int kind, double *out)
+{
+    const dim3 grid((unsigned)(PROBE_THREADS / TPB)), block(TPB);
+    if (kind == 0)
+        hipLaunchKernelGGL(k_probe_valu<0>, grid, block, 0, s, 0.999f, 1e-3f, out);
+    else if (kind == 1)
+        hipLaunchKernelGGL(k_probe_valu<1>, grid, block, 0, s, 0.999f, 1e-3f, out);
+    else
+        hipLaunchKernelGGL(k_probe_valu<2>, grid, block, 0, s, 0.5f, 0.0f, out);
+    return PROBE_THREADS * PROBE_CH * PROBE_ITER;
 }
 
 void launch_point_coulomb(hipStream_t s, int64_t npts, const double *pts, int64_t nc,

@@ -34,6 +34,9 @@ PB_KERNEL_PAIRS_FP32_T = 3
 PB_KERNEL_SOURCE = 4
 PB_KERNEL_CHARGE = 5
 PB_KERNEL_TREE = 6
+PB_PROBE_FMA_F32 = 0    # pb_probe_valu kinds
+PB_PROBE_FMA_F64 = 1
+PB_PROBE_EXP_F32 = 2
 
 # Every function the header declares, with its C prototype in ctypes terms.
 _vp = ctypes.c_void_p
@@ -127,6 +130,7 @@ _PROTOS = {
     "pb_get_memory_used": (_int, [_vp, ctypes.POINTER(_i64)]),
     "pb_profile_enable": (_int, [_vp, _int]),
     "pb_profile_reset": (_int, [_vp]),
+    "pb_probe_valu": (_int, [_vp, _int, ctypes.POINTER(_i64)]),
     "pb_profile_read": (_int, [_vp, _int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
                                ctypes.POINTER(_dbl)]),
 }
@@ -572,6 +576,13 @@ class Context:
 
     def profile_reset(self):
         self._check(self._L.pb_profile_reset(self._h))
+
+    def probe_valu(self, kind: int) -> int:
+        """One launch of the counter-calibration probe; returns its exact
+        operation count (lane-level)."""
+        n = _i64()
+        self._check(self._L.pb_probe_valu(self._h, int(kind), ctypes.byref(n)))
+        return int(n.value)
 
     def profile_read(self, kernel: int):
         """(launches, total_ms, algorithmic pairs) accumulated for one kernel id."""
