@@ -346,7 +346,7 @@ __global__ __launch_bounds__(TPB) void kb_pack_sym64(const double *__restrict__ 
 }
 
 template <bool SCALED>
-__global__ __launch_bounds__(SYM_NT) void kb_pairs_f32_sym(const Src12 *__restrict__ src,
+__global__ __launch_bounds__(SYM_NT, SYM_MIN_WAVES) void kb_pairs_f32_sym(const Src12 *__restrict__ src,
                                                         const SysDesc *__restrict__ sd,
                                                         const SItem *__restrict__ items,
                                                         int64_t n_items,
@@ -511,14 +511,14 @@ __global__ __launch_bounds__(TPB) void kb_source(const double *__restrict__ g, i
             const double4 c = sh[kk];
             const double dx = xi - c.x, dy = yi - c.y, dz = zi - c.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double ir = rsqrt(r2);
+            const double ir = rsqrt_t(r2);
             const double cxd = nxi * dx + nyi * dy + nzi * dz;
             if (!adjoint) {
                 s1 += c.w * ir;
                 s2 += c.w * cxd * (ir * ir * ir);
             } else {
                 const double kr = kappa * (r2 * ir);
-                const double e = exp(-kr);
+                const double e = exp_neg(kr);
                 const double em1 = e - 1.0;
                 const double g2 = fma(eps, fma(kr, e, em1), epsm1);
                 s1 = fma(c.w * g2 * cxd, ir * ir * ir, s1);
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(TPB) void kb_charge_pairs(const Src8<double> *__res
                 const Src8<double> f = shf[jj];
                 const double dx = yx - f.x, dy = yy - f.y, dz = yz - f.z;
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                const double ir = rsqrt(r2);
+                const double ir = rsqrt_t(r2);
                 const double ir2 = ir * ir;
                 const double u = ir2 * ir;
                 const double md = f.mx * dx + f.my * dy + f.mz * dz;
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(TPB) void kb_charge_pairs(const Src8<double> *__res
                     continue;
                 }
                 const double kr = kappa * (r2 * ir);
-                const double e = exp(-kr);
+                const double e = exp_neg(kr);
                 const double em1 = e - 1.0;
                 const double tm1 = fma(kr, e, em1);
                 const double g2 = fma(eps, tm1, epsm1);

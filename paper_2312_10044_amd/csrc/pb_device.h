@@ -24,10 +24,18 @@ struct alignas(8 * sizeof(T)) Src8 {
 
 // ---- precision-specific primitives ---------------------------------------
 
+// 1/sqrt(x), x > 0 (FP64: the hardware estimate refined by fm::rsqrt_refine,
+// within 1 ulp)
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
+__device__ __forceinline__ double rsqrt_t(double x)
+{
+    return fm::rsqrt_refine(x, __builtin_amdgcn_rsq(x));
+}
 
-// exp(-t) for t >= 0
+// exp(-t) for t >= 0.  FP64 keeps the library exp here: the table lookup of
+// fm::exp_neg_pair is a memory access, which the pairwise sweep hides behind
+// eight pairs in flight per lane but the one-pair-per-step charge and
+// per-target loops do not (measured no faster).
 __device__ __forceinline__ float exp_neg(float t)
 {
     return __builtin_amdgcn_exp2f(t * -1.44269504088896340736f);
@@ -143,9 +151,12 @@ struct CoefF32 {
     float kappa, kexp, c13, k23;
 };
 
-// Targets per thread of the pairwise FP32 sweep (blocks of TILE / SYM_TT).
+// Targets per thread of the pairwise FP32 sweep (blocks of TILE / SYM_TT),
+// and the waves per SIMD its register budget must allow (5: at most 96
+// VGPRs; 4 waves measured slower).
 constexpr int SYM_TT = 2;
 constexpr int SYM_NT = TILE / SYM_TT;
+constexpr int SYM_MIN_WAVES = 5;
 
 template <int TPT, int DSLOT, bool SCALED>
 __device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&tg)[TPT][9],
@@ -207,6 +218,7 @@ struct OwnF32 {
     float x, y, z;
     float nx, ny, nz;
     float w1, w2n, nu;
+    float mx, my, mz;   // -n / 3: n_i.sn_j / -3 in one dot product
 };
 
 __device__ __forceinline__ OwnF32 own_point(const Src12 &e)
@@ -221,6 +233,9 @@ __device__ __forceinline__ OwnF32 own_point(const Src12 &e)
     o.w1 = e.w1;
     o.w2n = e.w2n;
     o.nu = e.nu;
+    o.mx = e.nx * 0.333333343f;
+    o.my = e.ny * 0.333333343f;
+    o.mz = e.nz * 0.333333343f;
     return o;
 }
 
@@ -306,7 +321,8 @@ __device__ __forceinline__ T rs_finish(const T (&a)[4], int lane)
 // One pair, forward direction only (source s on the own point o); with DIAG the
 // pair is dropped when `skip` (ir = 0 zeroes every term).  With d = x_j - x_i,
 // A = n_i.d, B = sn_j.d, C = n_i.sn_j, t3n = -tm1/3 and
-// b = (tm1 + 1 - 1/eps)/3 = c13 - t3n:
+// b = (tm1 + 1 - 1/eps)/3 = c13 - t3n (the own point carries m = -n_i/3, so
+// t3n C = tm1 (m.sn_j) and t3n itself is never formed):
 //   row 1 / eps += (e-1) w2n_j / r + b nu_j B u
 //   row 2       += u [A (nu_j B h3 + tm1 w2n_j + w1_j) + t3n C nu_j]
 template <bool SCALED, bool DIAG>
@@ -326,16 +342,15 @@ __device__ __forceinline__ void pair_fwd(const Src12 &s, const OwnF32 &o, const 
     const float em1 = e - 1.f;
     P = fmaf(em1 * ir, s.w2n, P);
     const float tm1 = fmaf(kr, e, em1);
-    const float t3n = tm1 * -0.333333343f;
-    const float b = cf.c13 - t3n;
+    const float b = fmaf(tm1, 0.333333343f, cf.c13);   // c13 - t3n
     const float A = o.nx * dx + o.ny * dy + o.nz * dz;
     const float B = s.nx * dx + s.ny * dy + s.nz * dz;
-    const float C = o.nx * s.nx + o.ny * s.ny + o.nz * s.nz;
+    const float C3 = o.mx * s.nx + o.my * s.ny + o.mz * s.nz;   // -C / 3
     const float md = s.nu * B;
     P = fmaf(b * u, md, P);
     const float h3 = fmaf(tm1, ir2, cf.k23 * e);
     const float inner = fmaf(md, h3, fmaf(tm1, s.w2n, s.w1));
-    Q = fmaf(u, fmaf(A, inner, (t3n * C) * s.nu), Q);
+    Q = fmaf(u, fmaf(A, inner, (tm1 * C3) * s.nu), Q);
 }
 
 // One pair, both directions: P, Q accumulate row i; cp, cq receive the
@@ -343,7 +358,7 @@ __device__ __forceinline__ void pair_fwd(const Src12 &s, const OwnF32 &o, const 
 // formula with i and j exchanged and d negated; in the notation of pair_fwd:
 //   row j, 1 / eps: (e-1) w2n_i / r + b nu_i A u
 //   row j, 2:       u [B (nu_i A h3 + tm1 w2n_i + w1_i) + t3n C nu_i]
-// so the pair costs 44 VALU operations and two transcendentals.
+// so the pair costs 43 VALU operations and two transcendentals.
 // FIRST starts cp, cq; otherwise the pair's contributions are added to them
 // (the thread's further targets on the same source).
 template <bool SCALED, bool FIRST>
@@ -363,13 +378,12 @@ __device__ __forceinline__ void pair_both(const Src12 &s, const OwnF32 &o, const
     P = fmaf(em1ir, s.w2n, P);
     const float p2 = FIRST ? em1ir * o.w2n : fmaf(em1ir, o.w2n, cp);
     const float tm1 = fmaf(kr, e, em1);
-    const float t3n = tm1 * -0.333333343f;
-    const float bu = (cf.c13 - t3n) * u;
+    const float bu = fmaf(tm1, 0.333333343f, cf.c13) * u;   // (c13 - t3n) u
     const float h3 = fmaf(tm1, ir2, cf.k23 * e);
     const float A = o.nx * dx + o.ny * dy + o.nz * dz;
     const float B = s.nx * dx + s.ny * dy + s.nz * dz;
-    const float C = o.nx * s.nx + o.ny * s.ny + o.nz * s.nz;
-    const float tc = t3n * C;
+    const float C3 = o.mx * s.nx + o.my * s.ny + o.mz * s.nz;   // -C / 3
+    const float tc = tm1 * C3;   // t3n C
     // source j on row i
     const float md = s.nu * B;
     P = fmaf(bu, md, P);

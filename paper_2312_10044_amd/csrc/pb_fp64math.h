@@ -16,33 +16,36 @@
 namespace pbk {
 namespace fm {
 
-// 2^(-j/32), j = 0..31, correctly rounded (the table of Tang's method).
-constexpr double EXP2_NEG_J32[32] = {
-    0x1.0000000000000p+0, 0x1.f50765b6e4540p-1, 0x1.ea4afa2a490dap-1, 0x1.dfc97337b9b5fp-1,
-    0x1.d5818dcfba487p-1, 0x1.cb720dcef9069p-1, 0x1.c199bdd85529cp-1, 0x1.b7f76f2fb5e47p-1,
-    0x1.ae89f995ad3adp-1, 0x1.a5503b23e255dp-1, 0x1.9c49182a3f090p-1, 0x1.93737b0cdc5e5p-1,
-    0x1.8ace5422aa0dbp-1, 0x1.82589994cce13p-1, 0x1.7a11473eb0187p-1, 0x1.71f75e8ec5f74p-1,
-    0x1.6a09e667f3bcdp-1, 0x1.6247eb03a5585p-1, 0x1.5ab07dd485429p-1, 0x1.5342b569d4f82p-1,
-    0x1.4bfdad5362a27p-1, 0x1.44e086061892dp-1, 0x1.3dea64c123422p-1, 0x1.371a7373aa9cbp-1,
-    0x1.306fe0a31b715p-1, 0x1.29e9df51fdee1p-1, 0x1.2387a6e756238p-1, 0x1.1d4873168b9aap-1,
-    0x1.172b83c7d517bp-1, 0x1.11301d0125b51p-1, 0x1.0b5586cf9890fp-1, 0x1.059b0d3158574p-1,
+// 2^(j/32), j = 0..31, correctly rounded (the table of Tang's method).
+constexpr double EXP2_J32[32] = {
+    0x1.0000000000000p+0, 0x1.059b0d3158574p+0, 0x1.0b5586cf9890fp+0, 0x1.11301d0125b51p+0,
+    0x1.172b83c7d517bp+0, 0x1.1d4873168b9aap+0, 0x1.2387a6e756238p+0, 0x1.29e9df51fdee1p+0,
+    0x1.306fe0a31b715p+0, 0x1.371a7373aa9cbp+0, 0x1.3dea64c123422p+0, 0x1.44e086061892dp+0,
+    0x1.4bfdad5362a27p+0, 0x1.5342b569d4f82p+0, 0x1.5ab07dd485429p+0, 0x1.6247eb03a5585p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.71f75e8ec5f74p+0, 0x1.7a11473eb0187p+0, 0x1.82589994cce13p+0,
+    0x1.8ace5422aa0dbp+0, 0x1.93737b0cdc5e5p+0, 0x1.9c49182a3f090p+0, 0x1.a5503b23e255dp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b7f76f2fb5e47p+0, 0x1.c199bdd85529cp+0, 0x1.cb720dcef9069p+0,
+    0x1.d5818dcfba487p+0, 0x1.dfc97337b9b5fp+0, 0x1.ea4afa2a490dap+0, 0x1.f50765b6e4540p+0,
 };
 
 // exp(-x) for 0 <= x < 4.6e7 (the reduced exponent must fit an int; with
-// kappa <= 100 and coordinates within 1e5 of the origin, kappa r stays below
-// 3.5e7) by Tang's table-driven method: with n = rint(32 x / ln 2) = 32 m + j,
-// e^-x = 2^-m 2^(-j/32) e^r where r = n ln2/32 - x, |r| <= ln 2 / 64 (ln 2 / 32
-// split into a 32-bit head, exact times n while n < 2^21, and the rounded
-// remainder).  e^r - 1 is r (1 + r/2 + ... + r^5/720) (truncation below
-// 3.4e-18 relative), and the result 2^-m (t + t (e^r - 1)) is rounded once
-// from the table entry t = 2^(-j/32): within 1.02 ulp of exp(-x) on [0, 708].
-// Beyond x = 708 the result is subnormal, beyond 745 it is 0; no overflow or
-// special value can occur, so the general function's range checks are left
-// out.
+// kappa <= 100 and coordinates within 1e5 of the origin, kappa r between real
+// points stays below 3.5e7.  The sweeps' padding points, 2e6 out and of
+// weight 0, reach larger arguments once kappa > 23; there the device's
+// float-to-int conversion saturates, m = -2^26, and the result is 0) by
+// Tang's table-driven method: with n = rint(-32 x / ln 2) =
+// 32 m + j (j = n mod 32, m = floor(n / 32)), e^-x = 2^m 2^(j/32) e^r where
+// r = -x - n ln2/32, |r| <= ln 2 / 64 (ln 2 / 32 split into a 32-bit head,
+// exact times n while |n| < 2^21, and the rounded remainder).  e^r - 1 is
+// r (1 + r/2 + ... + r^5/720) (truncation below 3.4e-18 relative), and the
+// result 2^m (t + t (e^r - 1)) is rounded once from the table entry
+// t = 2^(j/32): within 1.02 ulp of exp(-x) on [0, 708].  Beyond x = 708 the
+// result is subnormal, beyond 745 it is 0; no overflow or special value can
+// occur, so the general function's range checks are left out.
 PB_HD double exp_neg_pair(double x)
 {
-    const double n = __builtin_rint(x * 46.16624130844683);
-    const double r = fma(n, 5.9631716539705866e-12, fma(n, 0.02166084938653512, -x));
+    const double n = __builtin_rint(x * -46.16624130844683);   // <= 0
+    const double r = fma(-n, 5.9631716539705866e-12, fma(-n, 0.02166084938653512, -x));
     const int ni = (int)n;
     double p = 1.3888888888888889e-03;        // 1/720
     p = fma(p, r, 8.3333333333333332e-03);    // 1/120
@@ -50,8 +53,8 @@ PB_HD double exp_neg_pair(double x)
     p = fma(p, r, 1.6666666666666666e-01);    // 1/6
     p = fma(p, r, 0.5);
     p = fma(p, r, 1.0);
-    const double t = EXP2_NEG_J32[ni & 31];
-    return ldexp(fma(t, p * r, t), -(ni >> 5));
+    const double t = EXP2_J32[ni & 31];
+    return ldexp(fma(t, p * r, t), ni >> 5);
 }
 
 // 1/sqrt(x) for finite x > 0 from an estimate y of relative error eps:

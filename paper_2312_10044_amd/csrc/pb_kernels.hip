@@ -360,7 +360,7 @@ __global__ __launch_bounds__(TPB) void k_pack_sym(const double *__restrict__ g, 
 }
 
 template <bool SCALED>
-__global__ __launch_bounds__(SYM_NT) void k_pairs_f32_sym(const Src12 *__restrict__ src,
+__global__ __launch_bounds__(SYM_NT, SYM_MIN_WAVES) void k_pairs_f32_sym(const Src12 *__restrict__ src,
                                                        const int4 *__restrict__ items, int T,
                                                        PairParams pp,
                                                        double *__restrict__ rowpart,
@@ -573,7 +573,7 @@ __global__ __launch_bounds__(TPB) void k_source(const double *__restrict__ g, in
         for (int kk = 0; kk < cnt; ++kk) {
             const double4 c = sh[kk];
             const double dx = xi - c.x, dy = yi - c.y, dz = zi - c.z;
-            const double ir = rsqrt(dx * dx + dy * dy + dz * dz);
+            const double ir = rsqrt_t(dx * dx + dy * dy + dz * dz);
             s1 += c.w * ir;
             s2 += c.w * (nxi * dx + nyi * dy + nzi * dz) * (ir * ir * ir);
         }
@@ -612,12 +612,12 @@ __global__ __launch_bounds__(TPB) void k_charge_pairs(const Src8<double> *__rest
             const Src8<double> s = sh[jj];
             const double dx = yx - s.x, dy = yy - s.y, dz = yz - s.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double ir = rsqrt(r2);
+            const double ir = rsqrt_t(r2);
             const double u = ir * ir * ir;
             const double md = s.mx * dx + s.my * dy + s.mz * dz;
             if (MODE == 0) {
                 const double kr = kap * (r2 * ir);
-                const double e = exp(-kr);
+                const double e = exp_neg(kr);
                 const double em1 = e - 1.0;
                 const double tm1 = fma(kr, e, em1);
                 const double g2 = fma(eps, tm1, epsm1);
@@ -690,9 +690,9 @@ __global__ __launch_bounds__(TPB) void k_adjoint_rhs(const double *__restrict__ 
             const double4 c = sh[kk];
             const double dx = xj - c.x, dy = yj - c.y, dz = zj - c.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double ir = rsqrt(r2);
+            const double ir = rsqrt_t(r2);
             const double kr = kappa * (r2 * ir);
-            const double e = exp(-kr);
+            const double e = exp_neg(kr);
             const double em1 = e - 1.0;
             const double g2 = fma(eps, fma(kr, e, em1), epsm1);
             const double cxd = nxj * dx + nyj * dy + nzj * dz;
@@ -743,11 +743,11 @@ __global__ __launch_bounds__(TPB) void k_force_pairs(const Src8<double> *__restr
             const Src8<double> a = sha[jj];
             const double dx = yx - f.x, dy = yy - f.y, dz = yz - f.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double ir = rsqrt(r2);
+            const double ir = rsqrt_t(r2);
             const double ir2 = ir * ir;
             const double u = ir2 * ir;
             const double kr = kap * (r2 * ir);
-            const double e = exp(-kr);
+            const double e = exp_neg(kr);
             const double em1 = e - 1.0;
             const double g2 = fma(eps, fma(kr, e, em1), epsm1);
             const double md = f.mx * dx + f.my * dy + f.mz * dz;
@@ -908,10 +908,10 @@ __device__ __forceinline__ void pc_pair(const double (*gp)[LMAX], int r, int q, 
         const double nxi = gp[3][r], nyi = gp[4][r], nzi = gp[5][r];
         const double nxj = gp[3][q], nyj = gp[4][q], nzj = gp[5][q];
         const double r2 = dx * dx + dy * dy + dz * dz;
-        const double ir = rsqrt(r2);
+        const double ir = rsqrt_t(r2);
         const double ir2 = ir * ir, u = ir2 * ir;
         const double kr = kappa * (r2 * ir);
-        const double ee = exp(-kr);
+        const double ee = exp_neg(kr);
         const double em1 = ee - 1.0;
         const double tm1 = fma(kr, ee, em1);
         const double cx = nxi * dx + nyi * dy + nzi * dz;
@@ -1235,7 +1235,7 @@ __global__ __launch_bounds__(TPB) void k_point_coulomb(int64_t npts, const doubl
                 continue;
             const double4 c = sh[ll];
             const double dx = x - c.x, dy = y - c.y, dz = z - c.z;
-            s += c.w * rsqrt(dx * dx + dy * dy + dz * dz);
+            s += c.w * rsqrt_t(dx * dx + dy * dy + dz * dz);
         }
     }
     if (k < npts)

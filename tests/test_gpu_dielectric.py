@@ -8,7 +8,8 @@ reduced FP32 form, and the input guards of the C ABI.
   same constants.
 * kappa in {1e-13, 1e-6, 1e-3}: the FP32 sweeps measure lengths in a unit
   bounded below by the mesh's own length scale, so (sigma r)^-3 stays finite
-  however small kappa is.
+  however small kappa is; kappa in {30, 100}: the large end of the accepted
+  range.
 * Coincident centroids, far coordinates, kappa out of range and a device
   memory cap are rejected with their status codes and the context stays
   usable.
@@ -116,6 +117,22 @@ def test_solve_and_forces_other_dielectrics(pb, star12):
     _say(f"  forces max rel {np.abs(dpos - o_pos).max() / np.abs(o_pos).max():.2e}")
     assert np.abs(dpos - o_pos).max() <= 1e-8 * np.abs(o_pos).max()
     assert np.abs(dq - o_q).max() <= 1e-8 * np.abs(o_q).max()
+
+
+@pytest.mark.parametrize("kappa", [30.0, 100.0])
+def test_sweeps_at_large_kappa(pb, star12, kappa):
+    """kappa up to the accepted maximum: kappa r between a real point and the
+    sweeps' padding points (2e6 A out, weight 0) then passes the FP64
+    exponential's exact range, where its conversion saturates to a zero
+    result.  Both precisions, both directions, all rows against the oracle."""
+    m, ctx = pb
+    for precision, bar in ((0, FP64_BAR), (1, FP32_BAR)):
+        for transpose in (False, True):
+            err = _matvec_err(m, ctx, star12, precision, transpose, kappa, eps_in=1.0,
+                              eps_out=80.0)
+            _say(f"kappa={kappa:g} precision={precision} transpose={transpose}: "
+                 f"max |dy|/S = {err:.3e}")
+            assert err <= bar
 
 
 @pytest.mark.parametrize("kappa", [1e-13, 1e-6, 1e-3])
