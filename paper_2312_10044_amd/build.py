@@ -10,10 +10,20 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pb_kernels.hip", "pb_batch.h
 # plain C++ host logic (no device code), also built by the host sanitizer test
 HOST_SOURCES = [os.path.join(HERE, "csrc", "pb_host.cpp")]
 LIB = os.path.join(HERE, "libpbdsbi.so")
+# the same library with its host code under sanitizers (device code
+# unchanged), loaded only by the sanitizer tests: SAN_LIB with AddressSanitizer
+# and UndefinedBehaviorSanitizer (ROCm's ASan runtime preloaded; its
+# interceptor of HSA memory-pool allocations needs device ASan, so this one
+# runs without a GPU), UBSAN_LIB with UndefinedBehaviorSanitizer alone
+# (minimal runtime), which runs on the GPU
+SAN_LIB = os.path.join(HERE, "libpbdsbi_hostsan.so")
+UBSAN_LIB = os.path.join(HERE, "libpbdsbi_hostubsan.so")
+LLVM = "/opt/rocm/lib/llvm"
 ARCH = "gfx950"
 
 # Packed FP32 instructions are kept out of the build (they are not trusted on
-# this hardware); the flag is for the device compiler only.
+# this hardware).  The flag reaches the host pass too, which ignores it with a
+# warning: no driver form sends a -Xclang pair to the device pass alone.
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wall", "-Wno-unused-command-line-argument"]
@@ -63,6 +73,65 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"built device code targets {sorted(targets)}, expected only {ARCH}")
     os.replace(tmp, LIB)
     return LIB
+
+
+def sanitizer_runtime(name: str) -> str | None:
+    """A shared sanitizer runtime of ROCm's clang (libclang_rt.<name>-x86_64.so),
+    or None."""
+    base = os.path.join(LLVM, "lib", "clang")
+    if not os.path.isdir(base):
+        return None
+    for ver in sorted(os.listdir(base), reverse=True):
+        path = os.path.join(base, ver, "lib", "linux", f"libclang_rt.{name}-x86_64.so")
+        if os.path.exists(path):
+            return path
+    return None
+
+
+def build_hostsan(kind: str = "asan", verbose: bool = False) -> str:
+    """Always recompiles SAN_LIB (kind "asan": -fsanitize=address,undefined)
+    or UBSAN_LIB (kind "ubsan": -fsanitize=undefined, minimal runtime): every
+    -fsanitize after -Xarch_host, so the device code is built as in LIB; the
+    plain C++ host sources by ROCm's clang++ (the same runtime as the HIP host
+    code)."""
+    out = SAN_LIB if kind == "asan" else UBSAN_LIB
+    tmp = out + ".tmp"
+    if kind == "asan":
+        san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+               "-fno-omit-frame-pointer"]
+        host_san = ["-Xarch_host", "-fsanitize=address,undefined",
+                    "-Xarch_host", "-fno-sanitize-recover=all",
+                    "-Xarch_host", "-fno-omit-frame-pointer"]
+    else:
+        san = ["-fsanitize=undefined", "-fsanitize-minimal-runtime", "-fno-sanitize-recover=all"]
+        host_san = ["-Xarch_host", "-fsanitize=undefined",
+                    "-Xarch_host", "-fsanitize-minimal-runtime",
+                    "-Xarch_host", "-fno-sanitize-recover=all"]
+    objs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(HERE, os.path.splitext(os.path.basename(src))[0] + f"_{kind}.o")
+        cmd = [os.path.join(LLVM, "bin", "clang++"), "-O1", "-g", "-std=c++17", "-fPIC",
+               "-pthread", *san, "-c", src, "-o", obj]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("host compile failed:\n" + " ".join(cmd) + "\n" + res.stderr)
+        objs.append(obj)
+    flags = [f for f in HIPCC_FLAGS if f != "-O3"]
+    cmd = [hipcc(), "-O2", "-g", *flags, *host_san, "-shared-libsan", "-o", tmp, *SOURCES,
+           "-x", "none", *objs]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    for obj in objs:
+        os.remove(obj)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
+    if verbose and (res.stdout or res.stderr):
+        print(res.stdout + res.stderr)
+    targets = device_targets(tmp)
+    if targets != {f"amdgcn-amd-amdhsa--{ARCH}"}:
+        os.remove(tmp)
+        raise RuntimeError(f"built device code targets {sorted(targets)}, expected only {ARCH}")
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -9,6 +9,14 @@
   bit-exact), including a cloud with coincident points that reaches the
   depth limit.
 
+* The library's own host code (the C ABI, planning, context and buffer
+  handling in the .hip sources), built with ASan and UBSan on the host side
+  only (libpbdsbi_hostsan.so), and with UBSan alone (libpbdsbi_hostubsan.so):
+  their argument and error paths without a GPU.  ROCm's ASan runtime
+  intercepts HSA memory-pool allocations for device ASan, which this GPU
+  pool does not run, so tests/test_gpu_host_sanitizers.py runs every entry
+  point on the GPU with the UBSan build.
+
 Any sanitizer report aborts the program (-fno-sanitize-recover=all).
 """
 import os
@@ -212,3 +220,42 @@ def test_banded_sweep_plan_under_sanitizers(tmp_path):
         # far fewer records than one per tile pair (the pairwise sweep's count)
         if target == 2048 and T >= 320:
             assert n_rec < T * (T + 1) // 2 * (0.5 if T < 1000 else 0.15)
+
+
+def sanitized_library_env(kind: str = "asan"):
+    """Environment for a child process that loads a host-sanitized library:
+    kind "asan" (libpbdsbi_hostsan.so) with the ASan runtime preloaded ahead of
+    whatever the environment preloads; kind "ubsan" (libpbdsbi_hostubsan.so)
+    with the directory of the minimal UBSan runtime on the library path.
+    PB_SANITIZED_LIBRARY names the library for the child."""
+    from paper_2312_10044_amd import build
+    rt = build.sanitizer_runtime("asan" if kind == "asan" else "ubsan_minimal")
+    if rt is None:
+        pytest.skip(f"ROCm's {kind} runtime not found")
+    lib = build.SAN_LIB if kind == "asan" else build.UBSAN_LIB
+    if not os.path.exists(lib):
+        build.build_hostsan(kind)
+    env = dict(os.environ)
+    env["PB_SANITIZED_LIBRARY"] = lib
+    if kind == "asan":
+        env["LD_PRELOAD"] = rt + (":" + env["LD_PRELOAD"] if env.get("LD_PRELOAD") else "")
+        env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1:verify_asan_link_order=0"
+        env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
+    else:
+        d = os.path.dirname(rt)
+        env["LD_LIBRARY_PATH"] = d + (":" + env["LD_LIBRARY_PATH"]
+                                      if env.get("LD_LIBRARY_PATH") else "")
+    return env
+
+
+@pytest.mark.parametrize("kind", ["asan", "ubsan"])
+def test_library_host_code_error_paths_under_sanitizers(kind):
+    """Without a GPU: pb_create fails cleanly and every §8(b) call rejects
+    NULL arguments, with no sanitizer report."""
+    import sys
+    env = sanitized_library_env(kind)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "tests", "hostsan_driver.py"), "cpu"],
+                       capture_output=True, text=True, timeout=300, env=env)
+    print(r.stdout[-2000:], r.stderr[-3000:])
+    assert r.returncode == 0, r.stderr[-3000:]
+    assert "cpu ok" in r.stdout
