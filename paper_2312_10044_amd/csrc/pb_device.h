@@ -152,11 +152,12 @@ struct CoefF32 {
 };
 
 // Targets per thread of the pairwise FP32 sweep (blocks of TILE / SYM_TT),
-// and the waves per SIMD its register budget must allow (5: at most 96
-// VGPRs; 4 waves measured slower).
+// and the waves per SIMD its launch bounds ask for: 4 (the compiler then
+// keeps both targets' pair heads in registers; forcing 5, at most 96 VGPRs,
+// measured 0.4 % slower, and 6 waves 4 % slower).
 constexpr int SYM_TT = 2;
 constexpr int SYM_NT = TILE / SYM_TT;
-constexpr int SYM_MIN_WAVES = 5;
+constexpr int SYM_MIN_WAVES = 4;
 
 template <int TPT, int DSLOT, bool SCALED>
 __device__ __forceinline__ void sweep_f32(const Src8<float> *sh, const float (&tg)[TPT][9],
@@ -358,21 +359,40 @@ __device__ __forceinline__ void pair_fwd(const Src12 &s, const OwnF32 &o, const 
 // formula with i and j exchanged and d negated; in the notation of pair_fwd:
 //   row j, 1 / eps: (e-1) w2n_i / r + b nu_i A u
 //   row j, 2:       u [B (nu_i A h3 + tm1 w2n_i + w1_i) + t3n C nu_i]
-// so the pair costs 43 VALU operations and two transcendentals.
+// so the pair costs 43 VALU operations and two transcendentals.  It is split
+// in two: pair_head (d, 1/r, r and e, the two transcendentals) and pair_tail
+// (the rest), so that a lane can issue the heads of both its targets before
+// either tail and hide the transcendentals' latency behind the other
+// target's work.
+struct PairHead {
+    float dx, dy, dz, ir, r, e;
+};
+
+template <bool SCALED>
+__device__ __forceinline__ PairHead pair_head(const Src12 &s, const OwnF32 &o, const CoefF32 &cf)
+{
+    PairHead h;
+    h.dx = s.x - o.x;
+    h.dy = s.y - o.y;
+    h.dz = s.z - o.z;
+    const float r2 = h.dx * h.dx + h.dy * h.dy + h.dz * h.dz;
+    h.ir = __builtin_amdgcn_rsqf(r2);
+    h.r = r2 * h.ir;
+    h.e = __builtin_amdgcn_exp2f(cf.kexp * h.r);
+    return h;
+}
+
 // FIRST starts cp, cq; otherwise the pair's contributions are added to them
 // (the thread's further targets on the same source).
 template <bool SCALED, bool FIRST>
-__device__ __forceinline__ void pair_both(const Src12 &s, const OwnF32 &o, const CoefF32 &cf,
-                                          float &P, float &Q, float &cp, float &cq)
+__device__ __forceinline__ void pair_tail(const Src12 &s, const OwnF32 &o, const CoefF32 &cf,
+                                          const PairHead &h, float &P, float &Q, float &cp,
+                                          float &cq)
 {
-    const float dx = s.x - o.x, dy = s.y - o.y, dz = s.z - o.z;
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    const float ir = __builtin_amdgcn_rsqf(r2);
+    const float dx = h.dx, dy = h.dy, dz = h.dz, ir = h.ir, r = h.r, e = h.e;
     const float ir2 = ir * ir;
     const float u = ir2 * ir;
-    const float r = r2 * ir;
     const float kr = SCALED ? r : cf.kappa * r;
-    const float e = __builtin_amdgcn_exp2f(cf.kexp * r);
     const float em1 = e - 1.f;
     const float em1ir = em1 * ir;
     P = fmaf(em1ir, s.w2n, P);
@@ -420,11 +440,16 @@ __device__ __forceinline__ void pair_both_tt(const Src12 &s, const OwnF32 (&o)[T
                                              const CoefF32 &cf, float (&P)[TT], float (&Q)[TT],
                                              float &cp, float &cq)
 {
-    pair_both<SCALED, true>(s, o[0], cf, P[0], Q[0], cp, cq);
+    PairHead h[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k)
+        h[k] = pair_head<SCALED>(s, o[k], cf);
+    __builtin_amdgcn_sched_barrier(0);
+    pair_tail<SCALED, true>(s, o[0], cf, h[0], P[0], Q[0], cp, cq);
 #pragma unroll
     for (int k = 1; k < TT; ++k) {
         __builtin_amdgcn_sched_barrier(0);
-        pair_both<SCALED, false>(s, o[k], cf, P[k], Q[k], cp, cq);
+        pair_tail<SCALED, false>(s, o[k], cf, h[k], P[k], Q[k], cp, cq);
     }
 }
 
