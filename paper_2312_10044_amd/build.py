@@ -43,36 +43,56 @@ def device_targets(path: str = LIB) -> set:
     return {m.decode() for m in re.findall(rb"amdgcn-amd-amdhsa-[a-z0-9:+-]*gfx[0-9a-z]+", data)}
 
 
-def build(verbose: bool = False) -> str:
-    """Always recompiles; writes libpbdsbi.so atomically next to this file.
-
-    The plain C++ host sources are compiled to objects by the host compiler
-    first: given to hipcc as C++ sources next to the .hip files, they make it
-    drop --offload-arch and build the device code for its default target."""
-    tmp = LIB + ".tmp"
-    objs = []
-    for src in HOST_SOURCES:
-        obj = os.path.join(HERE, os.path.splitext(os.path.basename(src))[0] + ".o")
-        cmd = [os.environ.get("CXX", "g++"), "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall",
-               "-c", src, "-o", obj]
-        res = subprocess.run(cmd, capture_output=True, text=True)
-        if res.returncode != 0:
-            raise RuntimeError("host compile failed:\n" + " ".join(cmd) + "\n" + res.stderr)
-        objs.append(obj)
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *SOURCES, "-x", "none", *objs]
+def _run(cmd: list) -> subprocess.CompletedProcess:
     res = subprocess.run(cmd, capture_output=True, text=True)
-    for obj in objs:
-        os.remove(obj)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
-    if verbose and (res.stdout or res.stderr):
-        print(res.stdout + res.stderr)
+        raise RuntimeError("compile failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
+    return res
+
+
+def _link(out: str, hip_flags: list, host_objs: list, link_flags: list, tag: str,
+          verbose: bool) -> str:
+    """Compile every HIP source to its own object in parallel (one fat binary
+    per object), link them with the host objects into `out` (atomically),
+    and check that the device code is gfx950's only."""
+    from concurrent.futures import ThreadPoolExecutor
+    tmp = out + ".tmp"
+    objs = [os.path.join(HERE, os.path.splitext(os.path.basename(src))[0] + f"_{tag}.o")
+            for src in SOURCES]
+    compile_flags = [f for f in hip_flags if f != "-shared"]
+    cmds = [[hipcc(), *compile_flags, "-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+    try:
+        with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+            results = list(ex.map(_run, cmds))
+        # host objects after "-x none": given as C++ sources, hipcc would drop
+        # --offload-arch and build device code for its default target
+        res = _run([hipcc(), *hip_flags, *link_flags, "-o", tmp, *objs, "-x", "none", *host_objs])
+    finally:
+        for obj in objs + list(host_objs):
+            if os.path.exists(obj):
+                os.remove(obj)
+    if verbose:
+        for r in results + [res]:
+            if r.stdout or r.stderr:
+                print(r.stdout + r.stderr)
     targets = device_targets(tmp)
     if targets != {f"amdgcn-amd-amdhsa--{ARCH}"}:
         os.remove(tmp)
         raise RuntimeError(f"built device code targets {sorted(targets)}, expected only {ARCH}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Always recompiles; writes libpbdsbi.so atomically next to this file.
+    The plain C++ host sources are compiled to objects by the host compiler."""
+    objs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(HERE, os.path.splitext(os.path.basename(src))[0] + ".o")
+        _run([os.environ.get("CXX", "g++"), "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall",
+              "-c", src, "-o", obj])
+        objs.append(obj)
+    return _link(LIB, HIPCC_FLAGS, objs, [], "prod", verbose)
 
 
 def sanitizer_runtime(name: str) -> str | None:
@@ -95,7 +115,6 @@ def build_hostsan(kind: str = "asan", verbose: bool = False) -> str:
     plain C++ host sources by ROCm's clang++ (the same runtime as the HIP host
     code)."""
     out = SAN_LIB if kind == "asan" else UBSAN_LIB
-    tmp = out + ".tmp"
     if kind == "asan":
         san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                "-fno-omit-frame-pointer"]
@@ -110,28 +129,12 @@ def build_hostsan(kind: str = "asan", verbose: bool = False) -> str:
     objs = []
     for src in HOST_SOURCES:
         obj = os.path.join(HERE, os.path.splitext(os.path.basename(src))[0] + f"_{kind}.o")
-        cmd = [os.path.join(LLVM, "bin", "clang++"), "-O1", "-g", "-std=c++17", "-fPIC",
-               "-pthread", *san, "-c", src, "-o", obj]
-        res = subprocess.run(cmd, capture_output=True, text=True)
-        if res.returncode != 0:
-            raise RuntimeError("host compile failed:\n" + " ".join(cmd) + "\n" + res.stderr)
+        _run([os.path.join(LLVM, "bin", "clang++"), "-O1", "-g", "-std=c++17", "-fPIC",
+              "-pthread", *san, "-c", src, "-o", obj])
         objs.append(obj)
     flags = [f for f in HIPCC_FLAGS if f != "-O3"]
-    cmd = [hipcc(), "-O2", "-g", *flags, *host_san, "-shared-libsan", "-o", tmp, *SOURCES,
-           "-x", "none", *objs]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    for obj in objs:
-        os.remove(obj)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
-    if verbose and (res.stdout or res.stderr):
-        print(res.stdout + res.stderr)
-    targets = device_targets(tmp)
-    if targets != {f"amdgcn-amd-amdhsa--{ARCH}"}:
-        os.remove(tmp)
-        raise RuntimeError(f"built device code targets {sorted(targets)}, expected only {ARCH}")
-    os.replace(tmp, out)
-    return out
+    return _link(out, ["-O2", "-Xarch_host", "-g", *flags, *host_san], objs, ["-shared-libsan"],
+                 kind, verbose)
 
 
 if __name__ == "__main__":

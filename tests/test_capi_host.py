@@ -48,15 +48,24 @@ def test_device_code_has_no_packed_fp32_arithmetic(tmp_path):
     if not all(os.path.exists(t) for t in tools):
         pytest.skip("ROCm LLVM tools not found")
     objcopy, bundler, objdump = tools
-    fat, co = str(tmp_path / "fat.bin"), str(tmp_path / "co.elf")
+    fat = str(tmp_path / "fat.bin")
     subprocess.run([objcopy, f"--dump-section=.hip_fatbin={fat}", build.LIB], check=True,
                    capture_output=True, timeout=60)
-    subprocess.run([bundler, "--type=o", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
-                    f"--input={fat}", f"--output={co}", "--unbundle"], check=True,
-                   capture_output=True, timeout=60)
-    asm = subprocess.run([objdump, "-d", "--mcpu=gfx950", co], check=True, capture_output=True,
-                         text=True, timeout=120).stdout
-    mnemonics = re.findall(r"^\s+(v_\w+)", asm, flags=re.M)
+    data = open(fat, "rb").read()
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    starts = [m.start() for m in re.finditer(re.escape(magic), data)]
+    assert starts, "no offload bundle in the library"
+    mnemonics = []
+    for i, a in enumerate(starts):   # one bundle per compiled source
+        b = starts[i + 1] if i + 1 < len(starts) else len(data)
+        part, co = str(tmp_path / f"fat{i}.bin"), str(tmp_path / f"co{i}.elf")
+        open(part, "wb").write(data[a:b])
+        subprocess.run([bundler, "--type=o", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950",
+                        f"--input={part}", f"--output={co}", "--unbundle"], check=True,
+                       capture_output=True, timeout=60)
+        asm = subprocess.run([objdump, "-d", "--mcpu=gfx950", co], check=True,
+                             capture_output=True, text=True, timeout=120).stdout
+        mnemonics += re.findall(r"^\s+(v_\w+)", asm, flags=re.M)
     assert len(mnemonics) > 10000            # the kernels are there
     packed = [m for m in mnemonics if re.fullmatch(r"v_pk_(?:add|mul|fma)_f32", m)]
     assert packed == []
