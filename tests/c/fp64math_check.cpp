@@ -16,7 +16,7 @@
 #include <random>
 
 using pbk::fm::exp_neg_pair;
-using pbk::fm::EXP2_J32;
+using pbk::fm::EXP2_J256;
 using pbk::fm::rsqrt_refine;
 
 static long double ulp_of(long double v)
@@ -75,12 +75,12 @@ int main()
     std::printf("exp_tail_bad %d\n", bad_tail);
     std::printf("exp_tail_max_abs_in_min_subnormals %.6f\n", max_abs_tail / std::ldexp(1.0, -1074));
     std::printf("exp_beyond_745 %.17g\n", exp_neg_pair(745.2));
-    std::printf("exp_at_max_arg %.17g\n", exp_neg_pair(4.6e7));
-    // the table holds 2^(j/32) correctly rounded
+    std::printf("exp_at_max_arg %.17g\n", exp_neg_pair(5.8e6));
+    // the table holds 2^(j/256) correctly rounded
     double max_tab_ulp = 0.0;
-    for (int j = 0; j < 32; ++j) {
-        const long double ref = exp2l((long double)j / 32.0L);
-        const double u = (double)(fabsl((long double)EXP2_J32[j] - ref) / ulp_of(ref));
+    for (int j = 0; j < 256; ++j) {
+        const long double ref = exp2l((long double)j / 256.0L);
+        const double u = (double)(fabsl((long double)EXP2_J256[j] - ref) / ulp_of(ref));
         if (u > max_tab_ulp)
             max_tab_ulp = u;
     }
