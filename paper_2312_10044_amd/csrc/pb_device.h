@@ -270,9 +270,31 @@ struct SrcTileF32 {
     }
 };
 
+// Lane exchanges by DPP.  CTRL is one of the in-row permutations (row mirror
+// 0x140, half-row mirror 0x141, quad permutations 0x1B and 0xB1) with every
+// row and bank enabled, so each lane reads a valid lane and no lane keeps its
+// old value.  FP32: the old value 0 lets the compiler fold the exchange into
+// the add that consumes it (one DPP add).  FP64 adds take no DPP operand, so
+// the two halves of a double move by mov_dpp, whose undefined old value
+// spares the register initialisation an explicit one costs.
+template <int CTRL>
+__device__ __forceinline__ void dpp_ctrl_check()
+{
+    static_assert(CTRL == 0x140 || CTRL == 0x141 || CTRL == 0x1B || CTRL == 0xB1,
+                  "only full in-row permutations");
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    dpp_ctrl_check<CTRL>();
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v)
 {
+    dpp_ctrl_check<CTRL>();
     return __int_as_float(
         __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
@@ -281,8 +303,8 @@ template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = dpp_i<CTRL>((int)(b & 0xffffffffll));
+    const int hi = dpp_i<CTRL>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
