@@ -79,13 +79,15 @@ def _code_only(text: str) -> str:
 
 def kernel_digest(kind: int) -> str:
     """SHA-256 of the FP32 forward sweep's code (comments and layout
-    stripped): the shared device headers, the host work plans (they set the
-    order in which items reach the XCDs, hence the traffic) and the text of
-    the sweep kernel that `kind` selects."""
+    stripped): the shared device headers, the kernel interface header (it
+    fixes the FP32 length unit and the tile sizes), the host work plans (they
+    set the order in which items reach the XCDs, hence the traffic) and the
+    text of the sweep kernel that `kind` selects."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2312_10044_amd", "csrc")
     dev = "".join(open(os.path.join(csrc, f)).read()
-                  for f in ("pb_fp64math.h", "pb_device.h", "pb_host.h", "pb_host.cpp")
+                  for f in ("pb_fp64math.h", "pb_device.h", "pb_kernels.h", "pb_host.h",
+                            "pb_host.cpp")
                   if os.path.exists(os.path.join(csrc, f)))
     ker = open(os.path.join(csrc, "pb_kernels.hip")).read()
     name = fp32_kernel_name(kind)
