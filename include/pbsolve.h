@@ -392,6 +392,27 @@ int pb_profile_read(pb_ctx *ctx, int kernel, int64_t *launches, double *total_ms
 #define PB_PROBE_EXP_F32 2
 int pb_probe_valu(pb_ctx *ctx, int kind, int64_t *lane_ops);
 
+/* ---- the FP64 pair functions (testing) ------------------------------------ */
+/* exp_out[k] = exp(-x[k]) and rsqrt_out[k] = 1/sqrt(y[k]), evaluated on the
+ * device by the functions the FP64 pair sweeps use for the screened Coulomb
+ * kernel e^(-kappa r) / (4 pi r) (Sec. 2.2.1, eq. eq_potential): x = kappa r,
+ * y = r^2.  For testing their accuracy against a reference and against a
+ * host build of the same code.  Host arrays of n values each (0 <= n <=
+ * PB_PAIR_MATH_MAX; n = 0 does nothing), with 0 <= x[k] <= PB_PAIR_MATH_XMAX
+ * and PB_PAIR_MATH_YMIN <= y[k] <= PB_PAIR_MATH_YMAX (the sweeps stay far
+ * inside: kappa r below 3.5e8 even for their padding points, r^2 within
+ * [1e-10, 1e13]).  exp(-x) is within 1.32 ulp for x <= 708, subnormal up to
+ * x = 745.2 and 0 beyond; 1/sqrt(y) is within 1 ulp.  Returns once the
+ * results are in exp_out and rsqrt_out.
+ * Errors: PB_ERR_ARG (n out of range, NULL arrays, an argument outside its
+ * domain: nothing is written), PB_ERR_OOM, PB_ERR_HIP. */
+#define PB_PAIR_MATH_MAX (1 << 24)
+#define PB_PAIR_MATH_XMAX 1e12
+#define PB_PAIR_MATH_YMIN 1e-30
+#define PB_PAIR_MATH_YMAX 1e30
+int pb_eval_pair_math(pb_ctx *ctx, int64_t n, const double *x, const double *y,
+                      double *exp_out, double *rsqrt_out);
+
 #ifdef __cplusplus
 }
 #endif

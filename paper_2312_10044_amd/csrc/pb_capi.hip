@@ -1911,6 +1911,46 @@ int pb_profile_read(pb_ctx *c, int kernel, int64_t *launches, double *total_ms, 
     return PB_OK;
 }
 
+static int pb_eval_pair_math_impl(pb_ctx *c, int64_t n, const double *x, const double *y,
+                                  double *exp_out, double *rsqrt_out)
+{
+    TRY(enter(c));
+    if (n < 0 || n > PB_PAIR_MATH_MAX)
+        return fail(c, PB_ERR_ARG, "n = %lld outside [0, %d]", (long long)n, PB_PAIR_MATH_MAX);
+    if (n == 0)
+        return PB_OK;
+    if (!x || !y || !exp_out || !rsqrt_out)
+        return fail(c, PB_ERR_ARG, "an argument or result array is NULL");
+    for (int64_t k = 0; k < n; ++k) {
+        if (!(x[k] >= 0.0 && x[k] <= PB_PAIR_MATH_XMAX))
+            return fail(c, PB_ERR_ARG, "x[%lld] = %g outside [0, %g]", (long long)k, x[k],
+                        PB_PAIR_MATH_XMAX);
+        if (!(y[k] >= PB_PAIR_MATH_YMIN && y[k] <= PB_PAIR_MATH_YMAX))
+            return fail(c, PB_ERR_ARG, "y[%lld] = %g outside [%g, %g]", (long long)k, y[k],
+                        PB_PAIR_MATH_YMIN, PB_PAIR_MATH_YMAX);
+    }
+    const size_t bytes = sizeof(double) * (size_t)n;
+    TRY(ensure(c, c->io_x, 2 * bytes));
+    TRY(ensure(c, c->io_y, 2 * bytes));
+    double *dx = as<double>(c->io_x), *dy = as<double>(c->io_y);
+    HIPCHK(hipMemcpyAsync(dx, x, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dx + n, y, bytes, hipMemcpyHostToDevice, c->stream));
+    launch_eval_pair_math(c->stream, n, dx, dx + n, dy, dy + n);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(exp_out, dy, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(rsqrt_out, dy + n, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return PB_OK;
+}
+
+int pb_eval_pair_math(pb_ctx *c, int64_t n, const double *x, const double *y, double *exp_out,
+                      double *rsqrt_out)
+{
+    return leave(c, guarded(c, [&] {
+        return pb_eval_pair_math_impl(c, n, x, y, exp_out, rsqrt_out);
+    }));
+}
+
 int pb_probe_valu(pb_ctx *c, int kind, int64_t *lane_ops)
 {
     if (!c || !lane_ops)

@@ -195,6 +195,10 @@ void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, cons
 // over lanes); each thread writes its result to out[thread].
 constexpr int64_t PROBE_THREADS = 1024 * 256;
 int64_t launch_probe_valu(hipStream_t s, int kind, double *out);
+// ex[k] = exp(-x[k]) and rq[k] = 1/sqrt(y[k]) by the FP64 sweeps' own
+// functions, k < n (n < 2^31 * TPB).
+void launch_eval_pair_math(hipStream_t s, int64_t n, const double *x, const double *y,
+                           double *ex, double *rq);
 void launch_point_coulomb(hipStream_t s, int64_t npts, const double *pts, int64_t nc,
                           const double *pos, const double *q, double scale, int skip_self,
                           double *out);

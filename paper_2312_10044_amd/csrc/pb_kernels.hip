@@ -1160,6 +1160,21 @@ __global__ __launch_bounds__(TPB) void k_pc_apply(const double *__restrict__ inv
     }
 }
 
+// ---- the FP64 pair functions, evaluated one argument per thread -------------
+// exp(-x) and 1/sqrt(y) exactly as the FP64 pair sweeps compute them
+// (pb_eval_pair_math).
+__global__ __launch_bounds__(TPB) void k_eval_pair_math(int64_t n, const double *__restrict__ x,
+                                                        const double *__restrict__ y,
+                                                        double *__restrict__ ex,
+                                                        double *__restrict__ rq)
+{
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i < n) {
+        ex[i] = dev::exp_neg_pair(x[i]);
+        rq[i] = dev::rsqrt_pos(y[i]);
+    }
+}
+
 // ---- counter-calibration probe ------------------------------------------------
 // Each thread runs PROBE_CH independent chains of PROBE_ITER steps of one
 // operation, so the count of that operation is known exactly:
@@ -1638,6 +1653,13 @@ void launch_pc_apply(hipStream_t s, const double *inv, const int64_t *boff, cons
 {
     hipLaunchKernelGGL(k_pc_apply, dim3((unsigned)n_leaves), dim3(TPB), 0, s, inv, boff, pidx,
                        qidx, lstart, x, trans, y);
+}
+
+void launch_eval_pair_math(hipStream_t s, int64_t n, const double *x, const double *y,
+                           double *ex, double *rq)
+{
+    hipLaunchKernelGGL(k_eval_pair_math, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s,
+                       n, x, y, ex, rq);
 }
 
 int64_t launch_probe_valu(hipStream_t s, int kind, double *out)

@@ -37,6 +37,10 @@ PB_KERNEL_TREE = 6
 PB_PROBE_FMA_F32 = 0    # pb_probe_valu kinds
 PB_PROBE_FMA_F64 = 1
 PB_PROBE_EXP_F32 = 2
+PB_PAIR_MATH_MAX = 1 << 24   # pb_eval_pair_math limits
+PB_PAIR_MATH_XMAX = 1e12
+PB_PAIR_MATH_YMIN = 1e-30
+PB_PAIR_MATH_YMAX = 1e30
 
 # Every function the header declares, with its C prototype in ctypes terms.
 _vp = ctypes.c_void_p
@@ -131,6 +135,7 @@ _PROTOS = {
     "pb_profile_enable": (_int, [_vp, _int]),
     "pb_profile_reset": (_int, [_vp]),
     "pb_probe_valu": (_int, [_vp, _int, ctypes.POINTER(_i64)]),
+    "pb_eval_pair_math": (_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "pb_profile_read": (_int, [_vp, _int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
                                ctypes.POINTER(_dbl)]),
 }
@@ -583,6 +588,18 @@ class Context:
         n = _i64()
         self._check(self._L.pb_probe_valu(self._h, int(kind), ctypes.byref(n)))
         return int(n.value)
+
+    def eval_pair_math(self, x, y):
+        """(exp(-x), 1/sqrt(y)) by the FP64 pair sweeps' device functions."""
+        xx, px = _host(x, np.float64)
+        yy, py = _host(y, np.float64)
+        if xx.shape != yy.shape or xx.ndim != 1:
+            raise PbError(PB_ERR_ARG, "x and y must be 1-d arrays of one length")
+        ex = np.empty_like(xx)
+        rq = np.empty_like(yy)
+        self._check(self._L.pb_eval_pair_math(self._h, int(xx.size), px, py,
+                                              _vp(ex.ctypes.data), _vp(rq.ctypes.data)))
+        return ex, rq
 
     def profile_read(self, kernel: int):
         """(launches, total_ms, algorithmic pairs) accumulated for one kernel id."""
