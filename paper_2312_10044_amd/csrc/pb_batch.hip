@@ -370,7 +370,7 @@ __global__ __launch_bounds__(SYM_NT, SYM_MIN_WAVES) void kb_pairs_f32_sym(const 
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(SYM64_NT) void kb_pairs_f64_sym(const Src8d *__restrict__ src,
+__global__ __launch_bounds__(SYM64_NT, SYM64_MIN_WAVES) void kb_pairs_f64_sym(const Src8d *__restrict__ src,
                                                         const SysDesc *__restrict__ sd,
                                                         const SItem *__restrict__ items,
                                                         int64_t n_items,

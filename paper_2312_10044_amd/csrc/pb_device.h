@@ -593,9 +593,13 @@ __device__ __forceinline__ void pair64(const Src8d &s, const OwnF64 &o, const Co
 }
 
 // Sources per LDS stage and targets per thread of the pairwise FP64 sweep:
-// blocks of TILE / SYM64_TT threads, each owning SYM64_TT targets; the
-// source tile is staged in halves so that a block holds 12 KB of LDS.
-constexpr int SYM64_TT = 2;
+// blocks of TILE / SYM64_TT threads (one wave), each owning SYM64_TT targets,
+// so that every column reduction serves four pairs per lane; the source tile
+// is staged in quarters, 5 KB of LDS per block.  The kernels' launch bounds
+// ask for SYM64_MIN_WAVES waves per SIMD (at most 168 VGPRs; left free, the
+// compiler takes 185 and 2 waves).
+constexpr int SYM64_TT = 4;
+constexpr int SYM64_MIN_WAVES = 3;
 constexpr int SYM64_NT = TILE / SYM64_TT;
 constexpr int SYM64_NS = SYM64_NT;
 
@@ -722,7 +726,7 @@ __device__ __forceinline__ void sym_item_f32(const Src12 *__restrict__ src, int 
 }
 
 // FP64: blocks of SYM64_NT threads (SYM64_TT targets each); every source tile
-// is staged and swept in halves of SYM64_NS sources.
+// is staged and swept in parts of SYM64_NS sources.
 template <bool TRANS>
 __device__ __forceinline__ void sym_item_f64(const Src8d *__restrict__ src, int I, int J0,
                                              int J1, int T, const Coef<double> &cf,
@@ -755,8 +759,14 @@ __device__ __forceinline__ void sym_item_f64(const Src8d *__restrict__ src, int 
                 sweep_pairwise64<TRANS>(sh, o, cf, P, Q, colw[wid], lane);
                 __syncthreads();
                 double *cp = cp_base + sym_pair_index(I, J, T) * (2 * TILE);
-                cp[base + t] = colw[0][t] + colw[1][t];
-                cp[TILE + base + t] = colw[0][NS + t] + colw[1][NS + t];
+                double c0 = colw[0][t], c1 = colw[0][NS + t];
+#pragma unroll
+                for (int w = 1; w < NT / 64; ++w) {   // the block's waves in order
+                    c0 += colw[w][t];
+                    c1 += colw[w][NS + t];
+                }
+                cp[base + t] = c0;
+                cp[TILE + base + t] = c1;
             }
         }
 #pragma unroll

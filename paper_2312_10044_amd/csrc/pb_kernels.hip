@@ -516,7 +516,7 @@ __global__ __launch_bounds__(TPB) void k_pack_sym64(const double *__restrict__ g
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(SYM64_NT) void k_pairs_f64_sym(const Src8d *__restrict__ src,
+__global__ __launch_bounds__(SYM64_NT, SYM64_MIN_WAVES) void k_pairs_f64_sym(const Src8d *__restrict__ src,
                                                        const int4 *__restrict__ items, int T,
                                                        PairParams pp,
                                                        double *__restrict__ rowpart,
