@@ -381,6 +381,7 @@ __global__ __launch_bounds__(SYM64_NT, SYM64_MIN_WAVES) void kb_pairs_f64_sym(co
 {
     __shared__ Src8d sh[SYM64_NS];
     __shared__ double colw[SYM64_NT / 64][2 * SYM64_NS];
+    __shared__ double acc[2 * SYM64_TT][SYM64_NT];
     PairParams pp;
     pp.eps = eps;
     pp.kappa = kappa;
@@ -393,7 +394,7 @@ __global__ __launch_bounds__(SYM64_NT, SYM64_MIN_WAVES) void kb_pairs_f64_sym(co
         const SysDesc d = sd[w.sys];
         sym_item_f64<TRANS>(src + d.goff, w.I, w.J0, w.J1, d.T, cf,
                             rowpart + (int64_t)w.slot * (2 * TILE),
-                            colpart + d.cp0 * (2 * TILE), sh, colw);
+                            colpart + d.cp0 * (2 * TILE), sh, colw, acc);
     }
 }
 

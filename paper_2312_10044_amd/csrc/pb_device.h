@@ -732,7 +732,8 @@ __device__ __forceinline__ void sym_item_f64(const Src8d *__restrict__ src, int 
                                              int J1, int T, const Coef<double> &cf,
                                              double *__restrict__ rp,
                                              double *__restrict__ cp_base, Src8d *sh,
-                                             double (*colw)[2 * SYM64_NS])
+                                             double (*colw)[2 * SYM64_NS],
+                                             double (*acc)[SYM64_NT])
 {
     constexpr int TT = SYM64_TT, NT = SYM64_NT, NS = SYM64_NS;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, t = threadIdx.x;
@@ -740,10 +741,12 @@ __device__ __forceinline__ void sym_item_f64(const Src8d *__restrict__ src, int 
 #pragma unroll
     for (int k = 0; k < TT; ++k)
         o[k] = own_point64(src[(int64_t)I * TILE + k * NT + t]);
-    double aP[TT], aQ[TT];
+    // The row sums over the item's source tiles live in LDS (acc[k][t] and
+    // acc[TT + k][t], private to the thread): in registers they would be
+    // spilled at this occupancy, at every source tile.
 #pragma unroll
     for (int k = 0; k < TT; ++k)
-        aP[k] = aQ[k] = 0.0;
+        acc[k][t] = acc[TT + k][t] = 0.0;
     for (int J = J0; J < J1; ++J) {
         double P[TT], Q[TT];
 #pragma unroll
@@ -771,14 +774,14 @@ __device__ __forceinline__ void sym_item_f64(const Src8d *__restrict__ src, int 
         }
 #pragma unroll
         for (int k = 0; k < TT; ++k) {
-            aP[k] += P[k];
-            aQ[k] += Q[k];
+            acc[k][t] += P[k];
+            acc[TT + k][t] += Q[k];
         }
     }
 #pragma unroll
     for (int k = 0; k < TT; ++k) {
-        rp[k * NT + t] = aP[k];
-        rp[TILE + k * NT + t] = aQ[k];
+        rp[k * NT + t] = acc[k][t];
+        rp[TILE + k * NT + t] = acc[TT + k][t];
     }
 }
 

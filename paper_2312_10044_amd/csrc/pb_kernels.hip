@@ -524,9 +524,10 @@ __global__ __launch_bounds__(SYM64_NT, SYM64_MIN_WAVES) void k_pairs_f64_sym(con
 {
     __shared__ Src8d sh[SYM64_NS];
     __shared__ double colw[SYM64_NT / 64][2 * SYM64_NS];
+    __shared__ double acc[2 * SYM64_TT][SYM64_NT];
     const int4 it = items[blockIdx.x];   // (I, J0, J1, slot)
     sym_item_f64<TRANS>(src, it.x, it.y, it.z, T, Coef<double>(pp),
-                        rowpart + (int64_t)it.w * (2 * TILE), colpart, sh, colw);
+                        rowpart + (int64_t)it.w * (2 * TILE), colpart, sh, colw, acc);
 }
 
 __global__ __launch_bounds__(TPB) void k_matvec_finish(const double *__restrict__ part,
