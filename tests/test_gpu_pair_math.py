@@ -12,7 +12,8 @@ kernel (Sec. 2.2.1, eq. eq_potential).
   reduction's integer conversion saturates.
 * 1/sqrt(y) (the hardware estimate refined once) is within 1 ulp of
   long-double 1/sqrt over the whole accepted range, log-uniform.
-* Arguments outside the documented ranges are rejected and nothing is written.
+* Arguments outside the documented ranges, and sizes above the limit, are
+  rejected and nothing is written.
 """
 import ctypes
 import os
@@ -113,6 +114,11 @@ def test_arguments_outside_the_ranges_are_rejected():
             with pytest.raises(m.PbError) as e:
                 ctx.eval_pair_math(np.array([0.5, xb]), np.array([1.0, yb]))
             assert e.value.status == m.PB_ERR_ARG
+        # one more than the size limit: rejected before anything is copied
+        big = pbs.PB_PAIR_MATH_MAX + 1
+        with pytest.raises(m.PbError) as e:
+            ctx.eval_pair_math(np.zeros(big), np.ones(big))
+        assert e.value.status == m.PB_ERR_ARG
         # the context stays usable
         ex, rq = ctx.eval_pair_math(np.array([0.0, 1.0]), np.array([1.0, 4.0]))
         assert ex[0] == 1.0
